@@ -1,0 +1,188 @@
+"""Seeded synthetic inputs shared by the CPU oracle, the tests and the benchmark.
+
+This module holds no arithmetic of the solver.  It only fixes *what* is solved:
+model Hamiltonians as lists of real Pauli-string terms on a periodic lattice,
+the workload configurations, the seeded parameter draws of the batched sweep
+and the warm-start sets, and seeded random symmetric matrices that imitate
+ADMM iterates for the isolated projection benchmark.  Random numbers that the
+method itself would draw do not exist (the iteration is deterministic).
+
+Term format (used by both sides)
+--------------------------------
+A term is ``(coeff, ((pauli, (ox, oy)), ...))``: a real coefficient times a
+product of Pauli letters ``"X" | "Y" | "Z"`` placed at site offsets ``(ox, oy)``
+relative to a lattice origin.  The Hamiltonian is the sum of every term
+translated to every lattice site (periodic boundary conditions).
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from typing import Tuple
+
+import numpy as np
+
+BASE_SEED = 210602682
+
+Term = Tuple[float, Tuple[Tuple[str, Tuple[int, int]], ...]]
+
+
+def tfi_terms(h: float, J: float = 1.0, ndim: int = 1) -> list:
+    """Transverse-field Ising model: -h sum X_i - J sum_<ij> Z_i Z_j (Section 2.1, eq. TFI)."""
+    terms = [(-float(h), (("X", (0, 0)),))]
+    terms.append((-float(J), (("Z", (0, 0)), ("Z", (1, 0)))))
+    if ndim == 2:
+        terms.append((-float(J), (("Z", (0, 0)), ("Z", (0, 1)))))
+    return terms
+
+
+def xxz_terms(Jz: float, ndim: int = 1) -> list:
+    """XXZ chain sum_<ij> (X_i X_j + Y_i Y_j + Jz Z_i Z_j); Jz = 1 is the AFH model (eq. AFH)."""
+    bonds = [(1, 0)] + ([(0, 1)] if ndim == 2 else [])
+    terms = []
+    for b in bonds:
+        terms.append((1.0, (("X", (0, 0)), ("X", b))))
+        terms.append((1.0, (("Y", (0, 0)), ("Y", b))))
+        terms.append((float(Jz), (("Z", (0, 0)), ("Z", b))))
+    return terms
+
+
+def afh_terms(ndim: int = 1) -> list:
+    return xxz_terms(1.0, ndim)
+
+
+@dataclass(frozen=True)
+class Workload:
+    """One solver instance: model terms on an Nx x Ny torus tiled by Lx x Ly clusters."""
+
+    name: str
+    terms: tuple
+    extent: Tuple[int, int]
+    cluster: Tuple[int, int]
+    opset: str = "complete"  # "complete" | "pauli1"
+    iters: int = 2000
+    mu: float = 10.0
+    nu: float = 10.0
+    eps: float = 2.0
+    meta: dict = field(default_factory=dict, compare=False, hash=False)
+
+    @property
+    def ndim(self) -> int:
+        return 1 if self.extent[1] == 1 else 2
+
+    @property
+    def L(self) -> int:
+        return self.cluster[0] * self.cluster[1]
+
+    @property
+    def M(self) -> int:
+        return (self.extent[0] // self.cluster[0]) * (self.extent[1] // self.cluster[1])
+
+    @property
+    def m(self) -> int:
+        return 2 ** self.L
+
+    @property
+    def n(self) -> int:
+        return self.m * self.m
+
+    @property
+    def n_op(self) -> int:
+        return self.m * self.m if self.opset == "complete" else 3 * self.L
+
+
+def tfi_ring(N: int, L: int, h: float, opset: str = "complete", iters: int = 2000, name=None) -> Workload:
+    return Workload(name or f"tfi_ring_N{N}_L{L}_h{h}_{opset}", tuple(tfi_terms(h, 1.0, 1)),
+                    (N, 1), (L, 1), opset, iters, meta={"model": "tfi", "h": h, "Jz": 0.0})
+
+
+def xxz_ring(N: int, L: int, Jz: float, opset: str = "complete", iters: int = 2000, name=None) -> Workload:
+    return Workload(name or f"xxz_ring_N{N}_L{L}_Jz{Jz}_{opset}", tuple(xxz_terms(Jz, 1)),
+                    (N, 1), (L, 1), opset, iters, meta={"model": "xxz", "h": 0.0, "Jz": Jz})
+
+
+def tfi_torus(Nx: int, Ny: int, Lx: int, Ly: int, h: float, iters: int = 2000, name=None) -> Workload:
+    return Workload(name or f"tfi_torus_{Nx}x{Ny}_{Lx}x{Ly}_h{h}", tuple(tfi_terms(h, 1.0, 2)),
+                    (Nx, Ny), (Lx, Ly), "complete", iters, meta={"model": "tfi", "h": h, "Jz": 0.0})
+
+
+def afh_torus(Nx: int, Ny: int, Lx: int, Ly: int, iters: int = 2000, name=None) -> Workload:
+    return Workload(name or f"afh_torus_{Nx}x{Ny}_{Lx}x{Ly}", tuple(afh_terms(2)),
+                    (Nx, Ny), (Lx, Ly), "complete", iters, meta={"model": "xxz", "h": 0.0, "Jz": 1.0})
+
+
+# ---------------------------------------------------------------------------
+# Workload configurations (the paper's method at the shapes of the five configs)
+# ---------------------------------------------------------------------------
+
+def config_c1() -> list:
+    """Ring N=8, J=1, h=1, 2000 iterations; four cluster choices (L=1 Pauli, L=1, 2, 4 complete)."""
+    return [tfi_ring(8, 1, 1.0, "pauli1", 2000, "C1a"), tfi_ring(8, 1, 1.0, "complete", 2000, "C1b"),
+            tfi_ring(8, 2, 1.0, "complete", 2000, "C1c"), tfi_ring(8, 4, 1.0, "complete", 2000, "C1d")]
+
+
+def config_c2(h: float = 1.0) -> list:
+    """Ring, J=1, h in {0.5, 1, 1.5}, 5000 iterations: N=128 with L=1 Pauli; N=384 with L=3."""
+    return [tfi_ring(128, 1, h, "pauli1", 5000, f"C2a_h{h}"), tfi_ring(384, 3, h, "complete", 5000, f"C2b_h{h}")]
+
+
+def config_c3() -> list:
+    """16x16 torus, J=1, h=3: 2x1 clusters and 2x2 plaquettes."""
+    return [tfi_torus(16, 16, 2, 1, 3.0, 2000, "C3a"), tfi_torus(16, 16, 2, 2, 3.0, 2000, "C3b")]
+
+
+def draw_instance(rng: np.random.Generator) -> dict:
+    """One batched-sweep draw; all five numbers are always drawn so streams stay aligned."""
+    model = int(rng.integers(2))
+    N = int(rng.integers(32, 513))
+    L = int(rng.integers(2, 5))
+    h = float(rng.uniform(0.2, 2.0))
+    Jz = float(rng.uniform(0.0, 2.0))
+    return {"model": "tfi" if model == 0 else "xxz", "N": N, "L": L, "h": h, "Jz": Jz}
+
+
+def instance_workload(d: dict, iters: int = 5000, name: str = "") -> Workload:
+    M = d["N"] // d["L"]
+    N_eff = M * d["L"]
+    if d["model"] == "tfi":
+        terms = tfi_terms(d["h"], 1.0, 1)
+    else:
+        terms = xxz_terms(d["Jz"], 1)
+    return Workload(name or f"{d['model']}_N{N_eff}_L{d['L']}", tuple(terms), (N_eff, 1), (d["L"], 1),
+                    "complete", iters, meta=dict(d, N_eff=N_eff))
+
+
+def c4_instances(count: int = 64) -> list:
+    return [draw_instance(np.random.default_rng([BASE_SEED, 4, i])) for i in range(count)]
+
+
+def c5_train_instances(count: int = 4096) -> list:
+    return [draw_instance(np.random.default_rng([BASE_SEED, 5, 0, i])) for i in range(count)]
+
+
+def c5_heldout_instances(count: int = 512) -> list:
+    return [draw_instance(np.random.default_rng([BASE_SEED, 5, 1, j])) for j in range(count)]
+
+
+# ---------------------------------------------------------------------------
+# Random symmetric inputs shaped like ADMM iterates (isolated projection benchmark)
+# ---------------------------------------------------------------------------
+
+def admm_like_batch(n: int, batch: int, mu: float = 10.0, tag: int = 0) -> np.ndarray:
+    """(batch, n, n) float64: W/Tr W - S/mu with W = G G^T, S = (Z + Z^T)/(2 sqrt n).
+
+    Roughly half of the eigenvalues come out negative, like rho - Lambda/mu.
+    """
+    rng = np.random.default_rng([BASE_SEED, tag, n, batch])
+    G = rng.standard_normal((batch, n, n))
+    W = G @ np.swapaxes(G, 1, 2)
+    tr = np.trace(W, axis1=1, axis2=2)[:, None, None]
+    Z = rng.standard_normal((batch, n, n))
+    S = (Z + np.swapaxes(Z, 1, 2)) / (2.0 * np.sqrt(n))
+    return W / tr - S / mu
+
+
+def hermitian_batch(n: int, batch: int, tag: int = 1) -> np.ndarray:
+    """(batch, n, n) complex128 Hermitian matrices with a spread of signed eigenvalues."""
+    rng = np.random.default_rng([BASE_SEED, tag, n, batch, 7])
+    A = rng.standard_normal((batch, n, n)) + 1j * rng.standard_normal((batch, n, n))
+    return (A + np.conj(np.swapaxes(A, 1, 2))) / (2.0 * np.sqrt(n))
