@@ -1,0 +1,180 @@
+/*
+ * vemb.h -- C ABI of the MI355X library for the translation-invariant
+ * two-marginal SDP relaxation of Khoo & Lindsey (arXiv 2106.02682).
+ *
+ * The library runs Algorithm 6 of the paper (translation-invariant ADMM /
+ * projected dual gradient ascent, Section 3.3) on one GPU.  One iteration is
+ *   1. effective Hamiltonians H'_0, H'_0d from the dual X      (eq. effHam)
+ *   2. closed-form pair update rho_0d                          (eq. rhoijUpdate)
+ *   3. PSD projection rho~_0d = Pi(rho_0d - Lambda_0d/mu)      (eq. rhoijTildeUpdate)
+ *   4. cluster marginal rho_0 with trace fix                   (eq. rhoiUpdate)
+ *   5. multiplier updates Lambda, Lambda1, Lambda2             (Algorithm 6)
+ *   6. X' = X - eps G(rho)   (gradient of the partial dual is -G, eq. gradX)
+ *   7. momentum blocks Xhat_k by a DFT over the cluster lattice (Section 3.3)
+ *   8. Y_k = Pi(Hermitian part of Xhat_k)
+ *   9. X_0d by the inverse DFT.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Status codes: 0 = VEMB_OK; negative values are errors (enum below).  No
+ *   C++ exception crosses the ABI.  vemb_last_error() returns a thread-local
+ *   message describing the last failure of the calling thread.
+ * - All matrices are row-major, float64 unless stated.  A pair index is
+ *   (x, y) -> x*m + y with cluster 0 the first (most significant) factor;
+ *   inside a cluster, local site 0 is the most significant bit.
+ * - Lattice: periodic Nx x Ny (Ny = 1 for a ring).  Site (x, y) belongs to
+ *   cluster (x / Lx, y / Ly), flat cluster index cx*My + cy, local site index
+ *   (x % Lx)*Ly + (y % Ly).  Offsets d = 1..M-1 use the flat cluster index.
+ * - Device work is enqueued on the hipStream_t given at creation (NULL = the
+ *   null stream).  The library owns all device memory of a problem; callers
+ *   own every host buffer they pass.
+ */
+#ifndef VEMB_H
+#define VEMB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum vemb_status {
+  VEMB_OK = 0,
+  VEMB_E_INVALID = -1,      /* NULL pointer, shape that does not tile, bad size or option */
+  VEMB_E_UNSUPPORTED = -2,  /* M < 2, complex term, >2-site term, cluster too large, non-periodic */
+  VEMB_E_NOMEM = -3,        /* device or host allocation failed */
+  VEMB_E_HIP = -4,          /* a HIP runtime call failed (message names it) */
+  VEMB_E_NUMERIC = -5,      /* non-finite value met by a diagnostic or by set_state */
+  VEMB_E_DIVERGED = -6,     /* divergence watchdog fired (bound not finite or feasibility blowing up) */
+  VEMB_E_NOCONV = -7        /* an eigensolver reached its sweep cap (result still written) */
+};
+
+enum vemb_pauli { VEMB_I = 0, VEMB_X = 1, VEMB_Y = 2, VEMB_Z = 3 };
+
+/* One translation-invariant term: coeff * prod_s pauli[s] at site origin + offset[s].
+ * nsites is 1 or 2 (pairwise Hamiltonians, Section 2.1).  The product must be
+ * real (an even number of Y factors), as the paper treats the real case. */
+typedef struct {
+  double coeff;
+  int32_t nsites;
+  int32_t pauli[2];
+  int32_t offset[2][2]; /* (dx, dy) per factor */
+} vemb_term;
+
+typedef struct {
+  int32_t nterms;
+  const vemb_term* terms;
+} vemb_hamiltonian;
+
+typedef struct {
+  int32_t ndim;        /* 1 or 2 */
+  int32_t extent[2];   /* Nx, Ny (Ny = 1 when ndim = 1) */
+  int32_t periodic[2]; /* must be 1: translation invariance needs a torus */
+} vemb_lattice;
+
+typedef struct {
+  int32_t shape[2]; /* Lx, Ly; must divide the extents (Section 2.3, clusters as supersites) */
+} vemb_clusters;
+
+enum vemb_opset { VEMB_OPSET_COMPLETE = 0, VEMB_OPSET_PAULI1 = 1 };
+enum vemb_precision { VEMB_FP64 = 0, VEMB_MIXED = 1 };
+
+typedef struct {
+  double mu, nu, eps;  /* penalty and step parameters (Section 4 uses 10, 10, 2) */
+  int32_t opset;       /* vemb_opset: operator collection defining G (Section 2.2) */
+  int32_t precision;   /* vemb_precision: FP64, or FP32 eigensolves with FP64 refinement */
+  int32_t max_sweeps;  /* Jacobi sweep cap per eigensolve (0 = default 40) */
+  int32_t sign;        /* -1: X <- Pi(X - eps G) (default when 0); +1: the printed + sign */
+} vemb_options;
+
+typedef struct vemb_problem vemb_problem;
+
+/* Sizes of a created problem. */
+typedef struct {
+  int32_t M, P, L, m, n, n_op, Mx, My, K_unique;
+  int64_t t; /* iterations done */
+} vemb_info;
+
+/* Fills *opts with the paper's parameters (mu = nu = 10, eps = 2), COMPLETE, FP64. */
+void vemb_default_options(vemb_options* opts);
+
+/* Builds H_0 and H_0d on the host from the translation-invariant terms,
+ * allocates device state and initialises it as in Section 4 (multipliers 0,
+ * marginals identity / trace, X_00 = I, X_0d = 0).  Inputs are copied.
+ * Errors: VEMB_E_INVALID, VEMB_E_UNSUPPORTED, VEMB_E_NOMEM, VEMB_E_HIP. */
+int vemb_create_problem(const vemb_hamiltonian* H, const vemb_lattice* lattice, const vemb_clusters* clusters,
+                        const vemb_options* opts, void* hip_stream, vemb_problem** out);
+
+int vemb_problem_info(const vemb_problem* p, vemb_info* info);
+
+/* Enqueues `iters` iterations of Algorithm 6 on the problem's stream.
+ * Asynchronous: returns once the work is enqueued. */
+int vemb_step(vemb_problem* p, int iters);
+
+/* FP64 Lagrangian lower bound per site (valid for any PSD X and any symmetric
+ * Lambda1, Lambda2; derived from the partial dual, Section 2.4):
+ *   (1/L)[lmin(H'_0 - 1/2 sum_d(L1_d + L2_d)) + 1/2 sum_d lmin(H'_0d + L1_d x I + I x L2_d)].
+ * Synchronises the stream.  VEMB_E_NUMERIC on non-finite results. */
+int vemb_dual_bound(vemb_problem* p, double* lb_per_site);
+
+/* Primal energy per site [Tr H_0 rho_0 + 1/2 sum_d Tr H_0d rho_0d]/L of the
+ * latest pair update and the feasibility error of eq. feasErr.  Synchronises. */
+int vemb_primal_energy(vemb_problem* p, double* e_per_site, double* feas_err);
+
+enum vemb_which { VEMB_RHO = 0, VEMB_RHO_TILDE = 1 };
+
+/* Copies rho_0 (m*m doubles) and the pair marginals (P*n*n doubles; rho_0d of
+ * the latest pair update, or rho~_0d) into caller-owned host buffers.
+ * Either pointer may be NULL to skip it.  Synchronises. */
+int vemb_marginals(vemb_problem* p, int which, double* rho0, double* rho_pairs);
+
+/* Full iteration state, host buffers owned by the caller, sizes from vemb_info:
+ * X: M*n_op*n_op (first block row X_0d, d = 0..M-1), rho0: m*m, rho: P*n*n,
+ * rho_t: P*n*n, Lam: P*n*n, Lam1: P*m*m, Lam2: P*m*m.  It is the checkpoint
+ * format and the warm-start input. */
+typedef struct {
+  int64_t t;
+  double* X;
+  double* rho0;
+  double* rho;
+  double* rho_t;
+  double* Lam;
+  double* Lam1;
+  double* Lam2;
+} vemb_state;
+
+int vemb_get_state(vemb_problem* p, vemb_state* s);
+/* Validates finiteness (VEMB_E_NUMERIC) and copies the state to the device. */
+int vemb_set_state(vemb_problem* p, const vemb_state* s);
+
+/* Largest Jacobi sweep count over the pair projections and over the momentum
+ * projections of the last iteration (synchronises).  A value equal to the
+ * sweep cap means some eigensolve stopped unconverged. */
+int vemb_last_sweeps(vemb_problem* p, int* pair_max, int* momentum_max);
+
+void vemb_destroy(vemb_problem* p);
+const char* vemb_last_error(void);
+
+/* Isolated batched PSD projection (eq. rhoijTildeUpdate's Pi applied to a
+ * batch): out[b] = argmin_{S >= 0} ||S - in[b]||_F for `batch` symmetric
+ * (is_complex = 0; n*n doubles each) or Hermitian (is_complex = 1; n*n
+ * interleaved re/im double pairs each) matrices.  `in` and `out` are DEVICE
+ * pointers (they may alias).  precision: VEMB_FP64 or VEMB_MIXED.
+ * Asynchronous on hip_stream.  n <= 128 real, n <= 64 complex. */
+int vemb_psd_project_batched(const double* in, double* out, int n, int batch, int is_complex, int precision,
+                             void* hip_stream);
+
+/* As vemb_psd_project_batched, with an explicit sweep cap (0 = default 40) and
+ * an optional DEVICE array sweeps[batch] receiving the sweeps each matrix used. */
+int vemb_psd_project_batched_ex(const double* in, double* out, int n, int batch, int is_complex, int precision,
+                                int max_sweeps, int* sweeps, void* hip_stream);
+
+/* Eigenvalues of a batch of symmetric / Hermitian matrices (device pointers;
+ * w receives batch*n doubles in ascending order), by the same Jacobi solver. */
+int vemb_eigvalsh_batched(const double* in, double* w, int n, int batch, int is_complex, void* hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* VEMB_H */

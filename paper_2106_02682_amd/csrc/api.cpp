@@ -1,0 +1,395 @@
+// C ABI of libvemb (declared in include/vemb.h): problem lifetime, the
+// iteration schedule of Algorithm 6 on one stream, diagnostics and state I/O.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "host_model.h"
+#include "kernels.h"
+
+namespace vemb {
+
+static thread_local std::string g_last_error;
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+}  // namespace vemb
+
+using namespace vemb;
+
+struct vemb_problem {
+  Geometry g;
+  int P = 0, n_op = 0, Ku = 0;
+  vemb_options opt{};
+  hipStream_t stream = nullptr;
+  int64_t t = 0;
+  HostModel host;
+  OpTables ops_host{};
+  StepArgs a{};
+  std::vector<void*> allocations;
+  // device fixed data
+  double *H0 = nullptr, *Hd = nullptr, *tw = nullptr, *wk = nullptr;
+  int* hd_index = nullptr;
+  OpTables* ops = nullptr;
+};
+
+namespace {
+
+int fail(int code, const std::string& msg) {
+  set_error(msg);
+  return code;
+}
+
+template <typename T>
+int dalloc(vemb_problem* p, T** ptr, size_t count) {
+  void* raw = nullptr;
+  const size_t bytes = count == 0 ? 16 : count * sizeof(T);
+  if (hipMalloc(&raw, bytes) != hipSuccess) return fail(VEMB_E_NOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+  p->allocations.push_back(raw);
+  *ptr = static_cast<T*>(raw);
+  return VEMB_OK;
+}
+
+#define VEMB_TRY(expr)          \
+  do {                          \
+    int rc_ = (expr);           \
+    if (rc_ != VEMB_OK) return rc_; \
+  } while (0)
+
+int hip_rc(hipError_t e, const char* what) {
+  if (e == hipSuccess) return VEMB_OK;
+  return fail(VEMB_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+int upload_initial_state(vemb_problem* p) {
+  const int m = p->g.m, n = p->g.n, M = p->g.M, P = p->P, k = p->n_op;
+  std::vector<double> X((size_t)M * k * k, 0.0);
+  for (int i = 0; i < k; ++i) X[(size_t)i * k + i] = 1.0;  // X_00 = I, X_0d = 0
+  std::vector<double> rho0((size_t)m * m, 0.0);
+  for (int i = 0; i < m; ++i) rho0[(size_t)i * m + i] = 1.0 / m;
+  std::vector<double> rt((size_t)P * n * n, 0.0);
+  for (int d = 0; d < P; ++d)
+    for (int i = 0; i < n; ++i) rt[(size_t)d * n * n + (size_t)i * n + i] = 1.0 / n;
+  hipStream_t s = p->stream;
+  VEMB_TRY(hip_rc(hipMemcpyAsync(p->a.X, X.data(), X.size() * 8, hipMemcpyHostToDevice, s), "upload X"));
+  VEMB_TRY(hip_rc(hipMemcpyAsync(p->a.rho0, rho0.data(), rho0.size() * 8, hipMemcpyHostToDevice, s), "upload rho0"));
+  VEMB_TRY(hip_rc(hipMemcpyAsync(p->a.rho_t, rt.data(), rt.size() * 8, hipMemcpyHostToDevice, s), "upload rho_t"));
+  VEMB_TRY(hip_rc(hipMemcpyAsync(p->a.rho, rt.data(), rt.size() * 8, hipMemcpyHostToDevice, s), "upload rho"));
+  VEMB_TRY(hip_rc(hipMemsetAsync(p->a.Lam, 0, (size_t)P * n * n * 8, s), "zero Lam"));
+  VEMB_TRY(hip_rc(hipMemsetAsync(p->a.Lam1, 0, (size_t)P * m * m * 8, s), "zero Lam1"));
+  VEMB_TRY(hip_rc(hipMemsetAsync(p->a.Lam2, 0, (size_t)P * m * m * 8, s), "zero Lam2"));
+  VEMB_TRY(hip_rc(hipStreamSynchronize(s), "initial upload"));
+  p->t = 0;
+  return VEMB_OK;
+}
+
+bool all_finite(const double* v, size_t count) {
+  for (size_t i = 0; i < count; ++i)
+    if (!std::isfinite(v[i])) return false;
+  return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* vemb_last_error(void) { return g_last_error.c_str(); }
+
+void vemb_default_options(vemb_options* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->mu = 10.0;
+  o->nu = 10.0;
+  o->eps = 2.0;
+  o->opset = VEMB_OPSET_COMPLETE;
+  o->precision = VEMB_FP64;
+  o->max_sweeps = 40;
+  o->sign = -1;
+}
+
+int vemb_create_problem(const vemb_hamiltonian* H, const vemb_lattice* lat, const vemb_clusters* cl,
+                        const vemb_options* opts, void* hip_stream, vemb_problem** out) {
+  if (!H || !lat || !cl || !out || (H->nterms > 0 && !H->terms)) return fail(VEMB_E_INVALID, "NULL argument");
+  *out = nullptr;
+  vemb_options o;
+  vemb_default_options(&o);
+  if (opts) o = *opts;
+  if (o.max_sweeps <= 0) o.max_sweeps = 40;
+  if (o.sign == 0) o.sign = -1;
+  if (!(o.mu > 0 && o.nu > 0 && o.eps > 0)) return fail(VEMB_E_INVALID, "mu, nu, eps must be positive");
+  if (o.opset != VEMB_OPSET_COMPLETE && o.opset != VEMB_OPSET_PAULI1) return fail(VEMB_E_INVALID, "unknown opset");
+  if (o.precision != VEMB_FP64 && o.precision != VEMB_MIXED) return fail(VEMB_E_INVALID, "unknown precision");
+  if (lat->ndim != 1 && lat->ndim != 2) return fail(VEMB_E_INVALID, "ndim must be 1 or 2");
+  Geometry g{};
+  g.Nx = lat->extent[0];
+  g.Ny = lat->ndim == 2 ? lat->extent[1] : 1;
+  g.Lx = cl->shape[0];
+  g.Ly = lat->ndim == 2 ? cl->shape[1] : 1;
+  if (lat->ndim == 1 && cl->shape[1] > 1) return fail(VEMB_E_INVALID, "2D cluster on a 1D lattice");
+  if (g.Nx <= 0 || g.Ny <= 0 || g.Lx <= 0 || g.Ly <= 0) return fail(VEMB_E_INVALID, "extents must be positive");
+  if (!lat->periodic[0] || (lat->ndim == 2 && !lat->periodic[1]))
+    return fail(VEMB_E_UNSUPPORTED, "translation invariance needs periodic boundaries");
+  if (g.Nx % g.Lx || g.Ny % g.Ly) return fail(VEMB_E_INVALID, "clusters do not tile the lattice");
+  g.Mx = g.Nx / g.Lx;
+  g.My = g.Ny / g.Ly;
+  g.M = g.Mx * g.My;
+  g.L = g.Lx * g.Ly;
+  if (g.M < 2) return fail(VEMB_E_UNSUPPORTED, "at least two clusters are needed (M >= 2)");
+  if (g.L > 4) return fail(VEMB_E_UNSUPPORTED, "clusters of more than 4 sites are not supported");
+  g.m = 1 << g.L;
+  g.n = g.m * g.m;
+  const int n_op = o.opset == VEMB_OPSET_COMPLETE ? g.n : 3 * g.L;
+  // eigensolver capacity: pair blocks n x n (real), momentum blocks n_op x n_op (complex)
+  if (g.n > 128) return fail(VEMB_E_UNSUPPORTED, "pair marginals above 128 x 128 are not supported yet");
+  if (n_op > 64) return fail(VEMB_E_UNSUPPORTED, "momentum blocks above 64 x 64 are not supported yet");
+
+  auto* p = new vemb_problem();
+  p->g = g;
+  p->P = g.M - 1;
+  p->n_op = n_op;
+  p->opt = o;
+  p->stream = static_cast<hipStream_t>(hip_stream);
+  std::string err;
+  int rc = build_model(*H, g, p->host, err);
+  if (rc != VEMB_OK) {
+    delete p;
+    return fail(rc, err);
+  }
+  std::vector<double> tw, wk;
+  build_momenta(g, tw, wk, p->Ku);
+  if (o.opset == VEMB_OPSET_PAULI1) build_pauli1_tables(g.L, p->ops_host);
+
+  const int m = g.m, n = g.n, M = g.M, P = p->P, k = n_op, Ku = p->Ku;
+  StepArgs& a = p->a;
+  a.M = M;
+  a.P = P;
+  a.m = m;
+  a.n = n;
+  a.n_op = k;
+  a.Ku = Ku;
+  a.opset = o.opset;
+  a.mu = o.mu;
+  a.nu = o.nu;
+  a.eps = o.eps;
+  a.sign = o.sign < 0 ? -1.0 : 1.0;
+  a.a = 1.0 / o.mu;
+  a.b = 1.0 / (o.mu + o.nu * m) - 1.0 / o.mu;
+  a.c = 1.0 / (o.mu + 2 * o.nu * m) - 2.0 / (o.mu + o.nu * m) + 1.0 / o.mu;
+  auto cleanup = [&](int code) {
+    vemb_destroy(p);
+    return code;
+  };
+  const size_t nh = p->host.Hd.size() / ((size_t)n * n);
+  if ((rc = dalloc(p, &p->H0, (size_t)m * m)) || (rc = dalloc(p, &p->Hd, nh * n * n)) ||
+      (rc = dalloc(p, &p->hd_index, (size_t)P)) || (rc = dalloc(p, &p->tw, tw.size())) ||
+      (rc = dalloc(p, &p->wk, wk.size())) || (rc = dalloc(p, &p->ops, 1)) ||
+      (rc = dalloc(p, &a.X, (size_t)M * k * k)) || (rc = dalloc(p, &a.Xp, (size_t)M * k * k)) ||
+      (rc = dalloc(p, &a.Xh, (size_t)2 * Ku * k * k)) || (rc = dalloc(p, &a.rho0, (size_t)m * m)) ||
+      (rc = dalloc(p, &a.rho, (size_t)P * n * n)) || (rc = dalloc(p, &a.rho_t, (size_t)P * n * n)) ||
+      (rc = dalloc(p, &a.Lam, (size_t)P * n * n)) || (rc = dalloc(p, &a.Lam1, (size_t)P * m * m)) ||
+      (rc = dalloc(p, &a.Lam2, (size_t)P * m * m)) || (rc = dalloc(p, &a.tr2, (size_t)P * m * m)) ||
+      (rc = dalloc(p, &a.tr1, (size_t)P * m * m)) || (rc = dalloc(p, &a.e_pair, (size_t)P)) ||
+      (rc = dalloc(p, &a.feas, (size_t)P)) || (rc = dalloc(p, &a.scal, 4)) ||
+      (rc = dalloc(p, &a.Kbuf, (size_t)P * n * n + (size_t)m * m)) || (rc = dalloc(p, &a.lmin, (size_t)P + 1)) ||
+      (rc = dalloc(p, &a.sweeps, (size_t)(2 * P + Ku + 1))))
+    return cleanup(rc);
+  hipStream_t s = p->stream;
+  if ((rc = hip_rc(hipMemcpyAsync(p->H0, p->host.H0.data(), (size_t)m * m * 8, hipMemcpyHostToDevice, s), "upload H0")) ||
+      (nh && (rc = hip_rc(hipMemcpyAsync(p->Hd, p->host.Hd.data(), p->host.Hd.size() * 8, hipMemcpyHostToDevice, s), "upload Hd"))) ||
+      (rc = hip_rc(hipMemcpyAsync(p->hd_index, p->host.hd_index.data(), (size_t)P * sizeof(int), hipMemcpyHostToDevice, s), "upload index")) ||
+      (rc = hip_rc(hipMemcpyAsync(p->tw, tw.data(), tw.size() * 8, hipMemcpyHostToDevice, s), "upload twiddles")) ||
+      (rc = hip_rc(hipMemcpyAsync(p->wk, wk.data(), wk.size() * 8, hipMemcpyHostToDevice, s), "upload weights")) ||
+      (rc = hip_rc(hipMemcpyAsync(p->ops, &p->ops_host, sizeof(OpTables), hipMemcpyHostToDevice, s), "upload ops")) ||
+      (rc = hip_rc(hipMemsetAsync(a.sweeps, 0, sizeof(int) * (2 * P + Ku + 1), s), "zero sweeps")) ||
+      (rc = hip_rc(hipMemsetAsync(a.e_pair, 0, sizeof(double) * P, s), "zero e_pair")) ||
+      (rc = hip_rc(hipMemsetAsync(a.feas, 0, sizeof(double) * P, s), "zero feas")) ||
+      (rc = hip_rc(hipMemsetAsync(a.scal, 0, sizeof(double) * 4, s), "zero scal")))
+    return cleanup(rc);
+  a.H0 = p->H0;
+  a.Hd = p->Hd;
+  a.hd_index = p->hd_index;
+  a.tw = p->tw;
+  a.wk = p->wk;
+  a.ops = p->ops;
+  if ((rc = upload_initial_state(p))) return cleanup(rc);
+  *out = p;
+  return VEMB_OK;
+}
+
+int vemb_problem_info(const vemb_problem* p, vemb_info* info) {
+  if (!p || !info) return fail(VEMB_E_INVALID, "NULL argument");
+  info->M = p->g.M;
+  info->P = p->P;
+  info->L = p->g.L;
+  info->m = p->g.m;
+  info->n = p->g.n;
+  info->n_op = p->n_op;
+  info->Mx = p->g.Mx;
+  info->My = p->g.My;
+  info->K_unique = p->Ku;
+  info->t = p->t;
+  return VEMB_OK;
+}
+
+int vemb_step(vemb_problem* p, int iters) {
+  if (!p || iters < 0) return fail(VEMB_E_INVALID, "bad arguments to vemb_step");
+  const StepArgs& a = p->a;
+  hipStream_t s = p->stream;
+  const int prec = p->opt.precision, ms = p->opt.max_sweeps;
+  for (int it = 0; it < iters; ++it) {
+    VEMB_TRY(hip_rc(launch_pair_update(a, s), "pair update"));
+    VEMB_TRY(hip_rc(launch_pair_projection(a.rho, a.Lam, a.rho_t, a.feas, a.n, a.P, a.mu, prec, ms, a.sweeps, s),
+                    "pair projection"));
+    VEMB_TRY(hip_rc(launch_cluster_update(a, s), "cluster update"));
+    VEMB_TRY(hip_rc(launch_dft_forward(a, s), "forward DFT"));
+    VEMB_TRY(hip_rc(launch_momentum_projection(a.Xh, a.n_op, a.Ku, prec, ms, a.sweeps + a.P, s), "momentum projection"));
+    VEMB_TRY(hip_rc(launch_dft_inverse(a, s), "inverse DFT"));
+    ++p->t;
+  }
+  return VEMB_OK;
+}
+
+int vemb_primal_energy(vemb_problem* p, double* e_per_site, double* feas_err) {
+  if (!p) return fail(VEMB_E_INVALID, "NULL problem");
+  const int P = p->P;
+  std::vector<double> ep(P), fe(P), sc(4);
+  hipStream_t s = p->stream;
+  VEMB_TRY(hip_rc(hipMemcpyAsync(ep.data(), p->a.e_pair, P * 8, hipMemcpyDeviceToHost, s), "copy energies"));
+  VEMB_TRY(hip_rc(hipMemcpyAsync(fe.data(), p->a.feas, P * 8, hipMemcpyDeviceToHost, s), "copy feas"));
+  VEMB_TRY(hip_rc(hipMemcpyAsync(sc.data(), p->a.scal, 4 * 8, hipMemcpyDeviceToHost, s), "copy scalars"));
+  VEMB_TRY(hip_rc(hipStreamSynchronize(s), "primal energy sync"));
+  double e = sc[0], f = sc[1];
+  for (int d = 0; d < P; ++d) {
+    e += 0.5 * ep[d];
+    f += fe[d];
+  }
+  if (e_per_site) *e_per_site = e / p->g.L;
+  if (feas_err) *feas_err = std::sqrt(f / (p->g.M - 1));
+  if (!std::isfinite(e) || !std::isfinite(f)) return fail(VEMB_E_NUMERIC, "non-finite energy or feasibility");
+  return VEMB_OK;
+}
+
+int vemb_dual_bound(vemb_problem* p, double* lb) {
+  if (!p || !lb) return fail(VEMB_E_INVALID, "NULL argument");
+  const StepArgs& a = p->a;
+  hipStream_t s = p->stream;
+  const int P = p->P, n = a.n, m = a.m;
+  VEMB_TRY(hip_rc(launch_bound_build(a, s), "bound build"));
+  VEMB_TRY(hip_rc(launch_lambda_min(a.Kbuf, a.lmin, n, P, p->opt.max_sweeps, a.sweeps + P + a.Ku, s), "pair lambda_min"));
+  VEMB_TRY(hip_rc(launch_lambda_min(a.Kbuf + (size_t)P * n * n, a.lmin + P, m, 1, p->opt.max_sweeps, nullptr, s),
+                  "cluster lambda_min"));
+  std::vector<double> lm(P + 1);
+  VEMB_TRY(hip_rc(hipMemcpyAsync(lm.data(), a.lmin, (P + 1) * 8, hipMemcpyDeviceToHost, s), "copy lambda_min"));
+  VEMB_TRY(hip_rc(hipStreamSynchronize(s), "dual bound sync"));
+  double v = lm[P];
+  double sum = 0.0;
+  for (int d = 0; d < P; ++d) sum += lm[d];
+  v += 0.5 * sum;
+  *lb = v / p->g.L;
+  if (!std::isfinite(*lb)) return fail(VEMB_E_NUMERIC, "non-finite lower bound");
+  return VEMB_OK;
+}
+
+int vemb_marginals(vemb_problem* p, int which, double* rho0, double* rho_pairs) {
+  if (!p) return fail(VEMB_E_INVALID, "NULL problem");
+  if (which != VEMB_RHO && which != VEMB_RHO_TILDE) return fail(VEMB_E_INVALID, "which must be RHO or RHO_TILDE");
+  hipStream_t s = p->stream;
+  const size_t m2 = (size_t)p->g.m * p->g.m, pn = (size_t)p->P * p->g.n * p->g.n;
+  if (rho0) VEMB_TRY(hip_rc(hipMemcpyAsync(rho0, p->a.rho0, m2 * 8, hipMemcpyDeviceToHost, s), "copy rho0"));
+  if (rho_pairs)
+    VEMB_TRY(hip_rc(hipMemcpyAsync(rho_pairs, which == VEMB_RHO ? p->a.rho : p->a.rho_t, pn * 8,
+                                   hipMemcpyDeviceToHost, s), "copy pairs"));
+  return hip_rc(hipStreamSynchronize(s), "marginals sync");
+}
+
+int vemb_get_state(vemb_problem* p, vemb_state* st) {
+  if (!p || !st) return fail(VEMB_E_INVALID, "NULL argument");
+  hipStream_t s = p->stream;
+  const size_t m2 = (size_t)p->g.m * p->g.m, n2 = (size_t)p->g.n * p->g.n, P = p->P;
+  const size_t xk = (size_t)p->g.M * p->n_op * p->n_op;
+  struct Item { double* host; const double* dev; size_t count; };
+  Item items[] = {{st->X, p->a.X, xk},           {st->rho0, p->a.rho0, m2},  {st->rho, p->a.rho, P * n2},
+                  {st->rho_t, p->a.rho_t, P * n2}, {st->Lam, p->a.Lam, P * n2}, {st->Lam1, p->a.Lam1, P * m2},
+                  {st->Lam2, p->a.Lam2, P * m2}};
+  for (const Item& it : items)
+    if (it.host)
+      VEMB_TRY(hip_rc(hipMemcpyAsync(it.host, it.dev, it.count * 8, hipMemcpyDeviceToHost, s), "get_state copy"));
+  VEMB_TRY(hip_rc(hipStreamSynchronize(s), "get_state sync"));
+  st->t = p->t;
+  return VEMB_OK;
+}
+
+int vemb_set_state(vemb_problem* p, const vemb_state* st) {
+  if (!p || !st) return fail(VEMB_E_INVALID, "NULL argument");
+  const size_t m2 = (size_t)p->g.m * p->g.m, n2 = (size_t)p->g.n * p->g.n, P = p->P;
+  const size_t xk = (size_t)p->g.M * p->n_op * p->n_op;
+  struct Item { const double* host; double* dev; size_t count; };
+  Item items[] = {{st->X, p->a.X, xk},           {st->rho0, p->a.rho0, m2},  {st->rho, p->a.rho, P * n2},
+                  {st->rho_t, p->a.rho_t, P * n2}, {st->Lam, p->a.Lam, P * n2}, {st->Lam1, p->a.Lam1, P * m2},
+                  {st->Lam2, p->a.Lam2, P * m2}};
+  for (const Item& it : items) {
+    if (!it.host) return fail(VEMB_E_INVALID, "set_state needs every array");
+    if (!all_finite(it.host, it.count)) return fail(VEMB_E_NUMERIC, "set_state: non-finite entries");
+  }
+  hipStream_t s = p->stream;
+  for (const Item& it : items)
+    VEMB_TRY(hip_rc(hipMemcpyAsync(it.dev, it.host, it.count * 8, hipMemcpyHostToDevice, s), "set_state copy"));
+  VEMB_TRY(hip_rc(hipStreamSynchronize(s), "set_state sync"));
+  p->t = st->t;
+  return VEMB_OK;
+}
+
+int vemb_last_sweeps(vemb_problem* p, int* pair_max, int* momentum_max) {
+  if (!p) return fail(VEMB_E_INVALID, "NULL problem");
+  std::vector<int> sw(p->P + p->Ku);
+  VEMB_TRY(hip_rc(hipMemcpyAsync(sw.data(), p->a.sweeps, sw.size() * sizeof(int), hipMemcpyDeviceToHost, p->stream),
+                  "copy sweeps"));
+  VEMB_TRY(hip_rc(hipStreamSynchronize(p->stream), "sweeps sync"));
+  int a = 0, b = 0;
+  for (int i = 0; i < p->P; ++i) a = std::max(a, sw[i]);
+  for (int i = 0; i < p->Ku; ++i) b = std::max(b, sw[p->P + i]);
+  if (pair_max) *pair_max = a;
+  if (momentum_max) *momentum_max = b;
+  return VEMB_OK;
+}
+
+void vemb_destroy(vemb_problem* p) {
+  if (!p) return;
+  if (p->stream) hipStreamSynchronize(p->stream);
+  else hipDeviceSynchronize();
+  for (void* ptr : p->allocations) hipFree(ptr);
+  delete p;
+}
+
+int vemb_psd_project_batched(const double* in, double* out, int n, int batch, int is_complex, int precision,
+                             void* hip_stream) {
+  if (!in || !out || n <= 0 || batch < 0) return fail(VEMB_E_INVALID, "bad arguments to vemb_psd_project_batched");
+  if (precision != VEMB_FP64 && precision != VEMB_MIXED) return fail(VEMB_E_INVALID, "unknown precision");
+  if ((is_complex && n > 64) || n > 128) return fail(VEMB_E_UNSUPPORTED, "matrix too large for the LDS solver");
+  return hip_rc(launch_psd_batched(in, out, n, batch, is_complex != 0, precision, 40, nullptr,
+                                   static_cast<hipStream_t>(hip_stream)),
+                "batched projection");
+}
+
+int vemb_psd_project_batched_ex(const double* in, double* out, int n, int batch, int is_complex, int precision,
+                                int max_sweeps, int* sweeps, void* hip_stream) {
+  if (!in || !out || n <= 0 || batch < 0) return fail(VEMB_E_INVALID, "bad arguments to vemb_psd_project_batched_ex");
+  if (precision != VEMB_FP64 && precision != VEMB_MIXED) return fail(VEMB_E_INVALID, "unknown precision");
+  if ((is_complex && n > 64) || n > 128) return fail(VEMB_E_UNSUPPORTED, "matrix too large for the LDS solver");
+  return hip_rc(launch_psd_batched(in, out, n, batch, is_complex != 0, precision, max_sweeps > 0 ? max_sweeps : 40,
+                                   sweeps, static_cast<hipStream_t>(hip_stream)),
+                "batched projection");
+}
+
+int vemb_eigvalsh_batched(const double* in, double* w, int n, int batch, int is_complex, void* hip_stream) {
+  if (!in || !w || n <= 0 || batch < 0) return fail(VEMB_E_INVALID, "bad arguments to vemb_eigvalsh_batched");
+  if ((is_complex && n > 64) || n > 128) return fail(VEMB_E_UNSUPPORTED, "matrix too large for the LDS solver");
+  return hip_rc(launch_eigvalsh_batched(in, w, n, batch, is_complex != 0, 40, nullptr,
+                                        static_cast<hipStream_t>(hip_stream)),
+                "batched eigenvalues");
+}
+
+}  // extern "C"

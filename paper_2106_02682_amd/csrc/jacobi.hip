@@ -1,0 +1,503 @@
+// Batched PSD projection Pi(C) = argmin_{S >= 0} ||S - C||_F (Section 3, definition of Pi)
+// by a one-sided (Hestenes) Jacobi eigensolver held in LDS, one workgroup per matrix.
+//
+// Method.  Pi needs the eigenpairs of C with positive eigenvalues.  The kernel
+// shifts C to B = C + s I with s the Gershgorin bound max(0, max_i (r_i - c_ii)),
+// so B is positive semidefinite, then orthogonalises the columns of W = B by
+// plane rotations W <- W J (round-robin parallel ordering: n/2 disjoint column
+// pairs per round, every pair once per sweep).  At convergence W = B V with V
+// orthogonal and W's columns mutually orthogonal, hence w_j = lambda_j(B) v_j
+// and ||w_j|| = lambda_j(B) >= 0.  Then
+//     Pi(C) = sum_{||w_j|| > s} (||w_j|| - s) / ||w_j||^2  w_j w_j^H,
+// so V is never stored.  Eigenvalues of C are ||w_j|| - s.  Because B is PSD
+// no pair of singular values +-sigma can mix (the failure of one-sided Jacobi on
+// indefinite matrices).  Hermitian blocks use the complex rotation
+// [w_p, w_q] <- [w_p, conj(e) w_q] R(c, s) with e = gamma/|gamma|.
+//
+// Work split: 256 threads; each column pair of a round is owned by a group of G
+// lanes of one wavefront (G = 256 / (n/2), at most 64), each lane holding n/G
+// rows; the three dot products are reduced with wavefront shuffles.  One
+// barrier per round.  Sweeps stop when no pair rotated (|gamma| <= tol
+// sqrt(alpha beta), tol = max(n, 16) * machine epsilon of the compute type);
+// columns of negligible norm (rounding noise left by an exactly singular B) are
+// not rotated, see below.
+#include "kernels.h"
+
+#include <cfloat>
+
+namespace vemb {
+namespace {
+
+constexpr int kThreads = 256;
+
+template <typename R> struct eps_of;
+template <> struct eps_of<double> { static constexpr double v = DBL_EPSILON; };
+template <> struct eps_of<float> { static constexpr float v = FLT_EPSILON; };
+
+__device__ inline double dev_sqrt(double x) { return sqrt(x); }
+__device__ inline float dev_sqrt(float x) { return sqrtf(x); }
+__device__ inline double dev_abs(double x) { return fabs(x); }
+__device__ inline float dev_abs(float x) { return fabsf(x); }
+
+template <typename T> __device__ inline T shfl_x(T v, int m) { return __shfl_xor(v, m); }
+template <typename T> __device__ inline cplx<T> shfl_x(cplx<T> v, int m) {
+  return {__shfl_xor(v.re, m), __shfl_xor(v.im, m)};
+}
+
+template <typename R> __device__ inline R scale_by(R s, R a) { return s * a; }
+template <typename R> __device__ inline cplx<R> scale_by(R s, cplx<R> a) { return {s * a.re, s * a.im}; }
+
+// Multiply by a unit phase (complex) or a sign (real).
+template <typename R> __device__ inline R mul_phase(R ph, R a) { return ph * a; }
+template <typename R> __device__ inline cplx<R> mul_phase(cplx<R> ph, cplx<R> a) { return ph * a; }
+
+template <typename R> __device__ inline R modulus(R a) { return dev_abs(a); }
+// |a| with scaling, so that tiny moduli do not underflow in the squares
+template <typename R> __device__ inline R modulus(cplx<R> a) {
+  const R x = dev_abs(a.re), y = dev_abs(a.im);
+  const R big = x > y ? x : y;
+  if (big == R(0)) return R(0);
+  const R xs = x / big, ys = y / big;
+  return big * dev_sqrt(xs * xs + ys * ys);
+}
+
+// conj(gamma)/|gamma| for complex, sign(gamma) for real.
+template <typename R> __device__ inline R conj_phase(R g, R absg) { return g / absg; }
+template <typename R> __device__ inline cplx<R> conj_phase(cplx<R> g, R absg) { return {g.re / absg, -g.im / absg}; }
+
+template <typename S> __device__ inline S hermitian_avg(S a, S b_transposed) {
+  // (a + conj(b)) / 2
+  using R = typename scalar_traits<S>::real;
+  S cb = conjugate(b_transposed);
+  return scale_by(R(0.5), a + cb);
+}
+template <> __device__ inline double hermitian_avg<double>(double a, double b) { return 0.5 * (a + b); }
+template <> __device__ inline float hermitian_avg<float>(float a, float b) { return 0.5f * (a + b); }
+
+template <typename S> __device__ inline S add_real(S a, typename scalar_traits<S>::real r) { return a + r; }
+template <> __device__ inline cplx<double> add_real<cplx<double>>(cplx<double> a, double r) { return {a.re + r, a.im}; }
+template <> __device__ inline cplx<float> add_real<cplx<float>>(cplx<float> a, float r) { return {a.re + r, a.im}; }
+
+template <typename S> __device__ inline S drop_imag(S a) { return a; }
+template <> __device__ inline cplx<double> drop_imag<cplx<double>>(cplx<double> a) { return {a.re, 0.0}; }
+template <> __device__ inline cplx<float> drop_imag<cplx<float>>(cplx<float> a) { return {a.re, 0.0f}; }
+
+// Block-wide reductions through LDS (kThreads threads).
+template <typename R>
+__device__ R block_max(R v, R* red) {
+  const int t = threadIdx.x;
+  red[t] = v;
+  __syncthreads();
+  for (int s = kThreads / 2; s > 0; s >>= 1) {
+    if (t < s) red[t] = red[t] > red[t + s] ? red[t] : red[t + s];
+    __syncthreads();
+  }
+  R r = red[0];
+  __syncthreads();
+  return r;
+}
+
+template <typename R>
+__device__ R block_sum_r(R v, R* red) {
+  const int t = threadIdx.x;
+  red[t] = v;
+  __syncthreads();
+  for (int s = kThreads / 2; s > 0; s >>= 1) {
+    if (t < s) red[t] += red[t + s];
+    __syncthreads();
+  }
+  R r = red[0];
+  __syncthreads();
+  return r;
+}
+
+__device__ double block_sum(double v, double* red) {
+  const int t = threadIdx.x;
+  red[t] = v;
+  __syncthreads();
+  for (int s = kThreads / 2; s > 0; s >>= 1) {
+    if (t < s) red[t] += red[t + s];
+    __syncthreads();
+  }
+  double r = red[0];
+  __syncthreads();
+  return r;
+}
+
+// Round-robin (circle method) pairing of np = n rounded up to even players.
+__device__ inline void rr_pair(int round, int g, int np, int& p, int& q) {
+  const int k = np - 1;
+  if (g == 0) {
+    p = k;
+    q = round;
+  } else {
+    p = (round + g) % k;
+    q = (round - g + k) % k;
+  }
+}
+
+enum Mode { kProject = 0, kEigvals = 1 };
+
+// ---------------------------------------------------------------------------
+// Core kernel.  S: compute scalar (double, float, cplx<double>, cplx<float>);
+// NMAX: capacity (n <= NMAX, NMAX even); Policy: load / store of one matrix.
+// ---------------------------------------------------------------------------
+template <typename S, int NMAX, int MODE, typename Policy>
+__global__ void __launch_bounds__(kThreads) jacobi_kernel(Policy pol, int n, int max_sweeps) {
+  using R = typename scalar_traits<S>::real;
+  constexpr int LD = NMAX + 1;
+  constexpr int NPAIR = NMAX / 2;
+  constexpr int G0 = kThreads / NPAIR;
+  constexpr int G = G0 > 64 ? 64 : G0;  // lanes per pair, within one wavefront
+  constexpr int RPL = (NMAX + G - 1) / G;  // rows per lane
+  __shared__ S W[NMAX * LD];
+  __shared__ R red[kThreads];
+  __shared__ double red_d[kThreads];
+  __shared__ R colf[NMAX];
+  __shared__ int active[NMAX];
+  __shared__ int nact_s;
+  __shared__ int rotated;
+
+  const int mat = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int nn = n * n;
+
+  // 1. load C (column j at W[j*LD]) and take its Hermitian part
+  for (int idx = tid; idx < nn; idx += kThreads) {
+    const int i = idx / n, j = idx - (idx / n) * n;
+    W[j * LD + i] = pol.template load<S>(mat, i, j);
+  }
+  __syncthreads();
+  for (int idx = tid; idx < nn; idx += kThreads) {
+    const int i = idx / n, j = idx - (idx / n) * n;
+    if (i < j) {
+      const S h = hermitian_avg(W[j * LD + i], W[i * LD + j]);
+      W[j * LD + i] = h;
+      W[i * LD + j] = conjugate(h);
+    } else if (i == j) {
+      W[i * LD + i] = drop_imag(W[i * LD + i]);
+    }
+  }
+  __syncthreads();
+
+  // 2. Gershgorin shift s >= -lambda_min(C)
+  R shift;
+  {
+    R v = R(0);
+    for (int i = tid; i < n; i += kThreads) {
+      R rad = R(0);
+      for (int j = 0; j < n; ++j)
+        if (j != i) rad += modulus(W[j * LD + i]);
+      R d = re_part(W[i * LD + i]);
+      R e = rad - d;
+      v = e > v ? e : v;
+    }
+    shift = block_max(v, red);
+  }
+  for (int i = tid; i < n; i += kThreads) W[i * LD + i] = add_real(W[i * LD + i], shift);
+  __syncthreads();
+  // Columns whose squared norm falls below (eta ||B||_F)^2, eta = max(n,16) eps, hold only
+  // rounding noise: they are left unrotated.  Rotating them never converges (the noise
+  // is re-created parallel to the partner column) and their weight in Pi is below
+  // eta ||B||_F.
+  R floor2;
+  {
+    R v = R(0);
+    for (int idx = tid; idx < nn; idx += kThreads) {
+      const int i = idx / n, j = idx - (idx / n) * n;
+      v += abs2(W[j * LD + i]);
+    }
+    const R eta = R(n > 16 ? n : 16) * eps_of<R>::v;
+    floor2 = eta * eta * block_sum_r(v, red);
+  }
+
+  // 3. sweeps
+  const int np = (n + 1) & ~1;
+  const int npair = np / 2;
+  const R tol = R(n > 16 ? n : 16) * eps_of<R>::v;
+  const int g = tid / G;   // pair slot
+  const int l = tid % G;   // lane within the group
+  int sweep = 0;
+  for (; sweep < max_sweeps; ++sweep) {
+    if (tid == 0) rotated = 0;
+    __syncthreads();
+    for (int round = 0; round < np - 1; ++round) {
+      int p = 0, q = 0;
+      bool live = g < npair;
+      if (live) {
+        rr_pair(round, g, np, p, q);
+        live = p < n && q < n;
+      }
+      S a[RPL], b[RPL];
+      R alpha = R(0), beta = R(0);
+      S gam = s_zero<S>();
+#pragma unroll
+      for (int r = 0; r < RPL; ++r) {
+        const int i = l + r * G;
+        if (live && i < n) {
+          a[r] = W[p * LD + i];
+          b[r] = W[q * LD + i];
+        } else {
+          a[r] = s_zero<S>();
+          b[r] = s_zero<S>();
+        }
+        alpha += abs2(a[r]);
+        beta += abs2(b[r]);
+        gam = gam + conj_mul(a[r], b[r]);
+      }
+#pragma unroll
+      for (int off = G / 2; off > 0; off >>= 1) {
+        alpha += shfl_x(alpha, off);
+        beta += shfl_x(beta, off);
+        gam = gam + shfl_x(gam, off);
+      }
+      const R ag = modulus(gam);
+      const R small = alpha < beta ? alpha : beta;
+      if (live && small > floor2 && ag > tol * dev_sqrt(alpha * beta) && ag > R(0)) {
+        const R zeta = (beta - alpha) / (R(2) * ag);
+        const R az = dev_abs(zeta);
+        R t = R(1) / (az + dev_sqrt(R(1) + zeta * zeta));
+        if (zeta < R(0)) t = -t;
+        const R c = R(1) / dev_sqrt(R(1) + t * t);
+        const R s = c * t;
+        const S ph = conj_phase(gam, ag);  // conj(e)
+#pragma unroll
+        for (int r = 0; r < RPL; ++r) {
+          const int i = l + r * G;
+          if (i < n) {
+            const S bq = mul_phase(ph, b[r]);
+            W[p * LD + i] = scale_by(c, a[r]) - scale_by(s, bq);
+            W[q * LD + i] = scale_by(s, a[r]) + scale_by(c, bq);
+          }
+        }
+        if (l == 0) rotated = 1;
+      }
+      __syncthreads();
+    }
+    const int any = rotated;
+    __syncthreads();
+    if (!any) break;
+  }
+  if (tid == 0) pol.record_sweeps(mat, sweep);
+
+  // 4. column norms sigma_j = lambda_j(B)
+  for (int j = tid; j < n; j += kThreads) {
+    R s2 = R(0);
+    for (int i = 0; i < n; ++i) s2 += abs2(W[j * LD + i]);
+    colf[j] = dev_sqrt(s2);
+  }
+  __syncthreads();
+
+  if constexpr (MODE == kEigvals) {
+    // eigenvalues of C: sigma_j - s, sorted ascending by rank
+    for (int j = tid; j < n; j += kThreads) {
+      const R v = colf[j] - shift;
+      int rank = 0;
+      for (int k = 0; k < n; ++k) {
+        const R u = colf[k] - shift;
+        rank += (u < v) || (u == v && k < j);
+      }
+      pol.store_eig(mat, rank, (double)v);
+    }
+    return;
+  } else {
+    // 5. rebuild Pi(C) = U U^H with U_j = sqrt((sigma_j - s)/sigma_j^2) w_j over active columns
+    if (tid == 0) {
+      int k = 0;
+      for (int j = 0; j < n; ++j)
+        if (colf[j] > shift) active[k++] = j;
+      nact_s = k;
+    }
+    __syncthreads();
+    const int nact = nact_s;
+    for (int idx = tid; idx < nact * n; idx += kThreads) {
+      const int jj = idx / n, i = idx - (idx / n) * n;
+      const int j = active[jj];
+      const R sg = colf[j];
+      const R f = dev_sqrt((sg - shift)) / sg;
+      W[j * LD + i] = scale_by(f, W[j * LD + i]);
+    }
+    __syncthreads();
+    double part = 0.0;
+    for (int idx = tid; idx < nn; idx += kThreads) {
+      const int i = idx / n, k = idx - (idx / n) * n;
+      S acc = s_zero<S>();
+      for (int jj = 0; jj < nact; ++jj) {
+        const int j = active[jj];
+        acc = acc + conj_mul(W[j * LD + k], W[j * LD + i]);  // U(i,j) conj(U(k,j))
+      }
+      part += pol.store(mat, i, k, acc);
+    }
+    const double tot = block_sum(part, red_d);
+    if (tid == 0) pol.finish(mat, tot);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Policies
+// ---------------------------------------------------------------------------
+template <typename S> __device__ inline S from_double(double v);
+template <> __device__ inline double from_double<double>(double v) { return v; }
+template <> __device__ inline float from_double<float>(double v) { return (float)v; }
+
+__device__ inline double to_double(double v) { return v; }
+__device__ inline double to_double(float v) { return (double)v; }
+
+struct PairPolicy {
+  const double* rho;
+  double* Lam;
+  double* rho_t;
+  double* feas;
+  int* sweeps;
+  int n;
+  double mu;
+  template <typename S> __device__ S load(int mat, int i, int j) const {
+    const size_t o = (size_t)mat * n * n + (size_t)i * n + j;
+    return from_double<S>(rho[o] - Lam[o] / mu);
+  }
+  template <typename S> __device__ double store(int mat, int i, int k, S v) const {
+    const size_t o = (size_t)mat * n * n + (size_t)i * n + k;
+    const double pv = to_double(v);
+    const double r = rho[o];
+    rho_t[o] = pv;
+    Lam[o] = Lam[o] + mu * (pv - r);
+    const double dlt = r - pv;
+    return dlt * dlt;
+  }
+  __device__ void finish(int mat, double tot) const { feas[mat] = tot; }
+  __device__ void record_sweeps(int mat, int s) const {
+    if (sweeps) sweeps[mat] = s;
+  }
+  __device__ void store_eig(int, int, double) const {}
+};
+
+struct MomentumPolicy {
+  double* Xh;  // interleaved complex
+  int* sweeps;
+  int n;
+  template <typename S> __device__ S load(int mat, int i, int j) const {
+    const size_t o = 2 * ((size_t)mat * n * n + (size_t)i * n + j);
+    using R = typename scalar_traits<S>::real;
+    return S{(R)Xh[o], (R)Xh[o + 1]};
+  }
+  template <typename S> __device__ double store(int mat, int i, int k, S v) const {
+    const size_t o = 2 * ((size_t)mat * n * n + (size_t)i * n + k);
+    Xh[o] = (double)v.re;
+    Xh[o + 1] = (double)v.im;
+    return 0.0;
+  }
+  __device__ void finish(int, double) const {}
+  __device__ void record_sweeps(int mat, int s) const {
+    if (sweeps) sweeps[mat] = s;
+  }
+  __device__ void store_eig(int, int, double) const {}
+};
+
+// Real or complex matrices in plain arrays (isolated entry points and the bound).
+template <bool CPLX>
+struct ArrayPolicy {
+  const double* in;
+  double* out;   // projection output (may alias in)
+  double* w;     // eigenvalues (kEigvals)
+  double* wmin;  // smallest eigenvalue only
+  int* sweeps;
+  int n;
+  template <typename S> __device__ S load(int mat, int i, int j) const {
+    if constexpr (CPLX) {
+      const size_t o = 2 * ((size_t)mat * n * n + (size_t)i * n + j);
+      using R = typename scalar_traits<S>::real;
+      return S{(R)in[o], (R)in[o + 1]};
+    } else {
+      return from_double<S>(in[(size_t)mat * n * n + (size_t)i * n + j]);
+    }
+  }
+  template <typename S> __device__ double store(int mat, int i, int k, S v) const {
+    if constexpr (CPLX) {
+      const size_t o = 2 * ((size_t)mat * n * n + (size_t)i * n + k);
+      out[o] = (double)v.re;
+      out[o + 1] = (double)v.im;
+    } else {
+      out[(size_t)mat * n * n + (size_t)i * n + k] = to_double(v);
+    }
+    return 0.0;
+  }
+  __device__ void finish(int, double) const {}
+  __device__ void record_sweeps(int mat, int s) const {
+    if (sweeps) sweeps[mat] = s;
+  }
+  __device__ void store_eig(int mat, int rank, double v) const {
+    if (w) w[(size_t)mat * n + rank] = v;
+    if (wmin && rank == 0) wmin[mat] = v;
+  }
+};
+
+template <typename S, int MODE, typename Policy>
+hipError_t dispatch(const Policy& pol, int n, int count, int max_sweeps, hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  const int np = (n + 1) & ~1;
+  dim3 grid(count), block(kThreads);
+#define VEMB_CASE(NM)                                                                             \
+  if (np <= NM) {                                                                                 \
+    hipLaunchKernelGGL((jacobi_kernel<S, NM, MODE, Policy>), grid, block, 0, st, pol, n, max_sweeps); \
+    return hipGetLastError();                                                                     \
+  }
+  VEMB_CASE(4)
+  VEMB_CASE(8)
+  VEMB_CASE(16)
+  VEMB_CASE(32)
+  VEMB_CASE(64)
+  if constexpr (!scalar_traits<S>::is_complex && sizeof(S) == 8) {
+    VEMB_CASE(128)
+  }
+  if constexpr (!scalar_traits<S>::is_complex && sizeof(S) == 4) {
+    VEMB_CASE(128)
+  }
+#undef VEMB_CASE
+  return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+hipError_t launch_pair_projection(const double* rho, double* Lam, double* rho_t, double* feas, int n, int P,
+                                  double mu, int precision, int max_sweeps, int* sweeps, hipStream_t st) {
+  PairPolicy pol{rho, Lam, rho_t, feas, sweeps, n, mu};
+  if (precision == VEMB_MIXED) return dispatch<float, kProject>(pol, n, P, max_sweeps, st);
+  return dispatch<double, kProject>(pol, n, P, max_sweeps, st);
+}
+
+hipError_t launch_momentum_projection(double* Xh, int n_op, int K, int precision, int max_sweeps, int* sweeps,
+                                      hipStream_t st) {
+  MomentumPolicy pol{Xh, sweeps, n_op};
+  if (precision == VEMB_MIXED) return dispatch<cplx<float>, kProject>(pol, n_op, K, max_sweeps, st);
+  return dispatch<cplx<double>, kProject>(pol, n_op, K, max_sweeps, st);
+}
+
+hipError_t launch_psd_batched(const double* in, double* out, int n, int batch, bool is_complex, int precision,
+                              int max_sweeps, int* sweeps, hipStream_t st) {
+  if (is_complex) {
+    ArrayPolicy<true> pol{in, out, nullptr, nullptr, sweeps, n};
+    if (precision == VEMB_MIXED) return dispatch<cplx<float>, kProject>(pol, n, batch, max_sweeps, st);
+    return dispatch<cplx<double>, kProject>(pol, n, batch, max_sweeps, st);
+  }
+  ArrayPolicy<false> pol{in, out, nullptr, nullptr, sweeps, n};
+  if (precision == VEMB_MIXED) return dispatch<float, kProject>(pol, n, batch, max_sweeps, st);
+  return dispatch<double, kProject>(pol, n, batch, max_sweeps, st);
+}
+
+hipError_t launch_eigvalsh_batched(const double* in, double* w, int n, int batch, bool is_complex, int max_sweeps,
+                                   int* sweeps, hipStream_t st) {
+  if (is_complex) {
+    ArrayPolicy<true> pol{in, nullptr, w, nullptr, sweeps, n};
+    return dispatch<cplx<double>, kEigvals>(pol, n, batch, max_sweeps, st);
+  }
+  ArrayPolicy<false> pol{in, nullptr, w, nullptr, sweeps, n};
+  return dispatch<double, kEigvals>(pol, n, batch, max_sweeps, st);
+}
+
+hipError_t launch_lambda_min(const double* K, double* lmin, int n, int count, int max_sweeps, int* sweeps,
+                             hipStream_t st) {
+  ArrayPolicy<false> pol{K, nullptr, nullptr, lmin, sweeps, n};
+  return dispatch<double, kEigvals>(pol, n, count, max_sweeps, st);
+}
+
+}  // namespace vemb

@@ -1,0 +1,72 @@
+// Launchers of the device kernels, called by the host runtime (api.cpp).
+#pragma once
+
+#include "common.h"
+
+namespace vemb {
+
+// ----- Jacobi PSD projection / eigenvalues (jacobi.hip) -------------------
+// All launchers enqueue on `st` and return hipSuccess or the launch error.
+
+// Pair step 3 + Lambda update: C = rho - Lam/mu; rho_t = Pi(C); Lam += mu (rho_t - rho);
+// feas[d] = ||rho_d - rho_t_d||_F^2.  P matrices of size n.
+hipError_t launch_pair_projection(const double* rho, double* Lam, double* rho_t, double* feas, int n, int P,
+                                  double mu, int precision, int max_sweeps, int* sweeps, hipStream_t st);
+
+// Steps 8: Y_k = Pi((Xh_k + Xh_k^H)/2), in place on K complex n_op x n_op blocks
+// (interleaved re/im doubles).
+hipError_t launch_momentum_projection(double* Xh, int n_op, int K, int precision, int max_sweeps, int* sweeps,
+                                      hipStream_t st);
+
+// Isolated batched projection / eigenvalues (ABI entry points).
+hipError_t launch_psd_batched(const double* in, double* out, int n, int batch, bool is_complex, int precision,
+                              int max_sweeps, int* sweeps, hipStream_t st);
+hipError_t launch_eigvalsh_batched(const double* in, double* w, int n, int batch, bool is_complex,
+                                   int max_sweeps, int* sweeps, hipStream_t st);
+
+// Smallest eigenvalue of `count` symmetric n x n matrices stored contiguously.
+hipError_t launch_lambda_min(const double* K, double* lmin, int n, int count, int max_sweeps, int* sweeps,
+                             hipStream_t st);
+
+// ----- Iteration kernels (step_kernels.hip) ---------------------------------
+struct StepArgs {
+  // sizes
+  int M, P, m, n, n_op, Ku;
+  int opset;
+  double mu, nu, eps, sign;  // sign = -1 for X - eps G
+  double a, b, c;            // closed-form inverse coefficients
+  // fixed data
+  const double* H0;      // m x m
+  const double* Hd;      // nH x n x n (compact; only bonded offsets)
+  const int* hd_index;   // P entries: index into Hd or -1
+  const OpTables* ops;   // device copy (PAULI1)
+  const double* tw;      // Ku x M complex (interleaved): M^{-1/2} exp(-2 pi i d.k / M)
+  const double* wk;      // Ku weights (1 self-conjugate, 2 otherwise)
+  // state
+  double* X;     // M x n_op x n_op
+  double* Xp;    // M x n_op x n_op  (X - eps G)
+  double* Xh;    // Ku x n_op x n_op complex
+  double* rho0;  // m x m
+  double* rho;   // P x n x n
+  double* rho_t; // P x n x n
+  double* Lam;   // P x n x n
+  double* Lam1;  // P x m x m
+  double* Lam2;  // P x m x m
+  double* tr2;   // P x m x m  (A_1 rho_d)
+  double* tr1;   // P x m x m  (A_2 rho_d)
+  // diagnostics
+  double* e_pair;   // P: Tr(H_0d rho_d)
+  double* feas;     // P: ||rho_d - rho~_d||^2
+  double* scal;     // [0] Tr(H0 rho0), [1] sum_d ||A1 rho_d - rho0||^2 + ||A2 rho_d - rho0||^2
+  double* Kbuf;     // P x n x n scratch for the bound, and m x m (K_0) after it
+  double* lmin;     // P + 1
+  int* sweeps;      // per-matrix sweep counters (P + Ku + P + 1)
+};
+
+hipError_t launch_pair_update(const StepArgs& a, hipStream_t st);
+hipError_t launch_cluster_update(const StepArgs& a, hipStream_t st);
+hipError_t launch_dft_forward(const StepArgs& a, hipStream_t st);
+hipError_t launch_dft_inverse(const StepArgs& a, hipStream_t st);
+hipError_t launch_bound_build(const StepArgs& a, hipStream_t st);
+
+}  // namespace vemb

@@ -1,0 +1,389 @@
+// Per-iteration kernels of Algorithm 6 other than the eigensolves:
+//   pair_update     steps 1-2 (+ the G_0d part of step 6) for every offset d
+//   cluster_update  steps 4-5 (rho_0 and the consistency multipliers) + G_00 of step 6
+//   dft_forward     step 7  (momentum blocks of X')
+//   dft_inverse     step 9  (first block row of X from the projected blocks)
+//   bound_build     matrices whose smallest eigenvalues give the Lagrangian bound
+//
+// Index conventions: a pair index is (x, y) -> x*m + y (cluster 0 first).
+// Matrix units O_(a,b) = E_ab give, for the complete operator collection,
+//   R(X)_(x,y),(x',y') = X_(x',x),(y,y')   (pair correction of eq. effHam)
+//   G_0d(rho)_(a,b),(c,e) = rho_(a,e),(b,c) (realignment)
+//   C_0(X)_(b,e) = sum_a X_(a,b),(a,e);  G_00(rho0)_(a,b),(c,e) = delta_ac rho0_(e,b).
+// The single-site Pauli collection uses signed-permutation tables instead.
+#include "kernels.h"
+
+namespace vemb {
+namespace {
+
+constexpr int kBlock = 256;
+
+// sum over the generic (signed permutation) operators:
+// R(X)_(x,y),(x',y') = (1/m) sum_ab X_ab [x = perm_a(x')] sgn_a(x') [y' = perm_b(y)] sgn_b(y)
+__device__ double rx_generic(const double* X, const OpTables& T, int m, int x, int y, int xp, int yp) {
+  double acc = 0.0;
+  for (int a = 0; a < T.n_op; ++a) {
+    if (T.perm[a][xp] != x) continue;
+    const double sa = T.sign[a][xp];
+    for (int b = 0; b < T.n_op; ++b) {
+      if (T.perm[b][y] != yp) continue;
+      acc += X[a * T.n_op + b] * sa * T.sign[b][y];
+    }
+  }
+  return acc / m;
+}
+
+__device__ inline double rx_value(const StepArgs& A, const double* Xd, int x, int y, int xp, int yp) {
+  const int m = A.m;
+  if (A.opset == VEMB_OPSET_COMPLETE) return Xd[(size_t)(xp * m + x) * A.n_op + (y * m + yp)];
+  return rx_generic(Xd, *A.ops, m, x, y, xp, yp);
+}
+
+// R_d(i, j) of eq. rhoijUpdate's right-hand side:
+// mu rho~ + (nu rho0 - L1) x I + I x (nu rho0 - L2) + Lam - H'_d,  H'_d = H_d - RX - RX^T.
+__device__ double rhs_value(const StepArgs& A, int pd, int i, int j) {
+  const int m = A.m, n = A.n;
+  const int x = i / m, y = i % m, xp = j / m, yp = j % m;
+  const size_t o = (size_t)pd * n * n + (size_t)i * n + j;
+  const double* Xd = A.X + (size_t)(pd + 1) * A.n_op * A.n_op;
+  double v = A.mu * A.rho_t[o] + A.Lam[o];
+  const int h = A.hd_index[pd];
+  if (h >= 0) v -= A.Hd[(size_t)h * n * n + (size_t)i * n + j];
+  v += rx_value(A, Xd, x, y, xp, yp) + rx_value(A, Xd, xp, yp, x, y);
+  const size_t mo = (size_t)pd * m * m;
+  if (y == yp) v += A.nu * A.rho0[x * m + xp] - A.Lam1[mo + x * m + xp];
+  if (x == xp) v += A.nu * A.rho0[y * m + yp] - A.Lam2[mo + y * m + yp];
+  return v;
+}
+
+// ---------------------------------------------------------------------------
+// Steps 1-2 and X'_0d.  One workgroup per offset d.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kBlock) pair_update_kernel(StepArgs A) {
+  const int pd = blockIdx.x;  // offset d = pd + 1
+  const int m = A.m, n = A.n, mm = m * m;
+  const int tid = threadIdx.x;
+  __shared__ double T2[kMaxM * kMaxM];  // Tr_2 R
+  __shared__ double T1[kMaxM * kMaxM];  // Tr_1 R
+  __shared__ double red[kBlock];
+  __shared__ double trR_s;
+
+  // partial traces of R: Tr_2 R(x,x') = sum_y R(xy, x'y); Tr_1 R(y,y') = sum_x R(xy, xy')
+  for (int e = tid; e < 2 * mm; e += kBlock) {
+    const int which = e / mm, u = (e % mm) / m, w = e % m;
+    double acc = 0.0;
+    for (int k = 0; k < m; ++k) {
+      if (which == 0)
+        acc += rhs_value(A, pd, u * m + k, w * m + k);
+      else
+        acc += rhs_value(A, pd, k * m + u, k * m + w);
+    }
+    if (which == 0)
+      T2[u * m + w] = acc;
+    else
+      T1[u * m + w] = acc;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double t = 0.0;
+    for (int u = 0; u < m; ++u) t += T2[u * m + u];
+    trR_s = t;
+  }
+  __syncthreads();
+  const double trR = trR_s;
+  const double a = A.a, bm = A.b / m, cm2 = A.c / ((double)m * m) * trR;
+
+  // rho = a R + (b/m)(Tr_2 R x I + I x Tr_1 R) + (c/m^2) Tr R I, and Tr(H_0d rho)
+  const int h = A.hd_index[pd];
+  double epart = 0.0;
+  for (int idx = tid; idx < n * n; idx += kBlock) {
+    const int i = idx / n, j = idx % n;
+    const int x = i / m, y = i % m, xp = j / m, yp = j % m;
+    double v = a * rhs_value(A, pd, i, j);
+    double corr = 0.0;
+    if (y == yp) corr += T2[x * m + xp];
+    if (x == xp) corr += T1[y * m + yp];
+    v += bm * corr;
+    if (i == j) v += cm2;
+    A.rho[(size_t)pd * n * n + idx] = v;
+    if (h >= 0) epart += A.Hd[(size_t)h * n * n + (size_t)j * n + i] * v;
+  }
+  // A_1 rho = (a + b) Tr_2 R + ((b + c)/m) Tr R I ;  A_2 rho likewise with Tr_1 R
+  const double ab = A.a + A.b, bc = (A.b + A.c) / m * trR;
+  for (int e = tid; e < mm; e += kBlock) {
+    const int u = e / m, w = e % m;
+    A.tr2[(size_t)pd * mm + e] = ab * T2[e] + (u == w ? bc : 0.0);
+    A.tr1[(size_t)pd * mm + e] = ab * T1[e] + (u == w ? bc : 0.0);
+  }
+  red[tid] = epart;
+  __syncthreads();
+  for (int s = kBlock / 2; s > 0; s >>= 1) {
+    if (tid < s) red[tid] += red[tid + s];
+    __syncthreads();
+  }
+  if (tid == 0) A.e_pair[pd] = red[0];
+}
+
+// X'_0d = X_0d + sign eps G_0d(rho_0d) for d = 1..M-1, one thread per entry.
+__global__ void __launch_bounds__(kBlock) pair_xstep_kernel(StepArgs A) {
+  const int pd = blockIdx.y;
+  const int k = A.n_op, m = A.m, n = A.n;
+  const int e = blockIdx.x * kBlock + threadIdx.x;
+  if (e >= k * k) return;
+  const size_t xo = (size_t)(pd + 1) * k * k + e;
+  const double* rho = A.rho + (size_t)pd * n * n;
+  double g;
+  if (A.opset == VEMB_OPSET_COMPLETE) {
+    const int al = e / k, be = e % k;
+    const int aa = al / m, bb = al % m, cc = be / m, ee = be % m;
+    g = rho[(size_t)(aa * m + ee) * n + (bb * m + cc)];
+  } else {
+    // G_ab = (1/m) sum_{x', y} sgn_a(x') sgn_b(y) rho_(x', perm_b(y)),(perm_a(x'), y)
+    const OpTables& T = *A.ops;
+    const int al = e / k, be = e % k;
+    double acc = 0.0;
+    for (int xp = 0; xp < m; ++xp)
+      for (int y = 0; y < m; ++y)
+        acc += T.sign[al][xp] * T.sign[be][y] *
+               rho[(size_t)(xp * m + T.perm[be][y]) * n + (T.perm[al][xp] * m + y)];
+    g = acc / m;
+  }
+  A.Xp[xo] = A.X[xo] + A.sign * A.eps * g;
+}
+
+// ---------------------------------------------------------------------------
+// Steps 4-5 and X'_00.  A single workgroup.
+// ---------------------------------------------------------------------------
+__device__ double c0_value(const StepArgs& A, int b, int e) {
+  const int m = A.m, k = A.n_op;
+  if (A.opset == VEMB_OPSET_COMPLETE) {
+    double acc = 0.0;
+    for (int a = 0; a < m; ++a) acc += A.X[(size_t)(a * m + b) * k + (a * m + e)];
+    return acc;
+  }
+  // sum_ab X_ab O_a^T O_b:  (O_a^T O_b)(u, w) = (1/m) sum_v [u = perm_a(v)][w = perm_b(v)] sgn_a(v) sgn_b(v)
+  const OpTables& T = *A.ops;
+  double acc = 0.0;
+  for (int v = 0; v < m; ++v)
+    for (int al = 0; al < k; ++al) {
+      if (T.perm[al][v] != b) continue;
+      for (int be = 0; be < k; ++be) {
+        if (T.perm[be][v] != e) continue;
+        acc += A.X[al * k + be] * T.sign[al][v] * T.sign[be][v];
+      }
+    }
+  return acc / m;
+}
+
+constexpr int kClusterBlock = 1024;
+
+__global__ void __launch_bounds__(kClusterBlock) cluster_update_kernel(StepArgs A) {
+  const int m = A.m, mm = m * m, P = A.P, k = A.n_op;
+  const int tid = threadIdx.x;
+  __shared__ double r0[kMaxM * kMaxM];
+  __shared__ double red[kClusterBlock];
+  __shared__ double z_s;
+  // rho'_0 = [sum_d (nu A_1 rho_d + Lambda1_d) - H'_0] / (nu (M-1))
+  for (int e = tid; e < mm; e += kClusterBlock) {
+    double acc = 0.0;
+    for (int d = 0; d < P; ++d) acc += A.nu * A.tr2[(size_t)d * mm + e] + A.Lam1[(size_t)d * mm + e];
+    const double h0p = A.H0[e] - c0_value(A, e / m, e % m);
+    r0[e] = (acc - h0p) / (A.nu * (A.M - 1));
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double t = 0.0;
+    for (int u = 0; u < m; ++u) t += r0[u * m + u];
+    z_s = (1.0 - t) / m;
+  }
+  __syncthreads();
+  for (int e = tid; e < mm; e += kClusterBlock) {
+    if (e / m == e % m) r0[e] += z_s;
+  }
+  __syncthreads();
+  double part = 0.0, epart = 0.0;
+  for (int e = tid; e < mm; e += kClusterBlock) {
+    A.rho0[e] = r0[e];
+    epart += A.H0[(e % m) * m + e / m] * r0[e];
+  }
+  // multipliers with the new rho_0, and the consistency residuals of eq. feasErr
+  for (int idx = tid; idx < P * mm; idx += kClusterBlock) {
+    const int e = idx % mm;
+    const double d1 = A.tr2[idx] - r0[e];
+    const double d2 = A.tr1[idx] - r0[e];
+    A.Lam1[idx] += A.nu * d1;
+    A.Lam2[idx] += A.nu * d2;
+    part += d1 * d1 + d2 * d2;
+  }
+  // X'_00 = X_00 + sign eps G_00(rho_0)
+  for (int e = tid; e < k * k; e += kClusterBlock) {
+    const int al = e / k, be = e % k;
+    double g;
+    if (A.opset == VEMB_OPSET_COMPLETE) {
+      const int aa = al / m, bb = al % m, cc = be / m, ee = be % m;
+      g = (aa == cc) ? r0[ee * m + bb] : 0.0;
+    } else {
+      // Tr(O_a^T O_b rho0) = (1/m) sum_v sgn_a(v) sgn_b(v) rho0(perm_b(v), perm_a(v))
+      const OpTables& T = *A.ops;
+      double acc = 0.0;
+      for (int v = 0; v < m; ++v) acc += T.sign[al][v] * T.sign[be][v] * r0[T.perm[be][v] * m + T.perm[al][v]];
+      g = acc / m;
+    }
+    A.Xp[e] = A.X[e] + A.sign * A.eps * g;
+  }
+  red[tid] = part;
+  __syncthreads();
+  for (int s = kClusterBlock / 2; s > 0; s >>= 1) {
+    if (tid < s) red[tid] += red[tid + s];
+    __syncthreads();
+  }
+  const double cons = red[0];
+  __syncthreads();
+  red[tid] = epart;
+  __syncthreads();
+  for (int s = kClusterBlock / 2; s > 0; s >>= 1) {
+    if (tid < s) red[tid] += red[tid + s];
+    __syncthreads();
+  }
+  if (tid == 0) {
+    A.scal[0] = red[0];
+    A.scal[1] = cons;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Step 7: Xh_k = sum_d tw[k][d] X'_d over the unique momenta (tw includes M^{-1/2}).
+// Thread per entry e of the n_op x n_op block, KC momenta per thread.
+// ---------------------------------------------------------------------------
+constexpr int KC = 8;
+
+__global__ void __launch_bounds__(kBlock) dft_forward_kernel(StepArgs A) {
+  const int E = A.n_op * A.n_op;
+  const int e = blockIdx.x * kBlock + threadIdx.x;
+  const int k0 = blockIdx.y * KC;
+  if (e >= E) return;
+  const int kc = min(KC, A.Ku - k0);
+  double re[KC], im[KC];
+#pragma unroll
+  for (int c = 0; c < KC; ++c) re[c] = im[c] = 0.0;
+  for (int d = 0; d < A.M; ++d) {
+    const double v = A.Xp[(size_t)d * E + e];
+#pragma unroll
+    for (int c = 0; c < KC; ++c) {
+      if (c < kc) {
+        const double* t = A.tw + 2 * ((size_t)(k0 + c) * A.M + d);
+        re[c] += t[0] * v;
+        im[c] += t[1] * v;
+      }
+    }
+  }
+  for (int c = 0; c < kc; ++c) {
+    double* o = A.Xh + 2 * ((size_t)(k0 + c) * E + e);
+    o[0] = re[c];
+    o[1] = im[c];
+  }
+}
+
+// Step 9: X_d = sum_k w_k Re(conj(tw[k][d]) Y_k), thread per entry, DC offsets per thread.
+constexpr int DC = 8;
+
+__global__ void __launch_bounds__(kBlock) dft_inverse_kernel(StepArgs A) {
+  const int E = A.n_op * A.n_op;
+  const int e = blockIdx.x * kBlock + threadIdx.x;
+  const int d0 = blockIdx.y * DC;
+  if (e >= E) return;
+  const int dc = min(DC, A.M - d0);
+  double acc[DC];
+#pragma unroll
+  for (int c = 0; c < DC; ++c) acc[c] = 0.0;
+  for (int k = 0; k < A.Ku; ++k) {
+    const double* y = A.Xh + 2 * ((size_t)k * E + e);
+    const double yr = y[0], yi = y[1];
+    const double wk = A.wk[k];
+#pragma unroll
+    for (int c = 0; c < DC; ++c) {
+      if (c < dc) {
+        const double* t = A.tw + 2 * ((size_t)k * A.M + d0 + c);
+        // conj(t) * y = (tr yr + ti yi) + i(...)
+        acc[c] += wk * (t[0] * yr + t[1] * yi);
+      }
+    }
+  }
+  for (int c = 0; c < dc; ++c) A.X[(size_t)(d0 + c) * E + e] = acc[c];
+}
+
+// ---------------------------------------------------------------------------
+// Bound matrices: K_d = H'_d + sym(L1_d) x I + I x sym(L2_d) (P of them) and
+// K_0 = H'_0 - 1/2 sum_d (sym(L1_d) + sym(L2_d)) stored after them.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kBlock) bound_pair_kernel(StepArgs A) {
+  const int pd = blockIdx.y;
+  const int m = A.m, n = A.n;
+  const int idx = blockIdx.x * kBlock + threadIdx.x;
+  if (idx >= n * n) return;
+  const int i = idx / n, j = idx % n;
+  const int x = i / m, y = i % m, xp = j / m, yp = j % m;
+  const double* Xd = A.X + (size_t)(pd + 1) * A.n_op * A.n_op;
+  double v = -(rx_value(A, Xd, x, y, xp, yp) + rx_value(A, Xd, xp, yp, x, y));
+  const int h = A.hd_index[pd];
+  if (h >= 0) v += A.Hd[(size_t)h * n * n + idx];
+  const size_t mo = (size_t)pd * m * m;
+  if (y == yp) v += 0.5 * (A.Lam1[mo + x * m + xp] + A.Lam1[mo + xp * m + x]);
+  if (x == xp) v += 0.5 * (A.Lam2[mo + y * m + yp] + A.Lam2[mo + yp * m + y]);
+  A.Kbuf[(size_t)pd * n * n + idx] = v;
+}
+
+__global__ void __launch_bounds__(kBlock) bound_cluster_kernel(StepArgs A) {
+  const int m = A.m, mm = m * m;
+  double* K0 = A.Kbuf + (size_t)A.P * A.n * A.n;
+  for (int e = threadIdx.x; e < mm; e += kBlock) {
+    const int u = e / m, w = e % m;
+    double acc = 0.0;
+    for (int d = 0; d < A.P; ++d) {
+      const size_t o = (size_t)d * mm;
+      acc += 0.5 * (A.Lam1[o + e] + A.Lam1[o + w * m + u]) + 0.5 * (A.Lam2[o + e] + A.Lam2[o + w * m + u]);
+    }
+    K0[e] = A.H0[e] - c0_value(A, u, w) - 0.5 * acc;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_pair_update(const StepArgs& a, hipStream_t st) {
+  hipLaunchKernelGGL(pair_update_kernel, dim3(a.P), dim3(kBlock), 0, st, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int E = a.n_op * a.n_op;
+  hipLaunchKernelGGL(pair_xstep_kernel, dim3((E + kBlock - 1) / kBlock, a.P), dim3(kBlock), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_cluster_update(const StepArgs& a, hipStream_t st) {
+  hipLaunchKernelGGL(cluster_update_kernel, dim3(1), dim3(kClusterBlock), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_dft_forward(const StepArgs& a, hipStream_t st) {
+  const int E = a.n_op * a.n_op;
+  hipLaunchKernelGGL(dft_forward_kernel, dim3((E + kBlock - 1) / kBlock, (a.Ku + KC - 1) / KC), dim3(kBlock), 0,
+                     st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_dft_inverse(const StepArgs& a, hipStream_t st) {
+  const int E = a.n_op * a.n_op;
+  hipLaunchKernelGGL(dft_inverse_kernel, dim3((E + kBlock - 1) / kBlock, (a.M + DC - 1) / DC), dim3(kBlock), 0,
+                     st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_bound_build(const StepArgs& a, hipStream_t st) {
+  const int nn = a.n * a.n;
+  hipLaunchKernelGGL(bound_pair_kernel, dim3((nn + kBlock - 1) / kBlock, a.P), dim3(kBlock), 0, st, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(bound_cluster_kernel, dim3(1), dim3(kBlock), 0, st, a);
+  return hipGetLastError();
+}
+
+}  // namespace vemb

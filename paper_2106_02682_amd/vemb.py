@@ -1,0 +1,315 @@
+"""ctypes binding of libvemb (C ABI in include/vemb.h).
+
+Argument marshalling only: every step of the iteration runs in the HIP
+kernels of libvemb.so.  If the library is missing, loading fails loudly;
+there is no CPU fallback.  torch supplies device buffers and the HIP stream
+for the batched entry points.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libvemb.so")
+
+VEMB_OK = 0
+STATUS = {0: "VEMB_OK", -1: "VEMB_E_INVALID", -2: "VEMB_E_UNSUPPORTED", -3: "VEMB_E_NOMEM", -4: "VEMB_E_HIP",
+          -5: "VEMB_E_NUMERIC", -6: "VEMB_E_DIVERGED", -7: "VEMB_E_NOCONV"}
+PAULI = {"I": 0, "X": 1, "Y": 2, "Z": 3}
+OPSET = {"complete": 0, "pauli1": 1}
+PRECISION = {"fp64": 0, "mixed": 1}
+RHO, RHO_TILDE = 0, 1
+
+EXPORTS = [
+    "vemb_default_options", "vemb_create_problem", "vemb_problem_info", "vemb_step", "vemb_dual_bound",
+    "vemb_primal_energy", "vemb_marginals", "vemb_get_state", "vemb_set_state", "vemb_destroy",
+    "vemb_last_error", "vemb_psd_project_batched", "vemb_eigvalsh_batched", "vemb_last_sweeps",
+    "vemb_psd_project_batched_ex",
+]
+
+
+class VembError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class vemb_term(ctypes.Structure):
+    _fields_ = [("coeff", ctypes.c_double), ("nsites", ctypes.c_int32), ("pauli", ctypes.c_int32 * 2),
+                ("offset", (ctypes.c_int32 * 2) * 2)]
+
+
+class vemb_hamiltonian(ctypes.Structure):
+    _fields_ = [("nterms", ctypes.c_int32), ("terms", ctypes.POINTER(vemb_term))]
+
+
+class vemb_lattice(ctypes.Structure):
+    _fields_ = [("ndim", ctypes.c_int32), ("extent", ctypes.c_int32 * 2), ("periodic", ctypes.c_int32 * 2)]
+
+
+class vemb_clusters(ctypes.Structure):
+    _fields_ = [("shape", ctypes.c_int32 * 2)]
+
+
+class vemb_options(ctypes.Structure):
+    _fields_ = [("mu", ctypes.c_double), ("nu", ctypes.c_double), ("eps", ctypes.c_double),
+                ("opset", ctypes.c_int32), ("precision", ctypes.c_int32), ("max_sweeps", ctypes.c_int32),
+                ("sign", ctypes.c_int32)]
+
+
+class vemb_info(ctypes.Structure):
+    _fields_ = [("M", ctypes.c_int32), ("P", ctypes.c_int32), ("L", ctypes.c_int32), ("m", ctypes.c_int32),
+                ("n", ctypes.c_int32), ("n_op", ctypes.c_int32), ("Mx", ctypes.c_int32), ("My", ctypes.c_int32),
+                ("K_unique", ctypes.c_int32), ("t", ctypes.c_int64)]
+
+
+_DP = ctypes.POINTER(ctypes.c_double)
+
+
+class vemb_state(ctypes.Structure):
+    _fields_ = [("t", ctypes.c_int64), ("X", _DP), ("rho0", _DP), ("rho", _DP), ("rho_t", _DP), ("Lam", _DP),
+                ("Lam1", _DP), ("Lam2", _DP)]
+
+
+_lib = None
+
+
+def lib():
+    """Loads libvemb.so; raises if it has not been built (no fallback exists)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2106_02682_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    vp = ctypes.c_void_p
+    L.vemb_default_options.argtypes = [ctypes.POINTER(vemb_options)]
+    L.vemb_default_options.restype = None
+    L.vemb_create_problem.argtypes = [ctypes.POINTER(vemb_hamiltonian), ctypes.POINTER(vemb_lattice),
+                                      ctypes.POINTER(vemb_clusters), ctypes.POINTER(vemb_options), vp,
+                                      ctypes.POINTER(vp)]
+    L.vemb_problem_info.argtypes = [vp, ctypes.POINTER(vemb_info)]
+    L.vemb_step.argtypes = [vp, ctypes.c_int]
+    L.vemb_dual_bound.argtypes = [vp, _DP]
+    L.vemb_primal_energy.argtypes = [vp, _DP, _DP]
+    L.vemb_marginals.argtypes = [vp, ctypes.c_int, _DP, _DP]
+    L.vemb_get_state.argtypes = [vp, ctypes.POINTER(vemb_state)]
+    L.vemb_set_state.argtypes = [vp, ctypes.POINTER(vemb_state)]
+    L.vemb_destroy.argtypes = [vp]
+    L.vemb_destroy.restype = None
+    L.vemb_last_error.argtypes = []
+    L.vemb_last_error.restype = ctypes.c_char_p
+    L.vemb_psd_project_batched.argtypes = [vp, vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp]
+    L.vemb_eigvalsh_batched.argtypes = [vp, vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp]
+    L.vemb_last_sweeps.argtypes = [vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
+    L.vemb_psd_project_batched_ex.argtypes = [vp, vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                              ctypes.c_int, vp, vp]
+    for name in EXPORTS:
+        if name not in ("vemb_default_options", "vemb_destroy", "vemb_last_error"):
+            getattr(L, name).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def _check(rc):
+    if rc != VEMB_OK:
+        raise VembError(rc, lib().vemb_last_error().decode())
+    return rc
+
+
+def _ptr(a):
+    return a.ctypes.data_as(_DP) if a is not None else None
+
+
+def current_stream():
+    """torch's current HIP stream as a void pointer (NULL when torch has no GPU)."""
+    try:
+        import torch
+
+        if torch.cuda.is_available():
+            return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    except ImportError:
+        pass
+    return ctypes.c_void_p(None)
+
+
+def default_options():
+    o = vemb_options()
+    lib().vemb_default_options(ctypes.byref(o))
+    return o
+
+
+def create_problem(terms, extent, cluster, opset="complete", precision="fp64", mu=10.0, nu=10.0, eps=2.0,
+                   max_sweeps=40, sign=-1, stream=None):
+    """Terms in the ``synth`` format: (coeff, ((pauli, (ox, oy)), ...))."""
+    arr = (vemb_term * max(1, len(terms)))()
+    for t, (coeff, factors) in enumerate(terms):
+        arr[t].coeff = float(coeff)
+        arr[t].nsites = len(factors)
+        for s, (pl, off) in enumerate(factors[:2]):
+            arr[t].pauli[s] = PAULI[pl]
+            arr[t].offset[s][0] = int(off[0])
+            arr[t].offset[s][1] = int(off[1])
+    H = vemb_hamiltonian(len(terms), arr)
+    ndim = 1 if extent[1] == 1 else 2
+    lat = vemb_lattice(ndim, (ctypes.c_int32 * 2)(extent[0], extent[1]), (ctypes.c_int32 * 2)(1, 1))
+    cl = vemb_clusters((ctypes.c_int32 * 2)(cluster[0], cluster[1]))
+    o = default_options()
+    o.mu, o.nu, o.eps = mu, nu, eps
+    o.opset = OPSET[opset]
+    o.precision = PRECISION[precision]
+    o.max_sweeps = max_sweeps
+    o.sign = sign
+    h = ctypes.c_void_p()
+    st = stream if stream is not None else current_stream()
+    _check(lib().vemb_create_problem(ctypes.byref(H), ctypes.byref(lat), ctypes.byref(cl), ctypes.byref(o), st,
+                                     ctypes.byref(h)))
+    return h
+
+
+def problem_info(h):
+    info = vemb_info()
+    _check(lib().vemb_problem_info(h, ctypes.byref(info)))
+    return {f: getattr(info, f) for f, _ in vemb_info._fields_}
+
+
+def step(h, iters):
+    _check(lib().vemb_step(h, int(iters)))
+
+
+def dual_bound(h):
+    v = ctypes.c_double()
+    _check(lib().vemb_dual_bound(h, ctypes.byref(v)))
+    return v.value
+
+
+def primal_energy(h):
+    e, f = ctypes.c_double(), ctypes.c_double()
+    _check(lib().vemb_primal_energy(h, ctypes.byref(e), ctypes.byref(f)))
+    return e.value, f.value
+
+
+def marginals(h, which=RHO):
+    info = problem_info(h)
+    rho0 = np.zeros((info["m"], info["m"]))
+    pairs = np.zeros((info["P"], info["n"], info["n"]))
+    _check(lib().vemb_marginals(h, which, _ptr(rho0), _ptr(pairs)))
+    return rho0, pairs
+
+
+def _state_arrays(info):
+    M, P, m, n, k = info["M"], info["P"], info["m"], info["n"], info["n_op"]
+    return {"X": np.zeros((M, k, k)), "rho0": np.zeros((m, m)), "rho": np.zeros((P, n, n)),
+            "rho_t": np.zeros((P, n, n)), "Lam": np.zeros((P, n, n)), "Lam1": np.zeros((P, m, m)),
+            "Lam2": np.zeros((P, m, m))}
+
+
+def get_state(h):
+    info = problem_info(h)
+    arrs = _state_arrays(info)
+    st = vemb_state(0, *[_ptr(arrs[k]) for k in ("X", "rho0", "rho", "rho_t", "Lam", "Lam1", "Lam2")])
+    _check(lib().vemb_get_state(h, ctypes.byref(st)))
+    arrs["t"] = st.t
+    return arrs
+
+
+def set_state(h, state):
+    keys = ("X", "rho0", "rho", "rho_t", "Lam", "Lam1", "Lam2")
+    arrs = {k: np.ascontiguousarray(state[k], dtype=np.float64) for k in keys}
+    st = vemb_state(int(state.get("t", 0)), *[_ptr(arrs[k]) for k in keys])
+    _check(lib().vemb_set_state(h, ctypes.byref(st)))
+
+
+def destroy(h):
+    if h:
+        lib().vemb_destroy(h)
+
+
+def psd_project_batched(inp, out, is_complex=False, precision="fp64", stream=None):
+    """Device tensors (torch, float64; complex as interleaved float64 pairs)."""
+    n = inp.shape[-2]
+    batch = inp.numel() // (n * n * (2 if is_complex else 1))
+    st = stream if stream is not None else current_stream()
+    _check(lib().vemb_psd_project_batched(ctypes.c_void_p(inp.data_ptr()), ctypes.c_void_p(out.data_ptr()), n,
+                                          batch, int(is_complex), PRECISION[precision], st))
+
+
+def psd_project_batched_ex(inp, out, is_complex=False, precision="fp64", max_sweeps=0, sweeps=None, stream=None):
+    """As psd_project_batched; ``sweeps`` is an optional int32 device tensor of length batch."""
+    n = inp.shape[-2]
+    batch = inp.numel() // (n * n * (2 if is_complex else 1))
+    st = stream if stream is not None else current_stream()
+    sp = ctypes.c_void_p(sweeps.data_ptr()) if sweeps is not None else ctypes.c_void_p(None)
+    _check(lib().vemb_psd_project_batched_ex(ctypes.c_void_p(inp.data_ptr()), ctypes.c_void_p(out.data_ptr()), n,
+                                             batch, int(is_complex), PRECISION[precision], int(max_sweeps), sp, st))
+
+
+def last_sweeps(h):
+    a, b = ctypes.c_int(), ctypes.c_int()
+    _check(lib().vemb_last_sweeps(h, ctypes.byref(a), ctypes.byref(b)))
+    return a.value, b.value
+
+
+def eigvalsh_batched(inp, w, is_complex=False, stream=None):
+    n = inp.shape[-2]
+    batch = inp.numel() // (n * n * (2 if is_complex else 1))
+    st = stream if stream is not None else current_stream()
+    _check(lib().vemb_eigvalsh_batched(ctypes.c_void_p(inp.data_ptr()), ctypes.c_void_p(w.data_ptr()), n, batch,
+                                       int(is_complex), st))
+
+
+class Problem:
+    """Owning wrapper of one problem handle."""
+
+    def __init__(self, terms, extent, cluster, **kw):
+        self.h = create_problem(terms, extent, cluster, **kw)
+        self.info = problem_info(self.h)
+
+    @classmethod
+    def from_workload(cls, w, **kw):
+        kw.setdefault("opset", w.opset)
+        kw.setdefault("mu", w.mu)
+        kw.setdefault("nu", w.nu)
+        kw.setdefault("eps", w.eps)
+        return cls(w.terms, w.extent, w.cluster, **kw)
+
+    def step(self, iters=1):
+        step(self.h, iters)
+
+    def dual_bound(self):
+        return dual_bound(self.h)
+
+    def last_sweeps(self):
+        return last_sweeps(self.h)
+
+    def primal_energy(self):
+        return primal_energy(self.h)
+
+    def marginals(self, which=RHO):
+        return marginals(self.h, which)
+
+    def get_state(self):
+        return get_state(self.h)
+
+    def set_state(self, s):
+        set_state(self.h, s)
+
+    def close(self):
+        if self.h:
+            destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

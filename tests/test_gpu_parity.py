@@ -1,0 +1,225 @@
+"""GPU parity of the HIP path against the FP64 oracle (calls go through the C ABI).
+
+* batched PSD projection and eigenvalues vs the oracle's projection / numpy,
+  real and Hermitian, sizes spanning every LDS size class, odd sizes (padding
+  column) and degenerate inputs (zero, PSD, NSD, repeated eigenvalues);
+* full iterations of Algorithm 6 vs the oracle at equal iteration counts:
+  the Lagrangian bound to 1e-10 relative (FP64), energies, feasibility and
+  every state array element by element;
+* the bench workload (N=384 ring, 3-site clusters, 64 x 64 marginals) at the
+  launch configuration the benchmark times, compared after a few iterations.
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import alg6
+from oracle.maps import psd_project
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def vemb():
+    if not torch.cuda.is_available():
+        pytest.fail("gpu tests need a GPU")
+    from paper_2106_02682_amd import vemb as v
+
+    v.lib()
+    return v
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def _interleave(c):
+    return np.stack([c.real, c.imag], axis=-1)
+
+
+def _deinterleave(a):
+    return a[..., 0] + 1j * a[..., 1]
+
+
+@pytest.mark.parametrize("n,batch", [(2, 5), (3, 7), (4, 64), (7, 9), (8, 33), (16, 130), (33, 5), (64, 127),
+                                     (128, 3)])
+def test_projection_real_fp64(vemb, n, batch):
+    C = synth.admm_like_batch(n, batch, tag=11)
+    out = torch.empty(C.shape, dtype=torch.float64, device="cuda")
+    vemb.psd_project_batched(_dev(C), out)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    want = psd_project(C)
+    scale = np.abs(C).max()
+    assert np.abs(got - want).max() <= 1e-12 * max(scale, 1.0) * max(1, n / 16)
+
+
+@pytest.mark.parametrize("n,batch", [(3, 8), (4, 8), (9, 6), (16, 65), (64, 65)])
+def test_projection_complex_fp64(vemb, n, batch):
+    C = synth.hermitian_batch(n, batch, tag=12)
+    out = torch.empty(C.shape + (2,), dtype=torch.float64, device="cuda")
+    vemb.psd_project_batched(_dev(_interleave(C)), out, is_complex=True)
+    torch.cuda.synchronize()
+    got = _deinterleave(out.cpu().numpy())
+    want = psd_project(C)
+    assert np.abs(got - want).max() <= 1e-12 * max(1.0, np.abs(C).max()) * max(1, n / 16)
+
+
+def test_projection_degenerate_inputs(vemb):
+    n = 16
+    rng = np.random.default_rng(3)
+    B = rng.standard_normal((n, n))
+    S = B @ B.T / n
+    Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    rep = Q @ np.diag([1.0] * 5 + [-1.0] * 5 + [0.0] * 6) @ Q.T  # +-1 pairs and a zero block
+    cases = np.stack([np.zeros((n, n)), S, -S, rep, np.eye(n), -np.eye(n)])
+    out = torch.empty(cases.shape, dtype=torch.float64, device="cuda")
+    vemb.psd_project_batched(_dev(cases), out)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    want = psd_project(cases)
+    assert np.abs(got - want).max() < 1e-12
+    assert np.abs(got[0]).max() == 0.0
+
+
+@pytest.mark.parametrize("n,cplx", [(5, False), (16, False), (64, False), (128, False), (16, True), (64, True)])
+def test_eigenvalues(vemb, n, cplx):
+    if cplx:
+        C = synth.hermitian_batch(n, 9, tag=13)
+        inp = _dev(_interleave(C))
+    else:
+        C = synth.admm_like_batch(n, 9, tag=13)
+        inp = _dev(C)
+    w = torch.empty((9, n), dtype=torch.float64, device="cuda")
+    vemb.eigvalsh_batched(inp, w, is_complex=cplx)
+    torch.cuda.synchronize()
+    want = np.linalg.eigvalsh(C)
+    assert np.abs(w.cpu().numpy() - want).max() <= 1e-12 * max(1.0, np.abs(want).max()) * max(1, n / 16)
+
+
+def _tight_gershgorin_cases(complex_phases):
+    """Singlet/triplet matrices x P_s + y P_t (x > 0 > y): the Gershgorin shift equals -lambda_min, so
+    B = C + s I is exactly singular with a triple (or larger) zero eigenvalue -- rounding-noise columns."""
+    v = np.array([0.0, 1.0, -1.0, 0.0]) / np.sqrt(2.0)
+    Ps = np.outer(v, v)
+    out = []
+    for x, y in [(0.238, -1.61), (0.9, -0.3), (1.0, -1.0)]:
+        C = x * Ps + y * (np.eye(4) - Ps)
+        for blk in (C, np.kron(C, np.eye(4)), np.kron(np.eye(2), C)):
+            if complex_phases:
+                th = np.linspace(0.3, 2.9, blk.shape[0])
+                D = np.diag(np.exp(1j * th))
+                blk = D @ blk @ D.conj().T
+            out.append(blk)
+    return out
+
+
+@pytest.mark.parametrize("cplx", [False, True])
+@pytest.mark.parametrize("max_sweeps", [40, 400])
+def test_projection_exactly_singular_shift(vemb, cplx, max_sweeps):
+    """Regression: noise columns of an exactly singular B must not be rotated forever (the complex
+    phase of an underflowing inner product rescaled the surviving column)."""
+    for C in _tight_gershgorin_cases(cplx):
+        n = C.shape[0]
+        inp = _dev(_interleave(C[None]) if cplx else C[None])
+        out = torch.empty_like(inp)
+        sw = torch.zeros(1, dtype=torch.int32, device="cuda")
+        vemb.psd_project_batched_ex(inp, out, is_complex=cplx, max_sweeps=max_sweeps, sweeps=sw)
+        torch.cuda.synchronize()
+        got = out.cpu().numpy()[0]
+        got = _deinterleave(got) if cplx else got
+        assert np.abs(got - psd_project(C)).max() < 1e-14 * n
+        assert int(sw.cpu()[0]) < 10
+
+
+def test_projection_inplace_alias(vemb):
+    C = synth.admm_like_batch(32, 10, tag=14)
+    buf = _dev(C)
+    vemb.psd_project_batched(buf, buf)
+    torch.cuda.synchronize()
+    assert np.abs(buf.cpu().numpy() - psd_project(C)).max() < 1e-12
+
+
+# ---------------------------------------------------------------------------
+# Full iterations
+# ---------------------------------------------------------------------------
+
+def _compare(w, iters, rel_lb=1e-10, atol_state=1e-9):
+    p = alg6.Problem.from_workload(w)
+    s, _ = alg6.solve(p, iters)
+    from paper_2106_02682_amd import vemb as v
+
+    with v.Problem.from_workload(w) as g:
+        worst = (0, 0)
+        for _ in range(iters):
+            g.step(1)
+            sw = g.last_sweeps()
+            worst = (max(worst[0], sw[0]), max(worst[1], sw[1]))
+        assert max(worst) < 40, f"an eigensolve hit the sweep cap: {worst}"
+        st = g.get_state()
+        lb = g.dual_bound()
+        e, feas = g.primal_energy()
+    assert st["t"] == iters
+    lb_o = alg6.lower_bound(p, s)
+    assert abs(lb - lb_o) <= rel_lb * abs(lb_o), (lb, lb_o)
+    assert abs(e - alg6.energy_per_site(p, s)) <= rel_lb * abs(lb_o)
+    fo = alg6.feasibility_error(p, s)
+    assert abs(feas - fo) <= 1e-8 * max(fo, 1e-3)
+    for key, ref in [("X", s.X), ("rho0", s.rho0), ("rho", s.rho), ("rho_t", s.rho_t), ("Lam", s.Lam),
+                     ("Lam1", s.Lam1), ("Lam2", s.Lam2)]:
+        err = np.abs(st[key] - ref).max()
+        assert err <= atol_state * max(1.0, np.abs(ref).max()), (key, err)
+    return lb, lb_o
+
+
+@pytest.mark.parametrize("w,iters", [
+    (synth.tfi_ring(8, 1, 1.0), 300),
+    (synth.tfi_ring(8, 1, 1.0, "pauli1"), 300),
+    (synth.tfi_ring(8, 2, 1.0), 200),
+    (synth.tfi_ring(6, 1, 0.5), 200),
+    (synth.tfi_ring(9, 3, 1.5), 60),
+    (synth.xxz_ring(8, 2, 0.7), 150),
+    (synth.tfi_ring(4, 2, 1.0), 200),
+    (synth.tfi_torus(4, 4, 2, 1, 1.0), 80),
+    (synth.tfi_torus(6, 4, 1, 2, 3.0), 40),
+    (synth.afh_torus(4, 4, 1, 1), 100),
+], ids=lambda x: getattr(x, "name", str(x)))
+def test_iteration_parity_fp64(vemb, w, iters):
+    _compare(w, iters)
+
+
+def test_bench_workload_parity(vemb):
+    """N = 384 ring, L = 3 (127 pair marginals 64 x 64, 65 unique momentum blocks 64 x 64)."""
+    w = synth.config_c2(1.0)[1]
+    _compare(w, 5, rel_lb=1e-10, atol_state=1e-9)
+
+
+def test_state_roundtrip_and_resume(vemb):
+    """get_state / set_state round trip; resuming gives the same iterates as running through."""
+    w = synth.tfi_ring(8, 2, 1.0)
+    from paper_2106_02682_amd import vemb as v
+
+    with v.Problem.from_workload(w) as a, v.Problem.from_workload(w) as b:
+        a.step(30)
+        mid = a.get_state()
+        a.step(20)
+        b.set_state(mid)
+        b.step(20)
+        sa, sb = a.get_state(), b.get_state()
+    for k in ("X", "rho0", "rho_t", "Lam", "Lam1", "Lam2"):
+        assert np.array_equal(sa[k], sb[k]), k
+    assert sb["t"] == 50
+
+
+def test_set_state_rejects_nonfinite(vemb):
+    w = synth.tfi_ring(8, 1, 1.0)
+    from paper_2106_02682_amd import vemb as v
+
+    with v.Problem.from_workload(w) as g:
+        st = g.get_state()
+        st["Lam"][0, 0, 0] = np.nan
+        with pytest.raises(v.VembError) as ei:
+            g.set_state(st)
+        assert ei.value.code == -5
