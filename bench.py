@@ -1,0 +1,186 @@
+"""Benchmark of the Algorithm 6 hot path on one MI355X.
+
+One step = one full iteration of Algorithm 6 (effective Hamiltonians, pair
+update, pair PSD projections, cluster update, multiplier updates, X gradient
+step, lattice DFT, momentum-block PSD projections, inverse DFT), with the FP64
+diagnostics (Lagrangian bound, energy, feasibility) every ``--lb-every`` steps,
+on synthetic input of the benchmark workload, all state resident in HBM.
+
+Default workload: transverse-field Ising ring, N = 384 sites, J = 1, h = 1,
+clusters of 3 sites (M = 128 clusters): 127 pair marginals of 64 x 64 and 65
+unique 64 x 64 complex momentum blocks per step.
+
+Prints ONE JSON line.  ``value`` = pair PSD projections per second (64 x 64).
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "PSD projections/s (2^k×2^k) & time to 1e-6 SDP gap: warm-start vs cold"
+PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3}  # MI355X vector peaks: 256 CU x 4 SIMD x 16 lanes x 2 x 2.4 GHz (f32 x2)
+
+
+def flops_per_launch(kernel, info):
+    """Algorithmic flops of one launch (Golub-Van Loan counts, no Jacobi overhead):
+    pair projection 11 n^3 per matrix (9 n^3 eigendecomposition with vectors + 2 n^3
+    rebuild); momentum projection 44 n_op^3 per complex block (4x real)."""
+    if kernel == "pair_projection":
+        return 11.0 * info["n"] ** 3 * info["P"]
+    if kernel == "momentum_projection":
+        return 44.0 * info["n_op"] ** 3 * info["K_unique"]
+    raise KeyError(kernel)
+
+
+def source_digest():
+    h = hashlib.sha256()
+    for f in ("jacobi.hip",):
+        with open(os.path.join(ROOT, "paper_2106_02682_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel, precision, launches_bytes=None):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it is current."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    entry = t.get(f"{kernel}/{precision}")
+    if not entry or entry.get("source_digest") != source_digest():
+        return None
+    return entry.get("bytes_per_launch")
+
+
+def cpu_baseline(workload, seconds):
+    """The FP64 oracle (numpy / LAPACK) on this host's cores, on a bounded number of iterations."""
+    import numpy as np  # noqa: F401
+    from oracle import alg6
+
+    threads = None
+    try:
+        from threadpoolctl import threadpool_info
+
+        threads = max((d.get("num_threads", 1) for d in threadpool_info()), default=None)
+    except Exception:
+        pass
+    p = alg6.Problem.from_workload(workload)
+    s = alg6.initial_state(p)
+    s = alg6.step(p, s)  # warm-up
+    t0 = time.perf_counter()
+    it = 0
+    while True:
+        s = alg6.step(p, s)
+        it += 1
+        if time.perf_counter() - t0 >= seconds:
+            break
+    dt = time.perf_counter() - t0
+    return {
+        "value": p.P * it / dt,
+        "unit": "projections/s",
+        "cores": threads or os.cpu_count(),
+        "kind": "oracle",
+        "sample": f"{it} oracle iterations of the same workload ({p.P} pair projections each) after 1 warm-up, "
+                  f"{dt:.1f} s",
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--h", type=float, default=1.0)
+    ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
+    ap.add_argument("--lb-every", type=int, default=10)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="oracle sample length (0 disables)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (this build has no multi-GPU path); got --gpus {args.gpus}",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import synth
+    from paper_2106_02682_amd import vemb
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    w = synth.config_c2(args.h)[1]
+    g = vemb.Problem.from_workload(w, precision=args.precision)
+    info = g.info
+    g.step(args.warmup)
+    torch.cuda.synchronize()
+    g.set_profiling(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lb = e = feas = None
+    for i in range(args.steps):
+        g.step(1)
+        if args.lb_every and (i + 1) % args.lb_every == 0:
+            lb = g.dual_bound()
+            e, feas = g.primal_energy()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    prof = g.get_profile()
+    sweeps = g.last_sweeps()
+    g.close()
+
+    dtype = "f64" if args.precision == "fp64" else "f32"
+    cand = {k: prof[k] for k in ("pair_projection", "momentum_projection")}
+    dom = max(cand, key=lambda k: cand[k][0])
+    ms_total, launches = prof[dom]
+    avg_s = ms_total / launches * 1e-3
+    achieved = flops_per_launch(dom, info) / avg_s / 1e12
+    peak = PEAK_TFLOPS[dtype]
+    roofline = {
+        "bound": "alu",
+        "kernel": dom,
+        "achieved": achieved,
+        "peak": peak,
+        "unit": "TFLOP/s",
+        "frac": achieved / peak,
+        "traffic": measured_traffic(dom, args.precision),
+        "avg_launch_ms": avg_s * 1e3,
+    }
+    out = {
+        "metric": METRIC,
+        "value": info["P"] * args.steps / dt,
+        "unit": "projections/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": dtype,
+        "data": "synthetic",
+        "config": {
+            "workload": f"TFI ring N={w.extent[0]} J=1 h={args.h}, 3-site clusters (M={info['M']}): "
+                        f"{info['P']} pair marginals {info['n']}x{info['n']}, {info['K_unique']} unique "
+                        f"{info['n_op']}x{info['n_op']} complex momentum blocks per step",
+            "precision": args.precision,
+            "lb_every": args.lb_every,
+        },
+        "roofline": roofline,
+        "kernels_avg_ms": {k: (v[0] / v[1] if v[1] else None) for k, v in prof.items()},
+        "max_sweeps_last_step": {"pair": sweeps[0], "momentum": sweeps[1]},
+        "final": {"lb_per_site": lb, "energy_per_site": e, "feas": feas},
+    }
+    if args.cpu_seconds > 0:
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

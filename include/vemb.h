@@ -153,6 +153,30 @@ int vemb_set_state(vemb_problem* p, const vemb_state* s);
  * sweep cap means some eigensolve stopped unconverged. */
 int vemb_last_sweeps(vemb_problem* p, int* pair_max, int* momentum_max);
 
+/* Kernel-level timing.  With profiling on, every kernel the problem launches is
+ * bracketed by HIP events recorded on the problem's stream; vemb_get_profile
+ * synchronises and returns the accumulated device milliseconds and launch counts
+ * per kernel since profiling was (re)enabled. */
+enum vemb_kernel_id {
+  VEMB_K_PAIR_UPDATE = 0,  /* steps 1-2 */
+  VEMB_K_PAIR_XSTEP = 1,   /* step 6, d != 0 */
+  VEMB_K_PAIR_PROJ = 2,    /* step 3 + Lambda update */
+  VEMB_K_CLUSTER = 3,      /* steps 4-5 + step 6, d = 0 */
+  VEMB_K_DFT_FWD = 4,      /* step 7 */
+  VEMB_K_MOM_PROJ = 5,     /* step 8 */
+  VEMB_K_DFT_INV = 6,      /* step 9 */
+  VEMB_K_BOUND_BUILD = 7,  /* bound matrices */
+  VEMB_K_LMIN = 8,         /* bound eigenvalues */
+  VEMB_K_COUNT = 9
+};
+typedef struct {
+  double ms[VEMB_K_COUNT];
+  int64_t launches[VEMB_K_COUNT];
+} vemb_profile;
+
+int vemb_set_profiling(vemb_problem* p, int enable);
+int vemb_get_profile(vemb_problem* p, vemb_profile* out);
+
 void vemb_destroy(vemb_problem* p);
 const char* vemb_last_error(void);
 

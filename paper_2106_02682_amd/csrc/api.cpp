@@ -34,6 +34,13 @@ struct vemb_problem {
   double *H0 = nullptr, *Hd = nullptr, *tw = nullptr, *wk = nullptr;
   int* hd_index = nullptr;
   OpTables* ops = nullptr;
+  // kernel timing (vemb_set_profiling)
+  bool profiling = false;
+  struct Mark { int id; hipEvent_t start, stop; };
+  std::vector<Mark> marks;
+  std::vector<hipEvent_t> free_events;
+  double prof_ms[VEMB_K_COUNT] = {};
+  int64_t prof_n[VEMB_K_COUNT] = {};
 };
 
 namespace {
@@ -83,6 +90,50 @@ int upload_initial_state(vemb_problem* p) {
   VEMB_TRY(hip_rc(hipMemsetAsync(p->a.Lam2, 0, (size_t)P * m * m * 8, s), "zero Lam2"));
   VEMB_TRY(hip_rc(hipStreamSynchronize(s), "initial upload"));
   p->t = 0;
+  return VEMB_OK;
+}
+
+hipEvent_t take_event(vemb_problem* p) {
+  if (!p->free_events.empty()) {
+    hipEvent_t e = p->free_events.back();
+    p->free_events.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Runs one launcher, bracketed by events when profiling is on.
+template <typename F>
+int timed(vemb_problem* p, int id, const char* what, F&& launch) {
+  hipEvent_t a = nullptr, b = nullptr;
+  if (p->profiling) {
+    a = take_event(p);
+    b = take_event(p);
+    if (a) hipEventRecord(a, p->stream);
+  }
+  int rc = hip_rc(launch(), what);
+  if (p->profiling && a && b) {
+    hipEventRecord(b, p->stream);
+    p->marks.push_back({id, a, b});
+  }
+  return rc;
+}
+
+int drain_marks(vemb_problem* p) {
+  if (p->marks.empty()) return VEMB_OK;
+  VEMB_TRY(hip_rc(hipStreamSynchronize(p->stream), "profile sync"));
+  for (auto& mk : p->marks) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, mk.start, mk.stop) == hipSuccess) {
+      p->prof_ms[mk.id] += ms;
+      p->prof_n[mk.id] += 1;
+    }
+    p->free_events.push_back(mk.start);
+    p->free_events.push_back(mk.stop);
+  }
+  p->marks.clear();
   return VEMB_OK;
 }
 
@@ -240,13 +291,17 @@ int vemb_step(vemb_problem* p, int iters) {
   hipStream_t s = p->stream;
   const int prec = p->opt.precision, ms = p->opt.max_sweeps;
   for (int it = 0; it < iters; ++it) {
-    VEMB_TRY(hip_rc(launch_pair_update(a, s), "pair update"));
-    VEMB_TRY(hip_rc(launch_pair_projection(a.rho, a.Lam, a.rho_t, a.feas, a.n, a.P, a.mu, prec, ms, a.sweeps, s),
-                    "pair projection"));
-    VEMB_TRY(hip_rc(launch_cluster_update(a, s), "cluster update"));
-    VEMB_TRY(hip_rc(launch_dft_forward(a, s), "forward DFT"));
-    VEMB_TRY(hip_rc(launch_momentum_projection(a.Xh, a.n_op, a.Ku, prec, ms, a.sweeps + a.P, s), "momentum projection"));
-    VEMB_TRY(hip_rc(launch_dft_inverse(a, s), "inverse DFT"));
+    VEMB_TRY(timed(p, VEMB_K_PAIR_UPDATE, "pair update", [&] { return launch_pair_update(a, s); }));
+    VEMB_TRY(timed(p, VEMB_K_PAIR_XSTEP, "pair X step", [&] { return launch_pair_xstep(a, s); }));
+    VEMB_TRY(timed(p, VEMB_K_PAIR_PROJ, "pair projection", [&] {
+      return launch_pair_projection(a.rho, a.Lam, a.rho_t, a.feas, a.n, a.P, a.mu, prec, ms, a.sweeps, s);
+    }));
+    VEMB_TRY(timed(p, VEMB_K_CLUSTER, "cluster update", [&] { return launch_cluster_update(a, s); }));
+    VEMB_TRY(timed(p, VEMB_K_DFT_FWD, "forward DFT", [&] { return launch_dft_forward(a, s); }));
+    VEMB_TRY(timed(p, VEMB_K_MOM_PROJ, "momentum projection", [&] {
+      return launch_momentum_projection(a.Xh, a.n_op, a.Ku, prec, ms, a.sweeps + a.P, s);
+    }));
+    VEMB_TRY(timed(p, VEMB_K_DFT_INV, "inverse DFT", [&] { return launch_dft_inverse(a, s); }));
     ++p->t;
   }
   return VEMB_OK;
@@ -277,10 +332,13 @@ int vemb_dual_bound(vemb_problem* p, double* lb) {
   const StepArgs& a = p->a;
   hipStream_t s = p->stream;
   const int P = p->P, n = a.n, m = a.m;
-  VEMB_TRY(hip_rc(launch_bound_build(a, s), "bound build"));
-  VEMB_TRY(hip_rc(launch_lambda_min(a.Kbuf, a.lmin, n, P, p->opt.max_sweeps, a.sweeps + P + a.Ku, s), "pair lambda_min"));
-  VEMB_TRY(hip_rc(launch_lambda_min(a.Kbuf + (size_t)P * n * n, a.lmin + P, m, 1, p->opt.max_sweeps, nullptr, s),
-                  "cluster lambda_min"));
+  VEMB_TRY(timed(p, VEMB_K_BOUND_BUILD, "bound build", [&] { return launch_bound_build(a, s); }));
+  VEMB_TRY(timed(p, VEMB_K_LMIN, "pair lambda_min", [&] {
+    return launch_lambda_min(a.Kbuf, a.lmin, n, P, p->opt.max_sweeps, a.sweeps + P + a.Ku, s);
+  }));
+  VEMB_TRY(timed(p, VEMB_K_LMIN, "cluster lambda_min", [&] {
+    return launch_lambda_min(a.Kbuf + (size_t)P * n * n, a.lmin + P, m, 1, p->opt.max_sweeps, nullptr, s);
+  }));
   std::vector<double> lm(P + 1);
   VEMB_TRY(hip_rc(hipMemcpyAsync(lm.data(), a.lmin, (P + 1) * 8, hipMemcpyDeviceToHost, s), "copy lambda_min"));
   VEMB_TRY(hip_rc(hipStreamSynchronize(s), "dual bound sync"));
@@ -356,10 +414,36 @@ int vemb_last_sweeps(vemb_problem* p, int* pair_max, int* momentum_max) {
   return VEMB_OK;
 }
 
+int vemb_set_profiling(vemb_problem* p, int enable) {
+  if (!p) return fail(VEMB_E_INVALID, "NULL problem");
+  VEMB_TRY(drain_marks(p));
+  for (int k = 0; k < VEMB_K_COUNT; ++k) {
+    p->prof_ms[k] = 0.0;
+    p->prof_n[k] = 0;
+  }
+  p->profiling = enable != 0;
+  return VEMB_OK;
+}
+
+int vemb_get_profile(vemb_problem* p, vemb_profile* out) {
+  if (!p || !out) return fail(VEMB_E_INVALID, "NULL argument");
+  VEMB_TRY(drain_marks(p));
+  for (int k = 0; k < VEMB_K_COUNT; ++k) {
+    out->ms[k] = p->prof_ms[k];
+    out->launches[k] = p->prof_n[k];
+  }
+  return VEMB_OK;
+}
+
 void vemb_destroy(vemb_problem* p) {
   if (!p) return;
   if (p->stream) hipStreamSynchronize(p->stream);
   else hipDeviceSynchronize();
+  for (auto& mk : p->marks) {
+    hipEventDestroy(mk.start);
+    hipEventDestroy(mk.stop);
+  }
+  for (hipEvent_t e : p->free_events) hipEventDestroy(e);
   for (void* ptr : p->allocations) hipFree(ptr);
   delete p;
 }

@@ -64,6 +64,7 @@ struct StepArgs {
 };
 
 hipError_t launch_pair_update(const StepArgs& a, hipStream_t st);
+hipError_t launch_pair_xstep(const StepArgs& a, hipStream_t st);
 hipError_t launch_cluster_update(const StepArgs& a, hipStream_t st);
 hipError_t launch_dft_forward(const StepArgs& a, hipStream_t st);
 hipError_t launch_dft_inverse(const StepArgs& a, hipStream_t st);

@@ -351,8 +351,10 @@ __global__ void __launch_bounds__(kBlock) bound_cluster_kernel(StepArgs A) {
 
 hipError_t launch_pair_update(const StepArgs& a, hipStream_t st) {
   hipLaunchKernelGGL(pair_update_kernel, dim3(a.P), dim3(kBlock), 0, st, a);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  return hipGetLastError();
+}
+
+hipError_t launch_pair_xstep(const StepArgs& a, hipStream_t st) {
   const int E = a.n_op * a.n_op;
   hipLaunchKernelGGL(pair_xstep_kernel, dim3((E + kBlock - 1) / kBlock, a.P), dim3(kBlock), 0, st, a);
   return hipGetLastError();

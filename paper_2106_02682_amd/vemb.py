@@ -27,8 +27,10 @@ EXPORTS = [
     "vemb_default_options", "vemb_create_problem", "vemb_problem_info", "vemb_step", "vemb_dual_bound",
     "vemb_primal_energy", "vemb_marginals", "vemb_get_state", "vemb_set_state", "vemb_destroy",
     "vemb_last_error", "vemb_psd_project_batched", "vemb_eigvalsh_batched", "vemb_last_sweeps",
-    "vemb_psd_project_batched_ex",
+    "vemb_psd_project_batched_ex", "vemb_set_profiling", "vemb_get_profile",
 ]
+KERNELS = ["pair_update", "pair_xstep", "pair_projection", "cluster_update", "dft_forward", "momentum_projection",
+           "dft_inverse", "bound_build", "lambda_min"]
 
 
 class VembError(RuntimeError):
@@ -69,6 +71,10 @@ class vemb_info(ctypes.Structure):
 _DP = ctypes.POINTER(ctypes.c_double)
 
 
+class vemb_profile(ctypes.Structure):
+    _fields_ = [("ms", ctypes.c_double * 9), ("launches", ctypes.c_int64 * 9)]
+
+
 class vemb_state(ctypes.Structure):
     _fields_ = [("t", ctypes.c_int64), ("X", _DP), ("rho0", _DP), ("rho", _DP), ("rho_t", _DP), ("Lam", _DP),
                 ("Lam1", _DP), ("Lam2", _DP)]
@@ -104,6 +110,8 @@ def lib():
     L.vemb_last_error.restype = ctypes.c_char_p
     L.vemb_psd_project_batched.argtypes = [vp, vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp]
     L.vemb_eigvalsh_batched.argtypes = [vp, vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp]
+    L.vemb_set_profiling.argtypes = [vp, ctypes.c_int]
+    L.vemb_get_profile.argtypes = [vp, ctypes.POINTER(vemb_profile)]
     L.vemb_last_sweeps.argtypes = [vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
     L.vemb_psd_project_batched_ex.argtypes = [vp, vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                               ctypes.c_int, vp, vp]
@@ -247,6 +255,17 @@ def psd_project_batched_ex(inp, out, is_complex=False, precision="fp64", max_swe
                                              batch, int(is_complex), PRECISION[precision], int(max_sweeps), sp, st))
 
 
+def set_profiling(h, enable=True):
+    _check(lib().vemb_set_profiling(h, int(bool(enable))))
+
+
+def get_profile(h):
+    """{kernel: (total device ms, launches)} since profiling was enabled."""
+    pr = vemb_profile()
+    _check(lib().vemb_get_profile(h, ctypes.byref(pr)))
+    return {k: (pr.ms[i], pr.launches[i]) for i, k in enumerate(KERNELS)}
+
+
 def last_sweeps(h):
     a, b = ctypes.c_int(), ctypes.c_int()
     _check(lib().vemb_last_sweeps(h, ctypes.byref(a), ctypes.byref(b)))
@@ -284,6 +303,12 @@ class Problem:
 
     def last_sweeps(self):
         return last_sweeps(self.h)
+
+    def set_profiling(self, enable=True):
+        set_profiling(self.h, enable)
+
+    def get_profile(self):
+        return get_profile(self.h)
 
     def primal_energy(self):
         return primal_energy(self.h)
