@@ -86,6 +86,9 @@ typedef struct {
   int32_t precision;   /* vemb_precision: FP64, or FP32 eigensolves with FP64 refinement */
   int32_t max_sweeps;  /* Jacobi sweep cap per eigensolve (0 = default 40) */
   int32_t sign;        /* -1: X <- Pi(X - eps G) (default when 0); +1: the printed + sign */
+  int32_t warm_refresh; /* eigensolves start from the previous iteration's eigenvectors; every
+                           warm_refresh-th iteration (t % warm_refresh == 0) starts cold.
+                           0 = default 64; negative = always cold. */
 } vemb_options;
 
 typedef struct vemb_problem vemb_problem;
@@ -132,7 +135,11 @@ int vemb_marginals(vemb_problem* p, int which, double* rho0, double* rho_pairs);
 /* Full iteration state, host buffers owned by the caller, sizes from vemb_info:
  * X: M*n_op*n_op (first block row X_0d, d = 0..M-1), rho0: m*m, rho: P*n*n,
  * rho_t: P*n*n, Lam: P*n*n, Lam1: P*m*m, Lam2: P*m*m.  It is the checkpoint
- * format and the warm-start input. */
+ * format and the warm-start input.  Optional (may be NULL): the eigenvectors
+ * the eigensolves keep between iterations, Vpair: P*n*n and Vmom:
+ * K_unique*n_op*n_op*2 (complex, interleaved), column-major per matrix.
+ * Restoring them makes a resumed FP64 run bit-identical to an uninterrupted
+ * one; without them the next iteration solves cold (same result up to rounding). */
 typedef struct {
   int64_t t;
   double* X;
@@ -142,6 +149,8 @@ typedef struct {
   double* Lam;
   double* Lam1;
   double* Lam2;
+  double* Vpair;
+  double* Vmom;
 } vemb_state;
 
 int vemb_get_state(vemb_problem* p, vemb_state* s);

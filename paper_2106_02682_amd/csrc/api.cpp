@@ -40,6 +40,7 @@ struct vemb_problem {
   std::vector<Mark> marks;
   std::vector<hipEvent_t> free_events;
   double prof_ms[VEMB_K_COUNT] = {};
+  bool v_valid = false;  // Vpair / Vmom hold eigenvectors of the previous iteration
   int64_t prof_n[VEMB_K_COUNT] = {};
 };
 
@@ -159,6 +160,7 @@ void vemb_default_options(vemb_options* o) {
   o->precision = VEMB_FP64;
   o->max_sweeps = 40;
   o->sign = -1;
+  o->warm_refresh = 64;
 }
 
 int vemb_create_problem(const vemb_hamiltonian* H, const vemb_lattice* lat, const vemb_clusters* cl,
@@ -170,6 +172,7 @@ int vemb_create_problem(const vemb_hamiltonian* H, const vemb_lattice* lat, cons
   if (opts) o = *opts;
   if (o.max_sweeps <= 0) o.max_sweeps = 40;
   if (o.sign == 0) o.sign = -1;
+  if (o.warm_refresh == 0) o.warm_refresh = 64;
   if (!(o.mu > 0 && o.nu > 0 && o.eps > 0)) return fail(VEMB_E_INVALID, "mu, nu, eps must be positive");
   if (o.opset != VEMB_OPSET_COMPLETE && o.opset != VEMB_OPSET_PAULI1) return fail(VEMB_E_INVALID, "unknown opset");
   if (o.precision != VEMB_FP64 && o.precision != VEMB_MIXED) return fail(VEMB_E_INVALID, "unknown precision");
@@ -245,7 +248,8 @@ int vemb_create_problem(const vemb_hamiltonian* H, const vemb_lattice* lat, cons
       (rc = dalloc(p, &a.tr1, (size_t)P * m * m)) || (rc = dalloc(p, &a.e_pair, (size_t)P)) ||
       (rc = dalloc(p, &a.feas, (size_t)P)) || (rc = dalloc(p, &a.scal, 4)) ||
       (rc = dalloc(p, &a.Kbuf, (size_t)P * n * n + (size_t)m * m)) || (rc = dalloc(p, &a.lmin, (size_t)P + 1)) ||
-      (rc = dalloc(p, &a.sweeps, (size_t)(2 * P + Ku + 1))))
+      (rc = dalloc(p, &a.sweeps, (size_t)(2 * P + Ku + 1))) ||
+      (rc = dalloc(p, &a.Vpair, (size_t)P * n * n)) || (rc = dalloc(p, &a.Vmom, (size_t)2 * Ku * k * k)))
     return cleanup(rc);
   hipStream_t s = p->stream;
   if ((rc = hip_rc(hipMemcpyAsync(p->H0, p->host.H0.data(), (size_t)m * m * 8, hipMemcpyHostToDevice, s), "upload H0")) ||
@@ -291,17 +295,21 @@ int vemb_step(vemb_problem* p, int iters) {
   hipStream_t s = p->stream;
   const int prec = p->opt.precision, ms = p->opt.max_sweeps;
   for (int it = 0; it < iters; ++it) {
+    const int refresh = p->opt.warm_refresh;
+    const int cold = (!p->v_valid || refresh < 0 || p->t % refresh == 0) ? 1 : 0;
     VEMB_TRY(timed(p, VEMB_K_PAIR_UPDATE, "pair update", [&] { return launch_pair_update(a, s); }));
     VEMB_TRY(timed(p, VEMB_K_PAIR_XSTEP, "pair X step", [&] { return launch_pair_xstep(a, s); }));
     VEMB_TRY(timed(p, VEMB_K_PAIR_PROJ, "pair projection", [&] {
-      return launch_pair_projection(a.rho, a.Lam, a.rho_t, a.feas, a.n, a.P, a.mu, prec, ms, a.sweeps, s);
+      return launch_pair_projection(a.rho, a.Lam, a.rho_t, a.feas, a.n, a.P, a.mu, prec, ms, a.sweeps, a.Vpair, cold,
+                                    s);
     }));
     VEMB_TRY(timed(p, VEMB_K_CLUSTER, "cluster update", [&] { return launch_cluster_update(a, s); }));
     VEMB_TRY(timed(p, VEMB_K_DFT_FWD, "forward DFT", [&] { return launch_dft_forward(a, s); }));
     VEMB_TRY(timed(p, VEMB_K_MOM_PROJ, "momentum projection", [&] {
-      return launch_momentum_projection(a.Xh, a.n_op, a.Ku, prec, ms, a.sweeps + a.P, s);
+      return launch_momentum_projection(a.Xh, a.n_op, a.Ku, prec, ms, a.sweeps + a.P, a.Vmom, cold, s);
     }));
     VEMB_TRY(timed(p, VEMB_K_DFT_INV, "inverse DFT", [&] { return launch_dft_inverse(a, s); }));
+    p->v_valid = true;
     ++p->t;
   }
   return VEMB_OK;
@@ -369,9 +377,12 @@ int vemb_get_state(vemb_problem* p, vemb_state* st) {
   const size_t m2 = (size_t)p->g.m * p->g.m, n2 = (size_t)p->g.n * p->g.n, P = p->P;
   const size_t xk = (size_t)p->g.M * p->n_op * p->n_op;
   struct Item { double* host; const double* dev; size_t count; };
+  const size_t vm = (size_t)2 * p->Ku * p->n_op * p->n_op;
   Item items[] = {{st->X, p->a.X, xk},           {st->rho0, p->a.rho0, m2},  {st->rho, p->a.rho, P * n2},
                   {st->rho_t, p->a.rho_t, P * n2}, {st->Lam, p->a.Lam, P * n2}, {st->Lam1, p->a.Lam1, P * m2},
-                  {st->Lam2, p->a.Lam2, P * m2}};
+                  {st->Lam2, p->a.Lam2, P * m2},   {st->Vpair, p->a.Vpair, P * n2}, {st->Vmom, p->a.Vmom, vm}};
+  if ((st->Vpair || st->Vmom) && !p->v_valid)
+    return fail(VEMB_E_INVALID, "get_state: no eigenvectors kept yet (run an iteration first)");
   for (const Item& it : items)
     if (it.host)
       VEMB_TRY(hip_rc(hipMemcpyAsync(it.host, it.dev, it.count * 8, hipMemcpyDeviceToHost, s), "get_state copy"));
@@ -392,10 +403,19 @@ int vemb_set_state(vemb_problem* p, const vemb_state* st) {
     if (!it.host) return fail(VEMB_E_INVALID, "set_state needs every array");
     if (!all_finite(it.host, it.count)) return fail(VEMB_E_NUMERIC, "set_state: non-finite entries");
   }
+  const size_t vm = (size_t)2 * p->Ku * p->n_op * p->n_op;
+  const bool with_v = st->Vpair && st->Vmom;
+  if (with_v && (!all_finite(st->Vpair, P * n2) || !all_finite(st->Vmom, vm)))
+    return fail(VEMB_E_NUMERIC, "set_state: non-finite eigenvectors");
   hipStream_t s = p->stream;
   for (const Item& it : items)
     VEMB_TRY(hip_rc(hipMemcpyAsync(it.dev, it.host, it.count * 8, hipMemcpyHostToDevice, s), "set_state copy"));
+  if (with_v) {
+    VEMB_TRY(hip_rc(hipMemcpyAsync(p->a.Vpair, st->Vpair, P * n2 * 8, hipMemcpyHostToDevice, s), "set_state V"));
+    VEMB_TRY(hip_rc(hipMemcpyAsync(p->a.Vmom, st->Vmom, vm * 8, hipMemcpyHostToDevice, s), "set_state V"));
+  }
   VEMB_TRY(hip_rc(hipStreamSynchronize(s), "set_state sync"));
+  p->v_valid = with_v;
   p->t = st->t;
   return VEMB_OK;
 }

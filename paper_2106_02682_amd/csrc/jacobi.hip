@@ -82,6 +82,25 @@ template <typename S> __device__ inline S drop_imag(S a) { return a; }
 template <> __device__ inline cplx<double> drop_imag<cplx<double>>(cplx<double> a) { return {a.re, 0.0}; }
 template <> __device__ inline cplx<float> drop_imag<cplx<float>>(cplx<float> a) { return {a.re, 0.0f}; }
 
+template <typename S> struct wide { using type = double; };
+template <> struct wide<float> { using type = double; };
+template <> struct wide<cplx<double>> { using type = cplx<double>; };
+template <> struct wide<cplx<float>> { using type = cplx<double>; };
+
+template <typename S> __device__ inline S narrow(typename wide<S>::type v);
+template <> __device__ inline double narrow<double>(double v) { return v; }
+template <> __device__ inline float narrow<float>(double v) { return (float)v; }
+template <> __device__ inline cplx<double> narrow<cplx<double>>(cplx<double> v) { return v; }
+template <> __device__ inline cplx<float> narrow<cplx<float>>(cplx<double> v) { return {(float)v.re, (float)v.im}; }
+__device__ inline double widen(double v) { return v; }
+__device__ inline double widen(float v) { return (double)v; }
+__device__ inline cplx<double> widen(cplx<double> v) { return v; }
+__device__ inline cplx<double> widen(cplx<float> v) { return {(double)v.re, (double)v.im}; }
+
+template <typename S> __device__ inline S one_of() { return S(1); }
+template <> __device__ inline cplx<double> one_of<cplx<double>>() { return {1.0, 0.0}; }
+template <> __device__ inline cplx<float> one_of<cplx<float>>() { return {1.0f, 0.0f}; }
+
 // Block-wide reductions through LDS (kThreads threads).
 template <typename R>
 __device__ R block_max(R v, R* red) {
@@ -142,15 +161,19 @@ enum Mode { kProject = 0, kEigvals = 1 };
 // Core kernel.  S: compute scalar (double, float, cplx<double>, cplx<float>);
 // NMAX: capacity (n <= NMAX, NMAX even); Policy: load / store of one matrix.
 // ---------------------------------------------------------------------------
-template <typename S, int NMAX, int MODE, typename Policy>
-__global__ void __launch_bounds__(kThreads) jacobi_kernel(Policy pol, int n, int max_sweeps) {
+template <typename S, int NMAX, int MODE, bool WARM, typename Policy>
+__global__ void __launch_bounds__(kThreads) jacobi_kernel(Policy pol, int n, int max_sweeps, void* vstore_raw,
+                                                          int cold) {
   using R = typename scalar_traits<S>::real;
+  using D = typename wide<S>::type;  // FP64 storage type of V
   constexpr int LD = NMAX + 1;
   constexpr int NPAIR = NMAX / 2;
   constexpr int G0 = kThreads / NPAIR;
   constexpr int G = G0 > 64 ? 64 : G0;  // lanes per pair, within one wavefront
   constexpr int RPL = (NMAX + G - 1) / G;  // rows per lane
   __shared__ S W[NMAX * LD];
+  __shared__ S V[WARM ? NMAX * LD : 1];
+  D* vstore = static_cast<D*>(vstore_raw);
   __shared__ R red[kThreads];
   __shared__ double red_d[kThreads];
   __shared__ R colf[NMAX];
@@ -196,6 +219,41 @@ __global__ void __launch_bounds__(kThreads) jacobi_kernel(Policy pol, int n, int
   }
   for (int i = tid; i < n; i += kThreads) W[i * LD + i] = add_real(W[i * LD + i], shift);
   __syncthreads();
+  // Warm start: W = B V_prev, where V_prev holds the eigenvectors of the previous
+  // solve of this matrix slot.  B V_prev is nearly column-orthogonal when the
+  // matrix moved little, so few sweeps remain.  V accumulates the rotations.
+  if constexpr (WARM) {
+    const D* vin = vstore + (size_t)mat * n * n;  // column-major: V(i, j) at [j*n + i]
+    if (cold) {
+      for (int idx = tid; idx < nn; idx += kThreads) {
+        const int j = idx / n, i = idx - (idx / n) * n;
+        V[j * LD + i] = (i == j) ? one_of<S>() : s_zero<S>();
+      }
+    } else {
+      for (int idx = tid; idx < nn; idx += kThreads) {
+        const int j = idx / n, i = idx - (idx / n) * n;
+        V[j * LD + i] = narrow<S>(vin[idx]);
+      }
+      __syncthreads();
+      constexpr int NOUT = (NMAX * NMAX + kThreads - 1) / kThreads;
+      S outv[NOUT];
+      int c = 0;
+      for (int idx = tid; idx < nn; idx += kThreads, ++c) {
+        const int j = idx / n, i = idx - (idx / n) * n;
+        S acc = s_zero<S>();
+        for (int k = 0; k < n; ++k) acc = acc + W[k * LD + i] * V[j * LD + k];
+        outv[c] = acc;
+      }
+      __syncthreads();
+      c = 0;
+      for (int idx = tid; idx < nn; idx += kThreads, ++c) {
+        const int j = idx / n, i = idx - (idx / n) * n;
+        W[j * LD + i] = outv[c];
+      }
+    }
+    __syncthreads();
+  }
+
   // Columns whose squared norm falls below (eta ||B||_F)^2, eta = max(n,16) eps, hold only
   // rounding noise: they are left unrotated.  Rotating them never converges (the noise
   // is re-created parallel to the partner column) and their weight in Pi is below
@@ -268,6 +326,12 @@ __global__ void __launch_bounds__(kThreads) jacobi_kernel(Policy pol, int n, int
             const S bq = mul_phase(ph, b[r]);
             W[p * LD + i] = scale_by(c, a[r]) - scale_by(s, bq);
             W[q * LD + i] = scale_by(s, a[r]) + scale_by(c, bq);
+            if constexpr (WARM) {
+              const S va = V[p * LD + i];
+              const S vb = mul_phase(ph, V[q * LD + i]);
+              V[p * LD + i] = scale_by(c, va) - scale_by(s, vb);
+              V[q * LD + i] = scale_by(s, va) + scale_by(c, vb);
+            }
           }
         }
         if (l == 0) rotated = 1;
@@ -330,6 +394,13 @@ __global__ void __launch_bounds__(kThreads) jacobi_kernel(Policy pol, int n, int
     }
     const double tot = block_sum(part, red_d);
     if (tid == 0) pol.finish(mat, tot);
+    if constexpr (WARM) {
+      D* vout = vstore + (size_t)mat * n * n;
+      for (int idx = tid; idx < nn; idx += kThreads) {
+        const int j = idx / n, i = idx - (idx / n) * n;
+        vout[idx] = widen(V[j * LD + i]);
+      }
+    }
   }
 }
 
@@ -431,45 +502,55 @@ struct ArrayPolicy {
   }
 };
 
+// vstore == nullptr: cold solve without eigenvector storage.  Otherwise the
+// eigenvectors of every matrix slot are read (unless cold) and written back.
 template <typename S, int MODE, typename Policy>
-hipError_t dispatch(const Policy& pol, int n, int count, int max_sweeps, hipStream_t st) {
+hipError_t dispatch(const Policy& pol, int n, int count, int max_sweeps, hipStream_t st, void* vstore = nullptr,
+                    int cold = 1) {
   if (count <= 0) return hipSuccess;
   const int np = (n + 1) & ~1;
   dim3 grid(count), block(kThreads);
-#define VEMB_CASE(NM)                                                                             \
-  if (np <= NM) {                                                                                 \
-    hipLaunchKernelGGL((jacobi_kernel<S, NM, MODE, Policy>), grid, block, 0, st, pol, n, max_sweeps); \
-    return hipGetLastError();                                                                     \
+#define VEMB_CASE(NM)                                                                                     \
+  if (np <= NM) {                                                                                         \
+    if (vstore)                                                                                           \
+      hipLaunchKernelGGL((jacobi_kernel<S, NM, MODE, true, Policy>), grid, block, 0, st, pol, n, max_sweeps, \
+                         vstore, cold);                                                                   \
+    else                                                                                                  \
+      hipLaunchKernelGGL((jacobi_kernel<S, NM, MODE, false, Policy>), grid, block, 0, st, pol, n,         \
+                         max_sweeps, nullptr, 1);                                                         \
+    return hipGetLastError();                                                                             \
   }
   VEMB_CASE(4)
   VEMB_CASE(8)
   VEMB_CASE(16)
   VEMB_CASE(32)
   VEMB_CASE(64)
-  if constexpr (!scalar_traits<S>::is_complex && sizeof(S) == 8) {
-    VEMB_CASE(128)
-  }
-  if constexpr (!scalar_traits<S>::is_complex && sizeof(S) == 4) {
-    VEMB_CASE(128)
-  }
 #undef VEMB_CASE
+  if constexpr (!scalar_traits<S>::is_complex) {
+    if (np <= 128 && !vstore) {
+      hipLaunchKernelGGL((jacobi_kernel<S, 128, MODE, false, Policy>), grid, block, 0, st, pol, n, max_sweeps,
+                         nullptr, 1);
+      return hipGetLastError();
+    }
+  }
   return hipErrorInvalidValue;
 }
 
 }  // namespace
 
 hipError_t launch_pair_projection(const double* rho, double* Lam, double* rho_t, double* feas, int n, int P,
-                                  double mu, int precision, int max_sweeps, int* sweeps, hipStream_t st) {
+                                  double mu, int precision, int max_sweeps, int* sweeps, double* vstore, int cold,
+                                  hipStream_t st) {
   PairPolicy pol{rho, Lam, rho_t, feas, sweeps, n, mu};
-  if (precision == VEMB_MIXED) return dispatch<float, kProject>(pol, n, P, max_sweeps, st);
-  return dispatch<double, kProject>(pol, n, P, max_sweeps, st);
+  if (precision == VEMB_MIXED) return dispatch<float, kProject>(pol, n, P, max_sweeps, st, vstore, cold);
+  return dispatch<double, kProject>(pol, n, P, max_sweeps, st, vstore, cold);
 }
 
 hipError_t launch_momentum_projection(double* Xh, int n_op, int K, int precision, int max_sweeps, int* sweeps,
-                                      hipStream_t st) {
+                                      double* vstore, int cold, hipStream_t st) {
   MomentumPolicy pol{Xh, sweeps, n_op};
-  if (precision == VEMB_MIXED) return dispatch<cplx<float>, kProject>(pol, n_op, K, max_sweeps, st);
-  return dispatch<cplx<double>, kProject>(pol, n_op, K, max_sweeps, st);
+  if (precision == VEMB_MIXED) return dispatch<cplx<float>, kProject>(pol, n_op, K, max_sweeps, st, vstore, cold);
+  return dispatch<cplx<double>, kProject>(pol, n_op, K, max_sweeps, st, vstore, cold);
 }
 
 hipError_t launch_psd_batched(const double* in, double* out, int n, int batch, bool is_complex, int precision,

@@ -10,13 +10,16 @@ namespace vemb {
 
 // Pair step 3 + Lambda update: C = rho - Lam/mu; rho_t = Pi(C); Lam += mu (rho_t - rho);
 // feas[d] = ||rho_d - rho_t_d||_F^2.  P matrices of size n.
+// vstore (P x n x n doubles, column-major per matrix) keeps each pair's eigenvectors for
+// the warm start of the next iteration; cold = 1 ignores its content.
 hipError_t launch_pair_projection(const double* rho, double* Lam, double* rho_t, double* feas, int n, int P,
-                                  double mu, int precision, int max_sweeps, int* sweeps, hipStream_t st);
+                                  double mu, int precision, int max_sweeps, int* sweeps, double* vstore, int cold,
+                                  hipStream_t st);
 
 // Steps 8: Y_k = Pi((Xh_k + Xh_k^H)/2), in place on K complex n_op x n_op blocks
 // (interleaved re/im doubles).
 hipError_t launch_momentum_projection(double* Xh, int n_op, int K, int precision, int max_sweeps, int* sweeps,
-                                      hipStream_t st);
+                                      double* vstore, int cold, hipStream_t st);
 
 // Isolated batched projection / eigenvalues (ABI entry points).
 hipError_t launch_psd_batched(const double* in, double* out, int n, int batch, bool is_complex, int precision,
@@ -61,6 +64,8 @@ struct StepArgs {
   double* Kbuf;     // P x n x n scratch for the bound, and m x m (K_0) after it
   double* lmin;     // P + 1
   int* sweeps;      // per-matrix sweep counters (P + Ku + P + 1)
+  double* Vpair;    // P x n x n eigenvectors of the pair projections (warm start)
+  double* Vmom;     // Ku x n_op x n_op complex eigenvectors of the momentum projections
 };
 
 hipError_t launch_pair_update(const StepArgs& a, hipStream_t st);

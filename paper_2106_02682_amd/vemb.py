@@ -59,7 +59,7 @@ class vemb_clusters(ctypes.Structure):
 class vemb_options(ctypes.Structure):
     _fields_ = [("mu", ctypes.c_double), ("nu", ctypes.c_double), ("eps", ctypes.c_double),
                 ("opset", ctypes.c_int32), ("precision", ctypes.c_int32), ("max_sweeps", ctypes.c_int32),
-                ("sign", ctypes.c_int32)]
+                ("sign", ctypes.c_int32), ("warm_refresh", ctypes.c_int32)]
 
 
 class vemb_info(ctypes.Structure):
@@ -77,7 +77,7 @@ class vemb_profile(ctypes.Structure):
 
 class vemb_state(ctypes.Structure):
     _fields_ = [("t", ctypes.c_int64), ("X", _DP), ("rho0", _DP), ("rho", _DP), ("rho_t", _DP), ("Lam", _DP),
-                ("Lam1", _DP), ("Lam2", _DP)]
+                ("Lam1", _DP), ("Lam2", _DP), ("Vpair", _DP), ("Vmom", _DP)]
 
 
 _lib = None
@@ -151,7 +151,7 @@ def default_options():
 
 
 def create_problem(terms, extent, cluster, opset="complete", precision="fp64", mu=10.0, nu=10.0, eps=2.0,
-                   max_sweeps=40, sign=-1, stream=None):
+                   max_sweeps=40, sign=-1, warm_refresh=64, stream=None):
     """Terms in the ``synth`` format: (coeff, ((pauli, (ox, oy)), ...))."""
     arr = (vemb_term * max(1, len(terms)))()
     for t, (coeff, factors) in enumerate(terms):
@@ -171,6 +171,7 @@ def create_problem(terms, extent, cluster, opset="complete", precision="fp64", m
     o.precision = PRECISION[precision]
     o.max_sweeps = max_sweeps
     o.sign = sign
+    o.warm_refresh = warm_refresh
     h = ctypes.c_void_p()
     st = stream if stream is not None else current_stream()
     _check(lib().vemb_create_problem(ctypes.byref(H), ctypes.byref(lat), ctypes.byref(cl), ctypes.byref(o), st,
@@ -215,19 +216,30 @@ def _state_arrays(info):
             "Lam2": np.zeros((P, m, m))}
 
 
-def get_state(h):
+_STATE_KEYS = ("X", "rho0", "rho", "rho_t", "Lam", "Lam1", "Lam2")
+
+
+def get_state(h, with_eigvecs=False):
+    """State arrays; with_eigvecs adds the kept eigenvectors (Vpair, Vmom) for bit-exact resume."""
     info = problem_info(h)
     arrs = _state_arrays(info)
-    st = vemb_state(0, *[_ptr(arrs[k]) for k in ("X", "rho0", "rho", "rho_t", "Lam", "Lam1", "Lam2")])
+    if with_eigvecs:
+        arrs["Vpair"] = np.zeros((info["P"], info["n"], info["n"]))
+        arrs["Vmom"] = np.zeros((info["K_unique"], info["n_op"], info["n_op"], 2))
+    ptrs = [_ptr(arrs[k]) for k in _STATE_KEYS] + [_ptr(arrs.get("Vpair")), _ptr(arrs.get("Vmom"))]
+    st = vemb_state(0, *ptrs)
     _check(lib().vemb_get_state(h, ctypes.byref(st)))
     arrs["t"] = st.t
     return arrs
 
 
 def set_state(h, state):
-    keys = ("X", "rho0", "rho", "rho_t", "Lam", "Lam1", "Lam2")
-    arrs = {k: np.ascontiguousarray(state[k], dtype=np.float64) for k in keys}
-    st = vemb_state(int(state.get("t", 0)), *[_ptr(arrs[k]) for k in keys])
+    arrs = {k: np.ascontiguousarray(state[k], dtype=np.float64) for k in _STATE_KEYS}
+    for k in ("Vpair", "Vmom"):
+        if state.get(k) is not None:
+            arrs[k] = np.ascontiguousarray(state[k], dtype=np.float64)
+    ptrs = [_ptr(arrs[k]) for k in _STATE_KEYS] + [_ptr(arrs.get("Vpair")), _ptr(arrs.get("Vmom"))]
+    st = vemb_state(int(state.get("t", 0)), *ptrs)
     _check(lib().vemb_set_state(h, ctypes.byref(st)))
 
 
@@ -316,8 +328,8 @@ class Problem:
     def marginals(self, which=RHO):
         return marginals(self.h, which)
 
-    def get_state(self):
-        return get_state(self.h)
+    def get_state(self, with_eigvecs=False):
+        return get_state(self.h, with_eigvecs)
 
     def set_state(self, s):
         set_state(self.h, s)

@@ -196,21 +196,41 @@ def test_bench_workload_parity(vemb):
     _compare(w, 5, rel_lb=1e-10, atol_state=1e-9)
 
 
-def test_state_roundtrip_and_resume(vemb):
-    """get_state / set_state round trip; resuming gives the same iterates as running through."""
-    w = synth.tfi_ring(8, 2, 1.0)
+@pytest.mark.parametrize("w", [synth.tfi_ring(8, 2, 1.0), synth.config_c2(0.5)[1]], ids=lambda w: w.name)
+def test_state_roundtrip_and_resume(vemb, w):
+    """Resuming from a checkpoint that includes the kept eigenvectors is bit-identical to running through;
+    without them the resumed run starts its eigensolves cold and agrees to rounding."""
     from paper_2106_02682_amd import vemb as v
 
-    with v.Problem.from_workload(w) as a, v.Problem.from_workload(w) as b:
+    with v.Problem.from_workload(w) as a, v.Problem.from_workload(w) as b, v.Problem.from_workload(w) as c:
         a.step(30)
-        mid = a.get_state()
+        mid = a.get_state(with_eigvecs=True)
         a.step(20)
         b.set_state(mid)
         b.step(20)
-        sa, sb = a.get_state(), b.get_state()
+        c.set_state({k: mid[k] for k in mid if k not in ("Vpair", "Vmom")})
+        c.step(20)
+        sa, sb, sc = a.get_state(), b.get_state(), c.get_state()
     for k in ("X", "rho0", "rho_t", "Lam", "Lam1", "Lam2"):
         assert np.array_equal(sa[k], sb[k]), k
+        assert np.abs(sa[k] - sc[k]).max() < 1e-11, k
     assert sb["t"] == 50
+
+
+@pytest.mark.parametrize("w", [synth.tfi_ring(8, 2, 1.0), synth.afh_torus(4, 4, 1, 1), synth.config_c2(1.5)[1]],
+                         ids=lambda w: w.name)
+def test_warm_started_eigensolves_match_cold(vemb, w):
+    """Eigensolves started from the previous eigenvectors give the same iterates as cold solves."""
+    from paper_2106_02682_amd import vemb as v
+
+    with v.Problem.from_workload(w) as a, v.Problem.from_workload(w, warm_refresh=-1) as b:
+        for _ in range(40):
+            a.step(1)
+            b.step(1)
+        sa, sb = a.get_state(), b.get_state()
+        assert max(a.last_sweeps()) <= max(b.last_sweeps())
+    for k in ("X", "rho0", "rho_t", "Lam", "Lam1", "Lam2"):
+        assert np.abs(sa[k] - sb[k]).max() < 1e-11 * max(1.0, np.abs(sb[k]).max()), k
 
 
 def test_set_state_rejects_nonfinite(vemb):
