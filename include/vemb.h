@@ -194,7 +194,9 @@ const char* vemb_last_error(void);
  * (is_complex = 0; n*n doubles each) or Hermitian (is_complex = 1; n*n
  * interleaved re/im double pairs each) matrices.  `in` and `out` are DEVICE
  * pointers (they may alias).  precision: VEMB_FP64 or VEMB_MIXED.
- * Asynchronous on hip_stream.  n <= 128 real, n <= 64 complex. */
+ * Asynchronous on hip_stream for n <= 128 real / n <= 64 complex (matrix held in
+ * LDS); larger n (<= 256, multiple of 16) use the streamed solver with scratch
+ * allocated for the call, and the call synchronises the stream. */
 int vemb_psd_project_batched(const double* in, double* out, int n, int batch, int is_complex, int precision,
                              void* hip_stream);
 

@@ -196,9 +196,8 @@ int vemb_create_problem(const vemb_hamiltonian* H, const vemb_lattice* lat, cons
   g.m = 1 << g.L;
   g.n = g.m * g.m;
   const int n_op = o.opset == VEMB_OPSET_COMPLETE ? g.n : 3 * g.L;
-  // eigensolver capacity: pair blocks n x n (real), momentum blocks n_op x n_op (complex)
-  if (g.n > 128) return fail(VEMB_E_UNSUPPORTED, "pair marginals above 128 x 128 are not supported yet");
-  if (n_op > 64) return fail(VEMB_E_UNSUPPORTED, "momentum blocks above 64 x 64 are not supported yet");
+  // eigensolver capacity: pair blocks n x n (real), momentum blocks n_op x n_op (complex), n <= 256
+  if (g.n > 256 || n_op > 256) return fail(VEMB_E_UNSUPPORTED, "matrices above 256 x 256 are not supported");
 
   auto* p = new vemb_problem();
   p->g = g;
@@ -249,7 +248,11 @@ int vemb_create_problem(const vemb_hamiltonian* H, const vemb_lattice* lat, cons
       (rc = dalloc(p, &a.feas, (size_t)P)) || (rc = dalloc(p, &a.scal, 4)) ||
       (rc = dalloc(p, &a.Kbuf, (size_t)P * n * n + (size_t)m * m)) || (rc = dalloc(p, &a.lmin, (size_t)P + 1)) ||
       (rc = dalloc(p, &a.sweeps, (size_t)(2 * P + Ku + 1))) ||
-      (rc = dalloc(p, &a.Vpair, (size_t)P * n * n)) || (rc = dalloc(p, &a.Vmom, (size_t)2 * Ku * k * k)))
+      (rc = dalloc(p, &a.Vpair, (size_t)P * n * n)) || (rc = dalloc(p, &a.Vmom, (size_t)2 * Ku * k * k)) ||
+      (n > 64 && ((rc = dalloc(p, (double**)&a.wscr_pair, (size_t)P * n * n)) ||
+                  (rc = dalloc(p, (double**)&a.tscr_pair, (size_t)P * n * n)))) ||
+      (k > 64 && ((rc = dalloc(p, (double**)&a.wscr_mom, (size_t)2 * Ku * k * k)) ||
+                  (rc = dalloc(p, (double**)&a.tscr_mom, (size_t)2 * Ku * k * k)))))
     return cleanup(rc);
   hipStream_t s = p->stream;
   if ((rc = hip_rc(hipMemcpyAsync(p->H0, p->host.H0.data(), (size_t)m * m * 8, hipMemcpyHostToDevice, s), "upload H0")) ||
@@ -300,12 +303,18 @@ int vemb_step(vemb_problem* p, int iters) {
     VEMB_TRY(timed(p, VEMB_K_PAIR_UPDATE, "pair update", [&] { return launch_pair_update(a, s); }));
     VEMB_TRY(timed(p, VEMB_K_PAIR_XSTEP, "pair X step", [&] { return launch_pair_xstep(a, s); }));
     VEMB_TRY(timed(p, VEMB_K_PAIR_PROJ, "pair projection", [&] {
+      if (a.n > 64)
+        return launch_pair_projection_big(a.rho, a.Lam, a.rho_t, a.feas, a.n, a.P, a.mu, prec, ms, a.sweeps, a.Vpair,
+                                          cold, a.wscr_pair, a.tscr_pair, s);
       return launch_pair_projection(a.rho, a.Lam, a.rho_t, a.feas, a.n, a.P, a.mu, prec, ms, a.sweeps, a.Vpair, cold,
                                     s);
     }));
     VEMB_TRY(timed(p, VEMB_K_CLUSTER, "cluster update", [&] { return launch_cluster_update(a, s); }));
     VEMB_TRY(timed(p, VEMB_K_DFT_FWD, "forward DFT", [&] { return launch_dft_forward(a, s); }));
     VEMB_TRY(timed(p, VEMB_K_MOM_PROJ, "momentum projection", [&] {
+      if (a.n_op > 64)
+        return launch_momentum_projection_big(a.Xh, a.n_op, a.Ku, prec, ms, a.sweeps + a.P, a.Vmom, cold, a.wscr_mom,
+                                              a.tscr_mom, s);
       return launch_momentum_projection(a.Xh, a.n_op, a.Ku, prec, ms, a.sweeps + a.P, a.Vmom, cold, s);
     }));
     VEMB_TRY(timed(p, VEMB_K_DFT_INV, "inverse DFT", [&] { return launch_dft_inverse(a, s); }));
@@ -342,6 +351,9 @@ int vemb_dual_bound(vemb_problem* p, double* lb) {
   const int P = p->P, n = a.n, m = a.m;
   VEMB_TRY(timed(p, VEMB_K_BOUND_BUILD, "bound build", [&] { return launch_bound_build(a, s); }));
   VEMB_TRY(timed(p, VEMB_K_LMIN, "pair lambda_min", [&] {
+    if (n > 128)
+      return launch_eigvals_big(a.Kbuf, nullptr, a.lmin, n, P, false, p->opt.max_sweeps, a.sweeps + P + a.Ku,
+                                a.wscr_pair, a.tscr_pair, s);
     return launch_lambda_min(a.Kbuf, a.lmin, n, P, p->opt.max_sweeps, a.sweeps + P + a.Ku, s);
   }));
   VEMB_TRY(timed(p, VEMB_K_LMIN, "cluster lambda_min", [&] {
@@ -470,30 +482,56 @@ void vemb_destroy(vemb_problem* p) {
 
 int vemb_psd_project_batched(const double* in, double* out, int n, int batch, int is_complex, int precision,
                              void* hip_stream) {
-  if (!in || !out || n <= 0 || batch < 0) return fail(VEMB_E_INVALID, "bad arguments to vemb_psd_project_batched");
-  if (precision != VEMB_FP64 && precision != VEMB_MIXED) return fail(VEMB_E_INVALID, "unknown precision");
-  if ((is_complex && n > 64) || n > 128) return fail(VEMB_E_UNSUPPORTED, "matrix too large for the LDS solver");
-  return hip_rc(launch_psd_batched(in, out, n, batch, is_complex != 0, precision, 40, nullptr,
-                                   static_cast<hipStream_t>(hip_stream)),
-                "batched projection");
+  return vemb_psd_project_batched_ex(in, out, n, batch, is_complex, precision, 0, nullptr, hip_stream);
 }
+
+namespace {
+// Large matrices (streamed solver) need per-matrix scratch: allocated for the call,
+// freed after the stream drains (these calls synchronise).
+struct Scratch {
+  void* w = nullptr;
+  void* t = nullptr;
+  ~Scratch() {
+    if (w) hipFree(w);
+    if (t) hipFree(t);
+  }
+};
+}  // namespace
 
 int vemb_psd_project_batched_ex(const double* in, double* out, int n, int batch, int is_complex, int precision,
                                 int max_sweeps, int* sweeps, void* hip_stream) {
   if (!in || !out || n <= 0 || batch < 0) return fail(VEMB_E_INVALID, "bad arguments to vemb_psd_project_batched_ex");
   if (precision != VEMB_FP64 && precision != VEMB_MIXED) return fail(VEMB_E_INVALID, "unknown precision");
-  if ((is_complex && n > 64) || n > 128) return fail(VEMB_E_UNSUPPORTED, "matrix too large for the LDS solver");
-  return hip_rc(launch_psd_batched(in, out, n, batch, is_complex != 0, precision, max_sweeps > 0 ? max_sweeps : 40,
-                                   sweeps, static_cast<hipStream_t>(hip_stream)),
-                "batched projection");
+  if (n > 256) return fail(VEMB_E_UNSUPPORTED, "matrices above 256 x 256 are not supported");
+  const int ms = max_sweeps > 0 ? max_sweeps : 40;
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  if ((is_complex && n <= 64) || (!is_complex && n <= 128))
+    return hip_rc(launch_psd_batched(in, out, n, batch, is_complex != 0, precision, ms, sweeps, st),
+                  "batched projection");
+  if (n % 16) return fail(VEMB_E_UNSUPPORTED, "streamed solver needs n divisible by 16");
+  Scratch sc;
+  const size_t bytes = (size_t)batch * n * n * (is_complex ? 16 : 8);
+  if (hipMalloc(&sc.w, bytes) != hipSuccess || hipMalloc(&sc.t, bytes) != hipSuccess)
+    return fail(VEMB_E_NOMEM, "scratch for the streamed solver");
+  VEMB_TRY(hip_rc(launch_psd_batched_big(in, out, n, batch, is_complex != 0, precision, ms, sweeps, sc.w, sc.t, st),
+                  "batched projection"));
+  return hip_rc(hipStreamSynchronize(st), "batched projection sync");
 }
 
 int vemb_eigvalsh_batched(const double* in, double* w, int n, int batch, int is_complex, void* hip_stream) {
   if (!in || !w || n <= 0 || batch < 0) return fail(VEMB_E_INVALID, "bad arguments to vemb_eigvalsh_batched");
-  if ((is_complex && n > 64) || n > 128) return fail(VEMB_E_UNSUPPORTED, "matrix too large for the LDS solver");
-  return hip_rc(launch_eigvalsh_batched(in, w, n, batch, is_complex != 0, 40, nullptr,
-                                        static_cast<hipStream_t>(hip_stream)),
-                "batched eigenvalues");
+  if (n > 256) return fail(VEMB_E_UNSUPPORTED, "matrices above 256 x 256 are not supported");
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  if ((is_complex && n <= 64) || (!is_complex && n <= 128))
+    return hip_rc(launch_eigvalsh_batched(in, w, n, batch, is_complex != 0, 40, nullptr, st), "batched eigenvalues");
+  if (n % 16) return fail(VEMB_E_UNSUPPORTED, "streamed solver needs n divisible by 16");
+  Scratch sc;
+  const size_t bytes = (size_t)batch * n * n * (is_complex ? 16 : 8);
+  if (hipMalloc(&sc.w, bytes) != hipSuccess || hipMalloc(&sc.t, bytes) != hipSuccess)
+    return fail(VEMB_E_NOMEM, "scratch for the streamed solver");
+  VEMB_TRY(hip_rc(launch_eigvals_big(in, w, nullptr, n, batch, is_complex != 0, 40, nullptr, sc.w, sc.t, st),
+                  "batched eigenvalues"));
+  return hip_rc(hipStreamSynchronize(st), "batched eigenvalues sync");
 }
 
 }  // extern "C"

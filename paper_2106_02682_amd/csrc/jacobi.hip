@@ -21,141 +21,10 @@
 // sqrt(alpha beta), tol = max(n, 16) * machine epsilon of the compute type);
 // columns of negligible norm (rounding noise left by an exactly singular B) are
 // not rotated, see below.
-#include "kernels.h"
-
-#include <cfloat>
+#include "jacobi_common.h"
 
 namespace vemb {
 namespace {
-
-constexpr int kThreads = 256;
-
-template <typename R> struct eps_of;
-template <> struct eps_of<double> { static constexpr double v = DBL_EPSILON; };
-template <> struct eps_of<float> { static constexpr float v = FLT_EPSILON; };
-
-__device__ inline double dev_sqrt(double x) { return sqrt(x); }
-__device__ inline float dev_sqrt(float x) { return sqrtf(x); }
-__device__ inline double dev_abs(double x) { return fabs(x); }
-__device__ inline float dev_abs(float x) { return fabsf(x); }
-
-template <typename T> __device__ inline T shfl_x(T v, int m) { return __shfl_xor(v, m); }
-template <typename T> __device__ inline cplx<T> shfl_x(cplx<T> v, int m) {
-  return {__shfl_xor(v.re, m), __shfl_xor(v.im, m)};
-}
-
-template <typename R> __device__ inline R scale_by(R s, R a) { return s * a; }
-template <typename R> __device__ inline cplx<R> scale_by(R s, cplx<R> a) { return {s * a.re, s * a.im}; }
-
-// Multiply by a unit phase (complex) or a sign (real).
-template <typename R> __device__ inline R mul_phase(R ph, R a) { return ph * a; }
-template <typename R> __device__ inline cplx<R> mul_phase(cplx<R> ph, cplx<R> a) { return ph * a; }
-
-template <typename R> __device__ inline R modulus(R a) { return dev_abs(a); }
-// |a| with scaling, so that tiny moduli do not underflow in the squares
-template <typename R> __device__ inline R modulus(cplx<R> a) {
-  const R x = dev_abs(a.re), y = dev_abs(a.im);
-  const R big = x > y ? x : y;
-  if (big == R(0)) return R(0);
-  const R xs = x / big, ys = y / big;
-  return big * dev_sqrt(xs * xs + ys * ys);
-}
-
-// conj(gamma)/|gamma| for complex, sign(gamma) for real.
-template <typename R> __device__ inline R conj_phase(R g, R absg) { return g / absg; }
-template <typename R> __device__ inline cplx<R> conj_phase(cplx<R> g, R absg) { return {g.re / absg, -g.im / absg}; }
-
-template <typename S> __device__ inline S hermitian_avg(S a, S b_transposed) {
-  // (a + conj(b)) / 2
-  using R = typename scalar_traits<S>::real;
-  S cb = conjugate(b_transposed);
-  return scale_by(R(0.5), a + cb);
-}
-template <> __device__ inline double hermitian_avg<double>(double a, double b) { return 0.5 * (a + b); }
-template <> __device__ inline float hermitian_avg<float>(float a, float b) { return 0.5f * (a + b); }
-
-template <typename S> __device__ inline S add_real(S a, typename scalar_traits<S>::real r) { return a + r; }
-template <> __device__ inline cplx<double> add_real<cplx<double>>(cplx<double> a, double r) { return {a.re + r, a.im}; }
-template <> __device__ inline cplx<float> add_real<cplx<float>>(cplx<float> a, float r) { return {a.re + r, a.im}; }
-
-template <typename S> __device__ inline S drop_imag(S a) { return a; }
-template <> __device__ inline cplx<double> drop_imag<cplx<double>>(cplx<double> a) { return {a.re, 0.0}; }
-template <> __device__ inline cplx<float> drop_imag<cplx<float>>(cplx<float> a) { return {a.re, 0.0f}; }
-
-template <typename S> struct wide { using type = double; };
-template <> struct wide<float> { using type = double; };
-template <> struct wide<cplx<double>> { using type = cplx<double>; };
-template <> struct wide<cplx<float>> { using type = cplx<double>; };
-
-template <typename S> __device__ inline S narrow(typename wide<S>::type v);
-template <> __device__ inline double narrow<double>(double v) { return v; }
-template <> __device__ inline float narrow<float>(double v) { return (float)v; }
-template <> __device__ inline cplx<double> narrow<cplx<double>>(cplx<double> v) { return v; }
-template <> __device__ inline cplx<float> narrow<cplx<float>>(cplx<double> v) { return {(float)v.re, (float)v.im}; }
-__device__ inline double widen(double v) { return v; }
-__device__ inline double widen(float v) { return (double)v; }
-__device__ inline cplx<double> widen(cplx<double> v) { return v; }
-__device__ inline cplx<double> widen(cplx<float> v) { return {(double)v.re, (double)v.im}; }
-
-template <typename S> __device__ inline S one_of() { return S(1); }
-template <> __device__ inline cplx<double> one_of<cplx<double>>() { return {1.0, 0.0}; }
-template <> __device__ inline cplx<float> one_of<cplx<float>>() { return {1.0f, 0.0f}; }
-
-// Block-wide reductions through LDS (kThreads threads).
-template <typename R>
-__device__ R block_max(R v, R* red) {
-  const int t = threadIdx.x;
-  red[t] = v;
-  __syncthreads();
-  for (int s = kThreads / 2; s > 0; s >>= 1) {
-    if (t < s) red[t] = red[t] > red[t + s] ? red[t] : red[t + s];
-    __syncthreads();
-  }
-  R r = red[0];
-  __syncthreads();
-  return r;
-}
-
-template <typename R>
-__device__ R block_sum_r(R v, R* red) {
-  const int t = threadIdx.x;
-  red[t] = v;
-  __syncthreads();
-  for (int s = kThreads / 2; s > 0; s >>= 1) {
-    if (t < s) red[t] += red[t + s];
-    __syncthreads();
-  }
-  R r = red[0];
-  __syncthreads();
-  return r;
-}
-
-__device__ double block_sum(double v, double* red) {
-  const int t = threadIdx.x;
-  red[t] = v;
-  __syncthreads();
-  for (int s = kThreads / 2; s > 0; s >>= 1) {
-    if (t < s) red[t] += red[t + s];
-    __syncthreads();
-  }
-  double r = red[0];
-  __syncthreads();
-  return r;
-}
-
-// Round-robin (circle method) pairing of np = n rounded up to even players.
-__device__ inline void rr_pair(int round, int g, int np, int& p, int& q) {
-  const int k = np - 1;
-  if (g == 0) {
-    p = k;
-    q = round;
-  } else {
-    p = (round + g) % k;
-    q = (round - g + k) % k;
-  }
-}
-
-enum Mode { kProject = 0, kEigvals = 1 };
 
 // ---------------------------------------------------------------------------
 // Core kernel.  S: compute scalar (double, float, cplx<double>, cplx<float>);
@@ -403,104 +272,6 @@ __global__ void __launch_bounds__(kThreads) jacobi_kernel(Policy pol, int n, int
     }
   }
 }
-
-// ---------------------------------------------------------------------------
-// Policies
-// ---------------------------------------------------------------------------
-template <typename S> __device__ inline S from_double(double v);
-template <> __device__ inline double from_double<double>(double v) { return v; }
-template <> __device__ inline float from_double<float>(double v) { return (float)v; }
-
-__device__ inline double to_double(double v) { return v; }
-__device__ inline double to_double(float v) { return (double)v; }
-
-struct PairPolicy {
-  const double* rho;
-  double* Lam;
-  double* rho_t;
-  double* feas;
-  int* sweeps;
-  int n;
-  double mu;
-  template <typename S> __device__ S load(int mat, int i, int j) const {
-    const size_t o = (size_t)mat * n * n + (size_t)i * n + j;
-    return from_double<S>(rho[o] - Lam[o] / mu);
-  }
-  template <typename S> __device__ double store(int mat, int i, int k, S v) const {
-    const size_t o = (size_t)mat * n * n + (size_t)i * n + k;
-    const double pv = to_double(v);
-    const double r = rho[o];
-    rho_t[o] = pv;
-    Lam[o] = Lam[o] + mu * (pv - r);
-    const double dlt = r - pv;
-    return dlt * dlt;
-  }
-  __device__ void finish(int mat, double tot) const { feas[mat] = tot; }
-  __device__ void record_sweeps(int mat, int s) const {
-    if (sweeps) sweeps[mat] = s;
-  }
-  __device__ void store_eig(int, int, double) const {}
-};
-
-struct MomentumPolicy {
-  double* Xh;  // interleaved complex
-  int* sweeps;
-  int n;
-  template <typename S> __device__ S load(int mat, int i, int j) const {
-    const size_t o = 2 * ((size_t)mat * n * n + (size_t)i * n + j);
-    using R = typename scalar_traits<S>::real;
-    return S{(R)Xh[o], (R)Xh[o + 1]};
-  }
-  template <typename S> __device__ double store(int mat, int i, int k, S v) const {
-    const size_t o = 2 * ((size_t)mat * n * n + (size_t)i * n + k);
-    Xh[o] = (double)v.re;
-    Xh[o + 1] = (double)v.im;
-    return 0.0;
-  }
-  __device__ void finish(int, double) const {}
-  __device__ void record_sweeps(int mat, int s) const {
-    if (sweeps) sweeps[mat] = s;
-  }
-  __device__ void store_eig(int, int, double) const {}
-};
-
-// Real or complex matrices in plain arrays (isolated entry points and the bound).
-template <bool CPLX>
-struct ArrayPolicy {
-  const double* in;
-  double* out;   // projection output (may alias in)
-  double* w;     // eigenvalues (kEigvals)
-  double* wmin;  // smallest eigenvalue only
-  int* sweeps;
-  int n;
-  template <typename S> __device__ S load(int mat, int i, int j) const {
-    if constexpr (CPLX) {
-      const size_t o = 2 * ((size_t)mat * n * n + (size_t)i * n + j);
-      using R = typename scalar_traits<S>::real;
-      return S{(R)in[o], (R)in[o + 1]};
-    } else {
-      return from_double<S>(in[(size_t)mat * n * n + (size_t)i * n + j]);
-    }
-  }
-  template <typename S> __device__ double store(int mat, int i, int k, S v) const {
-    if constexpr (CPLX) {
-      const size_t o = 2 * ((size_t)mat * n * n + (size_t)i * n + k);
-      out[o] = (double)v.re;
-      out[o + 1] = (double)v.im;
-    } else {
-      out[(size_t)mat * n * n + (size_t)i * n + k] = to_double(v);
-    }
-    return 0.0;
-  }
-  __device__ void finish(int, double) const {}
-  __device__ void record_sweeps(int mat, int s) const {
-    if (sweeps) sweeps[mat] = s;
-  }
-  __device__ void store_eig(int mat, int rank, double v) const {
-    if (w) w[(size_t)mat * n + rank] = v;
-    if (wmin && rank == 0) wmin[mat] = v;
-  }
-};
 
 // vstore == nullptr: cold solve without eigenvector storage.  Otherwise the
 // eigenvectors of every matrix slot are read (unless cold) and written back.

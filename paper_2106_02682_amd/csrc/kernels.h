@@ -27,6 +27,18 @@ hipError_t launch_psd_batched(const double* in, double* out, int n, int batch, b
 hipError_t launch_eigvalsh_batched(const double* in, double* w, int n, int batch, bool is_complex,
                                    int max_sweeps, int* sweeps, hipStream_t st);
 
+// Streaming variants for n > 64 (pairs) / n_op > 64 (momentum), n <= 256: W and T are
+// per-matrix scratch of count x n x n compute scalars each (sized for FP64 / complex FP64).
+hipError_t launch_pair_projection_big(const double* rho, double* Lam, double* rho_t, double* feas, int n, int P,
+                                      double mu, int precision, int max_sweeps, int* sweeps, double* vstore, int cold,
+                                      void* wscr, void* tscr, hipStream_t st);
+hipError_t launch_momentum_projection_big(double* Xh, int n_op, int K, int precision, int max_sweeps, int* sweeps,
+                                          double* vstore, int cold, void* wscr, void* tscr, hipStream_t st);
+hipError_t launch_psd_batched_big(const double* in, double* out, int n, int batch, bool is_complex, int precision,
+                                  int max_sweeps, int* sweeps, void* wscr, void* tscr, hipStream_t st);
+hipError_t launch_eigvals_big(const double* in, double* w, double* wmin, int n, int count, bool is_complex,
+                              int max_sweeps, int* sweeps, void* wscr, void* tscr, hipStream_t st);
+
 // Smallest eigenvalue of `count` symmetric n x n matrices stored contiguously.
 hipError_t launch_lambda_min(const double* K, double* lmin, int n, int count, int max_sweeps, int* sweeps,
                              hipStream_t st);
@@ -66,6 +78,10 @@ struct StepArgs {
   int* sweeps;      // per-matrix sweep counters (P + Ku + P + 1)
   double* Vpair;    // P x n x n eigenvectors of the pair projections (warm start)
   double* Vmom;     // Ku x n_op x n_op complex eigenvectors of the momentum projections
+  void* wscr_pair;  // streaming-solver scratch (n > 64): P x n x n doubles each
+  void* tscr_pair;
+  void* wscr_mom;   // (n_op > 64): Ku x n_op x n_op complex doubles each
+  void* tscr_mom;
 };
 
 hipError_t launch_pair_update(const StepArgs& a, hipStream_t st);

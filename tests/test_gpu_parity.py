@@ -67,6 +67,26 @@ def test_projection_complex_fp64(vemb, n, batch):
     assert np.abs(got - want).max() <= 1e-12 * max(1.0, np.abs(C).max()) * max(1, n / 16)
 
 
+@pytest.mark.parametrize("n,batch,cplx", [(256, 3, False), (144, 2, False), (256, 2, True), (128, 3, True)])
+def test_projection_streamed_solver(vemb, n, batch, cplx):
+    """Matrices above the LDS capacity go through the block-streamed solver."""
+    C = synth.hermitian_batch(n, batch, tag=15) if cplx else synth.admm_like_batch(n, batch, tag=15)
+    inp = _dev(_interleave(C) if cplx else C)
+    out = torch.empty_like(inp)
+    sw = torch.zeros(batch, dtype=torch.int32, device="cuda")
+    vemb.psd_project_batched_ex(inp, out, is_complex=cplx, sweeps=sw)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    got = _deinterleave(got) if cplx else got
+    assert np.abs(got - psd_project(C)).max() <= 1e-12 * max(1.0, np.abs(C).max()) * n / 16
+    assert int(sw.max()) < 40
+    w = torch.empty((batch, n), dtype=torch.float64, device="cuda")
+    vemb.eigvalsh_batched(inp, w, is_complex=cplx)
+    torch.cuda.synchronize()
+    want = np.linalg.eigvalsh(C)
+    assert np.abs(w.cpu().numpy() - want).max() <= 1e-12 * max(1.0, np.abs(want).max()) * n / 16
+
+
 def test_projection_degenerate_inputs(vemb):
     n = 16
     rng = np.random.default_rng(3)
@@ -185,6 +205,8 @@ def _compare(w, iters, rel_lb=1e-10, atol_state=1e-9):
     (synth.tfi_torus(4, 4, 2, 1, 1.0), 80),
     (synth.tfi_torus(6, 4, 1, 2, 3.0), 40),
     (synth.afh_torus(4, 4, 1, 1), 100),
+    (synth.tfi_ring(8, 4, 1.0), 12),
+    (synth.tfi_torus(4, 4, 2, 2, 3.0), 6),
 ], ids=lambda x: getattr(x, "name", str(x)))
 def test_iteration_parity_fp64(vemb, w, iters):
     _compare(w, iters)
