@@ -78,12 +78,15 @@ typedef struct {
 } vemb_clusters;
 
 enum vemb_opset { VEMB_OPSET_COMPLETE = 0, VEMB_OPSET_PAULI1 = 1 };
-enum vemb_precision { VEMB_FP64 = 0, VEMB_MIXED = 1 };
+/* VEMB_FP64: FP64 eigensolves.  VEMB_MIXED: FP32 Jacobi sweeps find the eigenvectors,
+ * then one FP64 sweep warm-started from them and an FP64 rebuild.  VEMB_FP32: FP32
+ * sweeps and rebuilds (state, diagnostics and vemb_refine stay FP64). */
+enum vemb_precision { VEMB_FP64 = 0, VEMB_MIXED = 1, VEMB_FP32 = 2 };
 
 typedef struct {
   double mu, nu, eps;  /* penalty and step parameters (Section 4 uses 10, 10, 2) */
   int32_t opset;       /* vemb_opset: operator collection defining G (Section 2.2) */
-  int32_t precision;   /* vemb_precision: FP64, or FP32 eigensolves with FP64 refinement */
+  int32_t precision;   /* vemb_precision */
   int32_t max_sweeps;  /* Jacobi sweep cap per eigensolve (0 = default 40) */
   int32_t sign;        /* -1: X <- Pi(X - eps G) (default when 0); +1: the printed + sign */
   int32_t warm_refresh; /* eigensolves start from the previous iteration's eigenvectors; every
@@ -114,6 +117,12 @@ int vemb_problem_info(const vemb_problem* p, vemb_info* info);
 /* Enqueues `iters` iterations of Algorithm 6 on the problem's stream.
  * Asynchronous: returns once the work is enqueued. */
 int vemb_step(vemb_problem* p, int iters);
+
+/* Mixed precision's final refinement: enqueues `iters` iterations whose
+ * eigensolves run in FP64, warm-started from the eigenvectors the FP32 solves
+ * kept, so one or two FP64 sweeps each remain.  Same as vemb_step for an FP64
+ * problem.  Asynchronous. */
+int vemb_refine(vemb_problem* p, int iters);
 
 /* FP64 Lagrangian lower bound per site (valid for any PSD X and any symmetric
  * Lambda1, Lambda2; derived from the partial dual, Section 2.4):

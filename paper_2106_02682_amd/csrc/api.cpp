@@ -175,7 +175,7 @@ int vemb_create_problem(const vemb_hamiltonian* H, const vemb_lattice* lat, cons
   if (o.warm_refresh == 0) o.warm_refresh = 64;
   if (!(o.mu > 0 && o.nu > 0 && o.eps > 0)) return fail(VEMB_E_INVALID, "mu, nu, eps must be positive");
   if (o.opset != VEMB_OPSET_COMPLETE && o.opset != VEMB_OPSET_PAULI1) return fail(VEMB_E_INVALID, "unknown opset");
-  if (o.precision != VEMB_FP64 && o.precision != VEMB_MIXED) return fail(VEMB_E_INVALID, "unknown precision");
+  if (o.precision < VEMB_FP64 || o.precision > VEMB_FP32) return fail(VEMB_E_INVALID, "unknown precision");
   if (lat->ndim != 1 && lat->ndim != 2) return fail(VEMB_E_INVALID, "ndim must be 1 or 2");
   Geometry g{};
   g.Nx = lat->extent[0];
@@ -292,11 +292,11 @@ int vemb_problem_info(const vemb_problem* p, vemb_info* info) {
   return VEMB_OK;
 }
 
-int vemb_step(vemb_problem* p, int iters) {
-  if (!p || iters < 0) return fail(VEMB_E_INVALID, "bad arguments to vemb_step");
+namespace {
+int run_iterations(vemb_problem* p, int iters, int prec) {
   const StepArgs& a = p->a;
   hipStream_t s = p->stream;
-  const int prec = p->opt.precision, ms = p->opt.max_sweeps;
+  const int ms = p->opt.max_sweeps;
   for (int it = 0; it < iters; ++it) {
     const int refresh = p->opt.warm_refresh;
     const int cold = (!p->v_valid || refresh < 0 || p->t % refresh == 0) ? 1 : 0;
@@ -322,6 +322,17 @@ int vemb_step(vemb_problem* p, int iters) {
     ++p->t;
   }
   return VEMB_OK;
+}
+}  // namespace
+
+int vemb_step(vemb_problem* p, int iters) {
+  if (!p || iters < 0) return fail(VEMB_E_INVALID, "bad arguments to vemb_step");
+  return run_iterations(p, iters, p->opt.precision);
+}
+
+int vemb_refine(vemb_problem* p, int iters) {
+  if (!p || iters < 0) return fail(VEMB_E_INVALID, "bad arguments to vemb_refine");
+  return run_iterations(p, iters, VEMB_FP64);
 }
 
 int vemb_primal_energy(vemb_problem* p, double* e_per_site, double* feas_err) {
@@ -491,9 +502,11 @@ namespace {
 struct Scratch {
   void* w = nullptr;
   void* t = nullptr;
+  void* v = nullptr;
   ~Scratch() {
     if (w) hipFree(w);
     if (t) hipFree(t);
+    if (v) hipFree(v);
   }
 };
 }  // namespace
@@ -501,19 +514,25 @@ struct Scratch {
 int vemb_psd_project_batched_ex(const double* in, double* out, int n, int batch, int is_complex, int precision,
                                 int max_sweeps, int* sweeps, void* hip_stream) {
   if (!in || !out || n <= 0 || batch < 0) return fail(VEMB_E_INVALID, "bad arguments to vemb_psd_project_batched_ex");
-  if (precision != VEMB_FP64 && precision != VEMB_MIXED) return fail(VEMB_E_INVALID, "unknown precision");
+  if (precision < VEMB_FP64 || precision > VEMB_FP32) return fail(VEMB_E_INVALID, "unknown precision");
   if (n > 256) return fail(VEMB_E_UNSUPPORTED, "matrices above 256 x 256 are not supported");
   const int ms = max_sweeps > 0 ? max_sweeps : 40;
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
-  if ((is_complex && n <= 64) || (!is_complex && n <= 128))
-    return hip_rc(launch_psd_batched(in, out, n, batch, is_complex != 0, precision, ms, sweeps, st),
-                  "batched projection");
-  if (n % 16) return fail(VEMB_E_UNSUPPORTED, "streamed solver needs n divisible by 16");
-  Scratch sc;
+  const bool lds = (is_complex && n <= 64) || (!is_complex && n <= 128);
+  const bool need_v = precision == VEMB_MIXED && !(n > 64 && n <= 128);  // MIXED keeps eigenvectors between passes
   const size_t bytes = (size_t)batch * n * n * (is_complex ? 16 : 8);
+  Scratch sc;
+  if (need_v && hipMalloc(&sc.v, bytes) != hipSuccess) return fail(VEMB_E_NOMEM, "eigenvector scratch");
+  if (lds) {
+    VEMB_TRY(hip_rc(launch_psd_batched(in, out, n, batch, is_complex != 0, precision, ms, sweeps, (double*)sc.v, st),
+                    "batched projection"));
+    return sc.v ? hip_rc(hipStreamSynchronize(st), "batched projection sync") : VEMB_OK;
+  }
+  if (n % 32) return fail(VEMB_E_UNSUPPORTED, "streamed solver needs n divisible by 32");
   if (hipMalloc(&sc.w, bytes) != hipSuccess || hipMalloc(&sc.t, bytes) != hipSuccess)
     return fail(VEMB_E_NOMEM, "scratch for the streamed solver");
-  VEMB_TRY(hip_rc(launch_psd_batched_big(in, out, n, batch, is_complex != 0, precision, ms, sweeps, sc.w, sc.t, st),
+  VEMB_TRY(hip_rc(launch_psd_batched_big(in, out, n, batch, is_complex != 0, precision, ms, sweeps, (double*)sc.v,
+                                         sc.w, sc.t, st),
                   "batched projection"));
   return hip_rc(hipStreamSynchronize(st), "batched projection sync");
 }
@@ -524,7 +543,7 @@ int vemb_eigvalsh_batched(const double* in, double* w, int n, int batch, int is_
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
   if ((is_complex && n <= 64) || (!is_complex && n <= 128))
     return hip_rc(launch_eigvalsh_batched(in, w, n, batch, is_complex != 0, 40, nullptr, st), "batched eigenvalues");
-  if (n % 16) return fail(VEMB_E_UNSUPPORTED, "streamed solver needs n divisible by 16");
+  if (n % 32) return fail(VEMB_E_UNSUPPORTED, "streamed solver needs n divisible by 32");
   Scratch sc;
   const size_t bytes = (size_t)batch * n * n * (is_complex ? 16 : 8);
   if (hipMalloc(&sc.w, bytes) != hipSuccess || hipMalloc(&sc.t, bytes) != hipSuccess)

@@ -2,16 +2,17 @@
 // by a one-sided (Hestenes) Jacobi eigensolver held in LDS, one workgroup per matrix.
 //
 // Method.  Pi needs the eigenpairs of C with positive eigenvalues.  The kernel
-// shifts C to B = C + s I with s the Gershgorin bound max(0, max_i (r_i - c_ii)),
-// so B is positive semidefinite, then orthogonalises the columns of W = B by
+// shifts C to B = C + s I with s from the Gershgorin bound g = max(0, max_i (r_i - c_ii))
+// >= -lambda_min(C) (s = g for eigenvalues, g/2 for Pi, see below), then
+// orthogonalises the columns of W = B by
 // plane rotations W <- W J (round-robin parallel ordering: n/2 disjoint column
 // pairs per round, every pair once per sweep).  At convergence W = B V with V
 // orthogonal and W's columns mutually orthogonal, hence w_j = lambda_j(B) v_j
 // and ||w_j|| = lambda_j(B) >= 0.  Then
 //     Pi(C) = sum_{||w_j|| > s} (||w_j|| - s) / ||w_j||^2  w_j w_j^H,
-// so V is never stored.  Eigenvalues of C are ||w_j|| - s.  Because B is PSD
-// no pair of singular values +-sigma can mix (the failure of one-sided Jacobi on
-// indefinite matrices).  Hermitian blocks use the complex rotation
+// so V is not needed for Pi.  Eigenvalues of C are ||w_j|| - s when B is PSD.
+// One-sided Jacobi sees only |b| of B's eigenvalues, so +-b pairs can mix; with
+// s >= -lambda_min/2 every such pair lies at or below the cut and Pi is unaffected.  Hermitian blocks use the complex rotation
 // [w_p, w_q] <- [w_p, conj(e) w_q] R(c, s) with e = gamma/|gamma|.
 //
 // Work split: 256 threads; each column pair of a round is owned by a group of G
@@ -53,6 +54,49 @@ __global__ void __launch_bounds__(kThreads) jacobi_kernel(Policy pol, int n, int
   const int mat = blockIdx.x;
   const int tid = threadIdx.x;
   const int nn = n * n;
+  constexpr int NOUT = (NMAX * NMAX + kThreads - 1) / kThreads;
+
+  // 0. cold == 2: the kept V comes from a lower-precision solve; restore its
+  // orthonormality first with one Newton-Schulz step V <- V (3I - V^H V)/2
+  // (defect E -> O(E^2)), using W as the buffer for G = V^H V.
+  if constexpr (WARM) {
+    if (cold == 2) {
+      const D* vin = vstore + (size_t)mat * n * n;
+      for (int idx = tid; idx < nn; idx += kThreads) {
+        const int j = idx / n, i = idx - (idx / n) * n;
+        V[j * LD + i] = narrow<S>(vin[idx]);
+      }
+      __syncthreads();
+      S outv[NOUT];
+      int c = 0;
+      for (int idx = tid; idx < nn; idx += kThreads, ++c) {
+        const int j = idx / n, i = idx - (idx / n) * n;
+        S acc = s_zero<S>();
+        for (int k = 0; k < n; ++k) acc = acc + conj_mul(V[i * LD + k], V[j * LD + k]);
+        outv[c] = acc;  // G(i, j)
+      }
+      c = 0;
+      for (int idx = tid; idx < nn; idx += kThreads, ++c) {
+        const int j = idx / n, i = idx - (idx / n) * n;
+        W[j * LD + i] = outv[c];
+      }
+      __syncthreads();
+      c = 0;
+      for (int idx = tid; idx < nn; idx += kThreads, ++c) {
+        const int j = idx / n, i = idx - (idx / n) * n;
+        S acc = s_zero<S>();
+        for (int k = 0; k < n; ++k) acc = acc + V[k * LD + i] * W[j * LD + k];
+        outv[c] = scale_by(R(1.5), V[j * LD + i]) - scale_by(R(0.5), acc);
+      }
+      __syncthreads();
+      c = 0;
+      for (int idx = tid; idx < nn; idx += kThreads, ++c) {
+        const int j = idx / n, i = idx - (idx / n) * n;
+        V[j * LD + i] = outv[c];
+      }
+      __syncthreads();
+    }
+  }
 
   // 1. load C (column j at W[j*LD]) and take its Hermitian part
   for (int idx = tid; idx < nn; idx += kThreads) {
@@ -84,7 +128,12 @@ __global__ void __launch_bounds__(kThreads) jacobi_kernel(Policy pol, int n, int
       R e = rad - d;
       v = e > v ? e : v;
     }
+    // Pi needs only s >= -lambda_min(C)/2: every negative eigenvalue b of B then has
+    // |b| <= s, so it and any column one-sided Jacobi mixes with it (same |b|) fall at or
+    // below the cut sigma > s.  Half the Gershgorin bound satisfies this and halves the
+    // shift's share of the rounding error.  Eigenvalue mode needs B >= 0: full bound.
     shift = block_max(v, red);
+    if constexpr (MODE != kEigvals) shift *= R(0.5);
   }
   for (int i = tid; i < n; i += kThreads) W[i * LD + i] = add_real(W[i * LD + i], shift);
   __syncthreads();
@@ -93,18 +142,19 @@ __global__ void __launch_bounds__(kThreads) jacobi_kernel(Policy pol, int n, int
   // matrix moved little, so few sweeps remain.  V accumulates the rotations.
   if constexpr (WARM) {
     const D* vin = vstore + (size_t)mat * n * n;  // column-major: V(i, j) at [j*n + i]
-    if (cold) {
+    if (cold == 1) {
       for (int idx = tid; idx < nn; idx += kThreads) {
         const int j = idx / n, i = idx - (idx / n) * n;
         V[j * LD + i] = (i == j) ? one_of<S>() : s_zero<S>();
       }
     } else {
-      for (int idx = tid; idx < nn; idx += kThreads) {
-        const int j = idx / n, i = idx - (idx / n) * n;
-        V[j * LD + i] = narrow<S>(vin[idx]);
+      if (cold != 2) {  // (cold == 2 loaded and orthonormalised V above)
+        for (int idx = tid; idx < nn; idx += kThreads) {
+          const int j = idx / n, i = idx - (idx / n) * n;
+          V[j * LD + i] = narrow<S>(vin[idx]);
+        }
       }
       __syncthreads();
-      constexpr int NOUT = (NMAX * NMAX + kThreads - 1) / kThreads;
       S outv[NOUT];
       int c = 0;
       for (int idx = tid; idx < nn; idx += kThreads, ++c) {
@@ -212,6 +262,14 @@ __global__ void __launch_bounds__(kThreads) jacobi_kernel(Policy pol, int n, int
     if (!any) break;
   }
   if (tid == 0) pol.record_sweeps(mat, sweep);
+  if constexpr (WARM) {
+    D* vout = vstore + (size_t)mat * n * n;
+    for (int idx = tid; idx < nn; idx += kThreads) {
+      const int j = idx / n, i = idx - (idx / n) * n;
+      vout[idx] = widen(V[j * LD + i]);
+    }
+  }
+  if constexpr (MODE == kVectors) return;
 
   // 4. column norms sigma_j = lambda_j(B)
   for (int j = tid; j < n; j += kThreads) {
@@ -263,13 +321,7 @@ __global__ void __launch_bounds__(kThreads) jacobi_kernel(Policy pol, int n, int
     }
     const double tot = block_sum(part, red_d);
     if (tid == 0) pol.finish(mat, tot);
-    if constexpr (WARM) {
-      D* vout = vstore + (size_t)mat * n * n;
-      for (int idx = tid; idx < nn; idx += kThreads) {
-        const int j = idx / n, i = idx - (idx / n) * n;
-        vout[idx] = widen(V[j * LD + i]);
-      }
-    }
+
   }
 }
 
@@ -309,31 +361,45 @@ hipError_t dispatch(const Policy& pol, int n, int count, int max_sweeps, hipStre
 
 }  // namespace
 
+// Precision modes: FP64 solves; FP32 solves; MIXED = FP32 sweeps for the eigenvectors,
+// then one FP64 sweep warm-started from them and the FP64 rebuild.
+template <typename S32, typename S64, typename Policy>
+hipError_t by_precision(const Policy& pol, const Policy& pol_quiet, int n, int count, int precision, int max_sweeps,
+                        double* vstore, int cold, hipStream_t st) {
+  if (precision == VEMB_FP32) return dispatch<S32, kProject>(pol, n, count, max_sweeps, st, vstore, cold);
+  if (precision == VEMB_MIXED && vstore) {
+    hipError_t e = dispatch<S32, kVectors>(pol, n, count, max_sweeps, st, vstore, cold);
+    if (e != hipSuccess) return e;
+    return dispatch<S64, kProject>(pol_quiet, n, count, 2, st, vstore, 2);
+  }
+  return dispatch<S64, kProject>(pol, n, count, max_sweeps, st, vstore, cold);
+}
+
 hipError_t launch_pair_projection(const double* rho, double* Lam, double* rho_t, double* feas, int n, int P,
                                   double mu, int precision, int max_sweeps, int* sweeps, double* vstore, int cold,
                                   hipStream_t st) {
   PairPolicy pol{rho, Lam, rho_t, feas, sweeps, n, mu};
-  if (precision == VEMB_MIXED) return dispatch<float, kProject>(pol, n, P, max_sweeps, st, vstore, cold);
-  return dispatch<double, kProject>(pol, n, P, max_sweeps, st, vstore, cold);
+  PairPolicy quiet{rho, Lam, rho_t, feas, nullptr, n, mu};
+  return by_precision<float, double>(pol, quiet, n, P, precision, max_sweeps, vstore, cold, st);
 }
 
 hipError_t launch_momentum_projection(double* Xh, int n_op, int K, int precision, int max_sweeps, int* sweeps,
                                       double* vstore, int cold, hipStream_t st) {
   MomentumPolicy pol{Xh, sweeps, n_op};
-  if (precision == VEMB_MIXED) return dispatch<cplx<float>, kProject>(pol, n_op, K, max_sweeps, st, vstore, cold);
-  return dispatch<cplx<double>, kProject>(pol, n_op, K, max_sweeps, st, vstore, cold);
+  MomentumPolicy quiet{Xh, nullptr, n_op};
+  return by_precision<cplx<float>, cplx<double>>(pol, quiet, n_op, K, precision, max_sweeps, vstore, cold, st);
 }
 
 hipError_t launch_psd_batched(const double* in, double* out, int n, int batch, bool is_complex, int precision,
-                              int max_sweeps, int* sweeps, hipStream_t st) {
+                              int max_sweeps, int* sweeps, double* vstore, hipStream_t st) {
   if (is_complex) {
     ArrayPolicy<true> pol{in, out, nullptr, nullptr, sweeps, n};
-    if (precision == VEMB_MIXED) return dispatch<cplx<float>, kProject>(pol, n, batch, max_sweeps, st);
-    return dispatch<cplx<double>, kProject>(pol, n, batch, max_sweeps, st);
+    ArrayPolicy<true> quiet{in, out, nullptr, nullptr, nullptr, n};
+    return by_precision<cplx<float>, cplx<double>>(pol, quiet, n, batch, precision, max_sweeps, vstore, 1, st);
   }
   ArrayPolicy<false> pol{in, out, nullptr, nullptr, sweeps, n};
-  if (precision == VEMB_MIXED) return dispatch<float, kProject>(pol, n, batch, max_sweeps, st);
-  return dispatch<double, kProject>(pol, n, batch, max_sweeps, st);
+  ArrayPolicy<false> quiet{in, out, nullptr, nullptr, nullptr, n};
+  return by_precision<float, double>(pol, quiet, n, batch, precision, max_sweeps, vstore, 1, st);
 }
 
 hipError_t launch_eigvalsh_batched(const double* in, double* w, int n, int batch, bool is_complex, int max_sweeps,

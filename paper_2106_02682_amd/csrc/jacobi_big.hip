@@ -151,6 +151,27 @@ __global__ void __launch_bounds__(kThreads) jacobi_big_kernel(Policy pol, int n,
   S* T = tscr + mat * nn;
   D* Vg = TRACKV ? static_cast<D*>(vstore_raw) + mat * nn : nullptr;
 
+  // 0. cold == 2: orthonormalise the kept V (from a lower-precision solve) by one
+  // Newton-Schulz step V <- V (3I - V^H V)/2, with G in T and the result via W.
+  if constexpr (TRACKV) {
+    if (cold == 2) {
+      tiled_gemm<S>(
+          n, n, L, [&](int i, int k) { return conjugate(narrow<S>(Vg[(size_t)i * n + k])); },
+          [&](int k, int j) { return narrow<S>(Vg[(size_t)j * n + k]); },
+          [&](int i, int j, S v) { T[(size_t)j * n + i] = v; });
+      __syncthreads();
+      tiled_gemm<S>(
+          n, n, L, [&](int i, int k) { return narrow<S>(Vg[(size_t)k * n + i]); },
+          [&](int k, int j) { return T[(size_t)j * n + k]; },
+          [&](int i, int j, S v) {
+            W[(size_t)j * n + i] = scale_by(R(1.5), narrow<S>(Vg[(size_t)j * n + i])) - scale_by(R(0.5), v);
+          });
+      __syncthreads();
+      for (size_t idx = tid; idx < nn; idx += kThreads) Vg[idx] = widen(W[idx]);
+      __syncthreads();
+    }
+  }
+
   // 1. T = Hermitian part of C
   for (size_t idx = tid; idx < nn; idx += kThreads) {
     const int j = (int)(idx / n), i = (int)(idx % n);
@@ -174,11 +195,16 @@ __global__ void __launch_bounds__(kThreads) jacobi_big_kernel(Policy pol, int n,
       const R e = rad - re_part(T[(size_t)i * n + i]);
       v = e > v ? e : v;
     }
+    // Pi needs only s >= -lambda_min(C)/2: every negative eigenvalue b of B then has
+    // |b| <= s, so it and any column one-sided Jacobi mixes with it (same |b|) fall at or
+    // below the cut sigma > s.  Half the Gershgorin bound satisfies this and halves the
+    // shift's share of the rounding error.  Eigenvalue mode needs B >= 0: full bound.
     shift = block_max(v, red);
+    if constexpr (MODE != kEigvals) shift *= R(0.5);
   }
 
   // 3. W = (T + s I) V_prev (warm) or T + s I (cold, V = I)
-  if (TRACKV && !cold) {
+  if (TRACKV && cold != 1) {
     tiled_gemm<S>(
         n, n, L, [&](int i, int k) { return T[(size_t)k * n + i]; },
         [&](int k, int j) { return narrow<S>(Vg[(size_t)j * n + k]); },
@@ -272,6 +298,7 @@ __global__ void __launch_bounds__(kThreads) jacobi_big_kernel(Policy pol, int n,
     if (!any) break;
   }
   if (tid == 0) pol.record_sweeps(mat, sweep);
+  if constexpr (MODE == kVectors) return;
 
   // 5. column norms
   for (int j = tid; j < n; j += kThreads) {
@@ -325,7 +352,7 @@ hipError_t big_dispatch(const Policy& pol, int n, int count, int max_sweeps, dou
                         int cold, hipStream_t st) {
   if (count <= 0) return hipSuccess;
   if (n > kBigMax || n % big_block<S>::v) return hipErrorInvalidValue;
-  if (vstore && MODE == kProject)
+  if (vstore && MODE != kEigvals)
     hipLaunchKernelGGL((jacobi_big_kernel<S, MODE, true, Policy>), dim3(count), dim3(kThreads), 0, st, pol, n,
                        max_sweeps, (void*)vstore, (S*)wscr, (S*)tscr, cold);
   else
@@ -334,34 +361,46 @@ hipError_t big_dispatch(const Policy& pol, int n, int count, int max_sweeps, dou
   return hipGetLastError();
 }
 
+// FP64, FP32, or MIXED (FP32 sweeps for the eigenvectors, then one warm FP64 sweep + FP64 rebuild).
+template <typename S32, typename S64, typename Policy>
+hipError_t big_by_precision(const Policy& pol, const Policy& quiet, int n, int count, int precision, int max_sweeps,
+                            double* vstore, int cold, void* wscr, void* tscr, hipStream_t st) {
+  if (precision == VEMB_FP32) return big_dispatch<S32, kProject>(pol, n, count, max_sweeps, vstore, wscr, tscr, cold, st);
+  if (precision == VEMB_MIXED && vstore) {
+    hipError_t e = big_dispatch<S32, kVectors>(pol, n, count, max_sweeps, vstore, wscr, tscr, cold, st);
+    if (e != hipSuccess) return e;
+    return big_dispatch<S64, kProject>(quiet, n, count, 3, vstore, wscr, tscr, 2, st);
+  }
+  return big_dispatch<S64, kProject>(pol, n, count, max_sweeps, vstore, wscr, tscr, cold, st);
+}
+
 hipError_t launch_pair_projection_big(const double* rho, double* Lam, double* rho_t, double* feas, int n, int P,
                                       double mu, int precision, int max_sweeps, int* sweeps, double* vstore, int cold,
                                       void* wscr, void* tscr, hipStream_t st) {
   PairPolicy pol{rho, Lam, rho_t, feas, sweeps, n, mu};
-  if (precision == VEMB_MIXED)
-    return big_dispatch<float, kProject>(pol, n, P, max_sweeps, vstore, wscr, tscr, cold, st);
-  return big_dispatch<double, kProject>(pol, n, P, max_sweeps, vstore, wscr, tscr, cold, st);
+  PairPolicy quiet{rho, Lam, rho_t, feas, nullptr, n, mu};
+  return big_by_precision<float, double>(pol, quiet, n, P, precision, max_sweeps, vstore, cold, wscr, tscr, st);
 }
 
 hipError_t launch_momentum_projection_big(double* Xh, int n_op, int K, int precision, int max_sweeps, int* sweeps,
                                           double* vstore, int cold, void* wscr, void* tscr, hipStream_t st) {
   MomentumPolicy pol{Xh, sweeps, n_op};
-  if (precision == VEMB_MIXED)
-    return big_dispatch<cplx<float>, kProject>(pol, n_op, K, max_sweeps, vstore, wscr, tscr, cold, st);
-  return big_dispatch<cplx<double>, kProject>(pol, n_op, K, max_sweeps, vstore, wscr, tscr, cold, st);
+  MomentumPolicy quiet{Xh, nullptr, n_op};
+  return big_by_precision<cplx<float>, cplx<double>>(pol, quiet, n_op, K, precision, max_sweeps, vstore, cold, wscr,
+                                                     tscr, st);
 }
 
 hipError_t launch_psd_batched_big(const double* in, double* out, int n, int batch, bool is_complex, int precision,
-                                  int max_sweeps, int* sweeps, void* wscr, void* tscr, hipStream_t st) {
+                                  int max_sweeps, int* sweeps, double* vstore, void* wscr, void* tscr, hipStream_t st) {
   if (is_complex) {
     ArrayPolicy<true> pol{in, out, nullptr, nullptr, sweeps, n};
-    if (precision == VEMB_MIXED)
-      return big_dispatch<cplx<float>, kProject>(pol, n, batch, max_sweeps, nullptr, wscr, tscr, 1, st);
-    return big_dispatch<cplx<double>, kProject>(pol, n, batch, max_sweeps, nullptr, wscr, tscr, 1, st);
+    ArrayPolicy<true> quiet{in, out, nullptr, nullptr, nullptr, n};
+    return big_by_precision<cplx<float>, cplx<double>>(pol, quiet, n, batch, precision, max_sweeps, vstore, 1, wscr,
+                                                       tscr, st);
   }
   ArrayPolicy<false> pol{in, out, nullptr, nullptr, sweeps, n};
-  if (precision == VEMB_MIXED) return big_dispatch<float, kProject>(pol, n, batch, max_sweeps, nullptr, wscr, tscr, 1, st);
-  return big_dispatch<double, kProject>(pol, n, batch, max_sweeps, nullptr, wscr, tscr, 1, st);
+  ArrayPolicy<false> quiet{in, out, nullptr, nullptr, nullptr, n};
+  return big_by_precision<float, double>(pol, quiet, n, batch, precision, max_sweeps, vstore, 1, wscr, tscr, st);
 }
 
 hipError_t launch_eigvals_big(const double* in, double* w, double* wmin, int n, int count, bool is_complex,

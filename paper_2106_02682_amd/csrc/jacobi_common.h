@@ -136,7 +136,9 @@ __device__ inline void rr_pair(int round, int g, int np, int& p, int& q) {
   }
 }
 
-enum Mode { kProject = 0, kEigvals = 1 };
+// kProject: Pi(C) through the policy's store; kEigvals: sorted eigenvalues;
+// kVectors: only the eigenvectors (kept V), for a later refinement pass.
+enum Mode { kProject = 0, kEigvals = 1, kVectors = 2 };
 
 // ---------------------------------------------------------------------------
 // Policies

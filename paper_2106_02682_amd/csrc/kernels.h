@@ -11,7 +11,8 @@ namespace vemb {
 // Pair step 3 + Lambda update: C = rho - Lam/mu; rho_t = Pi(C); Lam += mu (rho_t - rho);
 // feas[d] = ||rho_d - rho_t_d||_F^2.  P matrices of size n.
 // vstore (P x n x n doubles, column-major per matrix) keeps each pair's eigenvectors for
-// the warm start of the next iteration; cold = 1 ignores its content.
+// the warm start of the next iteration; cold = 1 ignores its content, cold = 0 starts
+// from it, cold = 2 first restores its orthonormality (kept V from an FP32 solve).
 hipError_t launch_pair_projection(const double* rho, double* Lam, double* rho_t, double* feas, int n, int P,
                                   double mu, int precision, int max_sweeps, int* sweeps, double* vstore, int cold,
                                   hipStream_t st);
@@ -22,8 +23,9 @@ hipError_t launch_momentum_projection(double* Xh, int n_op, int K, int precision
                                       double* vstore, int cold, hipStream_t st);
 
 // Isolated batched projection / eigenvalues (ABI entry points).
+// vstore: eigenvector scratch (batch x n x n, complex doubles for Hermitian), needed by MIXED.
 hipError_t launch_psd_batched(const double* in, double* out, int n, int batch, bool is_complex, int precision,
-                              int max_sweeps, int* sweeps, hipStream_t st);
+                              int max_sweeps, int* sweeps, double* vstore, hipStream_t st);
 hipError_t launch_eigvalsh_batched(const double* in, double* w, int n, int batch, bool is_complex,
                                    int max_sweeps, int* sweeps, hipStream_t st);
 
@@ -35,7 +37,7 @@ hipError_t launch_pair_projection_big(const double* rho, double* Lam, double* rh
 hipError_t launch_momentum_projection_big(double* Xh, int n_op, int K, int precision, int max_sweeps, int* sweeps,
                                           double* vstore, int cold, void* wscr, void* tscr, hipStream_t st);
 hipError_t launch_psd_batched_big(const double* in, double* out, int n, int batch, bool is_complex, int precision,
-                                  int max_sweeps, int* sweeps, void* wscr, void* tscr, hipStream_t st);
+                                  int max_sweeps, int* sweeps, double* vstore, void* wscr, void* tscr, hipStream_t st);
 hipError_t launch_eigvals_big(const double* in, double* w, double* wmin, int n, int count, bool is_complex,
                               int max_sweeps, int* sweeps, void* wscr, void* tscr, hipStream_t st);
 

@@ -20,14 +20,14 @@ STATUS = {0: "VEMB_OK", -1: "VEMB_E_INVALID", -2: "VEMB_E_UNSUPPORTED", -3: "VEM
           -5: "VEMB_E_NUMERIC", -6: "VEMB_E_DIVERGED", -7: "VEMB_E_NOCONV"}
 PAULI = {"I": 0, "X": 1, "Y": 2, "Z": 3}
 OPSET = {"complete": 0, "pauli1": 1}
-PRECISION = {"fp64": 0, "mixed": 1}
+PRECISION = {"fp64": 0, "mixed": 1, "fp32": 2}
 RHO, RHO_TILDE = 0, 1
 
 EXPORTS = [
     "vemb_default_options", "vemb_create_problem", "vemb_problem_info", "vemb_step", "vemb_dual_bound",
     "vemb_primal_energy", "vemb_marginals", "vemb_get_state", "vemb_set_state", "vemb_destroy",
     "vemb_last_error", "vemb_psd_project_batched", "vemb_eigvalsh_batched", "vemb_last_sweeps",
-    "vemb_psd_project_batched_ex", "vemb_set_profiling", "vemb_get_profile",
+    "vemb_psd_project_batched_ex", "vemb_set_profiling", "vemb_get_profile", "vemb_refine",
 ]
 KERNELS = ["pair_update", "pair_xstep", "pair_projection", "cluster_update", "dft_forward", "momentum_projection",
            "dft_inverse", "bound_build", "lambda_min"]
@@ -99,6 +99,7 @@ def lib():
                                       ctypes.POINTER(vp)]
     L.vemb_problem_info.argtypes = [vp, ctypes.POINTER(vemb_info)]
     L.vemb_step.argtypes = [vp, ctypes.c_int]
+    L.vemb_refine.argtypes = [vp, ctypes.c_int]
     L.vemb_dual_bound.argtypes = [vp, _DP]
     L.vemb_primal_energy.argtypes = [vp, _DP, _DP]
     L.vemb_marginals.argtypes = [vp, ctypes.c_int, _DP, _DP]
@@ -187,6 +188,10 @@ def problem_info(h):
 
 def step(h, iters):
     _check(lib().vemb_step(h, int(iters)))
+
+
+def refine(h, iters=1):
+    _check(lib().vemb_refine(h, int(iters)))
 
 
 def dual_bound(h):
@@ -309,6 +314,9 @@ class Problem:
 
     def step(self, iters=1):
         step(self.h, iters)
+
+    def refine(self, iters=1):
+        refine(self.h, iters)
 
     def dual_bound(self):
         return dual_bound(self.h)

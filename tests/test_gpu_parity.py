@@ -67,7 +67,7 @@ def test_projection_complex_fp64(vemb, n, batch):
     assert np.abs(got - want).max() <= 1e-12 * max(1.0, np.abs(C).max()) * max(1, n / 16)
 
 
-@pytest.mark.parametrize("n,batch,cplx", [(256, 3, False), (144, 2, False), (256, 2, True), (128, 3, True)])
+@pytest.mark.parametrize("n,batch,cplx", [(256, 3, False), (160, 2, False), (256, 2, True), (128, 3, True)])
 def test_projection_streamed_solver(vemb, n, batch, cplx):
     """Matrices above the LDS capacity go through the block-streamed solver."""
     C = synth.hermitian_batch(n, batch, tag=15) if cplx else synth.admm_like_batch(n, batch, tag=15)
