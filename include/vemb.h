@@ -92,6 +92,8 @@ typedef struct {
   int32_t warm_refresh; /* eigensolves start from the previous iteration's eigenvectors; every
                            warm_refresh-th iteration (t % warm_refresh == 0) starts cold.
                            0 = default 64; negative = always cold. */
+  int32_t tpb;          /* threads per workgroup of the LDS eigensolver: 256, 512 or 1024;
+                           0 = chosen by the autotuner (vemb_tuned_threads). */
 } vemb_options;
 
 typedef struct vemb_problem vemb_problem;
@@ -194,6 +196,17 @@ typedef struct {
 
 int vemb_set_profiling(vemb_problem* p, int enable);
 int vemb_get_profile(vemb_problem* p, vemb_profile* out);
+
+/* Autotuner of the LDS eigensolver's threads per workgroup (256 / 512 / 1024) for
+ * batches of `batch` n x n matrices: times the candidates on seeded synthetic
+ * matrices with HIP events on hip_stream and returns the fastest (>0), or a
+ * negative status.  Results are cached per (device, n, real/complex, precision,
+ * batch rounded up to a power of two) in memory and in the text file
+ * $VEMB_TUNE_CACHE (default $HOME/.cache/vemb_tune.txt; "none" = memory only).
+ * Synchronises the stream.  vemb_create_problem calls it unless opts->tpb is set. */
+int vemb_tuned_threads(int n, int is_complex, int precision, int batch, void* hip_stream);
+/* Threads per workgroup the problem's pair and momentum eigensolves use. */
+int vemb_problem_threads(const vemb_problem* p, int* pair_tpb, int* momentum_tpb);
 
 void vemb_destroy(vemb_problem* p);
 const char* vemb_last_error(void);

@@ -4,7 +4,11 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -41,6 +45,7 @@ struct vemb_problem {
   std::vector<hipEvent_t> free_events;
   double prof_ms[VEMB_K_COUNT] = {};
   bool v_valid = false;  // Vpair / Vmom hold eigenvectors of the previous iteration
+  int tpb_pair = 256, tpb_mom = 256;  // threads per workgroup of the LDS solver (autotuned)
   int64_t prof_n[VEMB_K_COUNT] = {};
 };
 
@@ -136,6 +141,138 @@ int drain_marks(vemb_problem* p) {
   }
   p->marks.clear();
   return VEMB_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Autotuner: threads per workgroup of the LDS Jacobi solver (256 / 512 / 1024),
+// chosen per (device, n, real/complex, precision, batch size rounded up to a
+// power of two) by timing the candidates with HIP events on seeded synthetic
+// matrices shaped like ADMM iterates.  Results are cached in memory and in a
+// text file: $VEMB_TUNE_CACHE, default $HOME/.cache/vemb_tune.txt ("none"
+// keeps the cache in memory only).
+// ---------------------------------------------------------------------------
+std::mutex g_tune_mu;
+std::map<std::string, int> g_tune;
+bool g_tune_loaded = false;
+
+std::string tune_path() {
+  const char* env = std::getenv("VEMB_TUNE_CACHE");
+  if (env) return std::string(env) == "none" ? std::string() : std::string(env);
+  const char* home = std::getenv("HOME");
+  return home ? std::string(home) + "/.cache/vemb_tune.txt" : std::string();
+}
+
+void tune_load() {
+  if (g_tune_loaded) return;
+  g_tune_loaded = true;
+  const std::string path = tune_path();
+  if (path.empty()) return;
+  if (FILE* f = std::fopen(path.c_str(), "r")) {
+    char key[256];
+    int v = 0;
+    while (std::fscanf(f, "%255s %d", key, &v) == 2) g_tune[key] = v;
+    std::fclose(f);
+  }
+}
+
+void tune_store(const std::string& key, int v) {
+  g_tune[key] = v;
+  const std::string path = tune_path();
+  if (path.empty()) return;
+  const size_t slash = path.rfind('/');
+  if (slash != std::string::npos) {
+    const std::string dir = path.substr(0, slash);
+    std::string cmd_dir = dir;  // create the directory if missing (best effort)
+    (void)std::system(("mkdir -p '" + cmd_dir + "' 2>/dev/null").c_str());
+  }
+  if (FILE* f = std::fopen(path.c_str(), "a")) {
+    std::fprintf(f, "%s %d\n", key.c_str(), v);
+    std::fclose(f);
+  }
+}
+
+// Seeded symmetric / Hermitian test matrices: diagonal ~ U[0, 2/n], off-diagonal ~ U[-1, 1]/(2n),
+// roughly half of the eigenvalues negative, like rho - Lambda/mu.
+void synth_batch(std::vector<double>& h, int n, int count, bool cplx) {
+  const int w = cplx ? 2 : 1;
+  h.assign((size_t)count * n * n * w, 0.0);
+  uint64_t x = 0x9E3779B97F4A7C15ull ^ ((uint64_t)n << 32) ^ (uint64_t)count;
+  auto next = [&]() {  // xorshift64*
+    x ^= x >> 12;
+    x ^= x << 25;
+    x ^= x >> 27;
+    return (double)((x * 0x2545F4914F6CDD1Dull) >> 11) * (1.0 / 9007199254740992.0);
+  };
+  for (int b = 0; b < count; ++b)
+    for (int i = 0; i < n; ++i)
+      for (int j = i; j < n; ++j) {
+        double re = (i == j) ? 2.0 * next() / n - 0.5 / n : (2.0 * next() - 1.0) / (2.0 * n);
+        double im = (cplx && i != j) ? (2.0 * next() - 1.0) / (2.0 * n) : 0.0;
+        const size_t o1 = ((size_t)b * n * n + (size_t)i * n + j) * w, o2 = ((size_t)b * n * n + (size_t)j * n + i) * w;
+        h[o1] = re;
+        h[o2] = re;
+        if (cplx) {
+          h[o1 + 1] = im;
+          h[o2 + 1] = -im;
+        }
+      }
+}
+
+int tuned_tpb(int n, bool cplx, int precision, int count, hipStream_t st) {
+  const int np = (n + 1) & ~1;
+  if (np < 16 || np > 64 || count <= 0) return 256;  // one variant only
+  int bucket = 1;
+  while (bucket < count) bucket <<= 1;
+  bucket = std::min(bucket, 4096);
+  int dev = 0;
+  hipGetDevice(&dev);
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return 256;
+  char key[256];
+  std::snprintf(key, sizeof(key), "%s:cu%d:n%d:%s:p%d:b%d", prop.gcnArchName, prop.multiProcessorCount, n,
+                cplx ? "c" : "r", precision, bucket);
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  tune_load();
+  auto it = g_tune.find(key);
+  if (it != g_tune.end()) return it->second;
+  std::vector<double> h;
+  synth_batch(h, n, bucket, cplx);
+  const size_t bytes = h.size() * sizeof(double);
+  double *din = nullptr, *dout = nullptr, *dv = nullptr;
+  int best = 256;
+  if (hipMalloc(&din, bytes) == hipSuccess && hipMalloc(&dout, bytes) == hipSuccess &&
+      hipMalloc(&dv, bytes) == hipSuccess && hipMemcpyAsync(din, h.data(), bytes, hipMemcpyHostToDevice, st) == hipSuccess) {
+    hipEvent_t e0, e1;
+    hipEventCreate(&e0);
+    hipEventCreate(&e1);
+    float best_ms = 1e30f;
+    for (int tpb : {256, 512, 1024}) {
+      float t_min = 1e30f;
+      bool ok = true;
+      for (int rep = 0; rep < 3 && ok; ++rep) {
+        hipEventRecord(e0, st);
+        ok = launch_psd_batched(din, dout, n, bucket, cplx, precision, 40, nullptr, dv, tpb, st) == hipSuccess;
+        hipEventRecord(e1, st);
+        hipEventSynchronize(e1);
+        float ms = 0.f;
+        hipEventElapsedTime(&ms, e0, e1);
+        if (rep > 0) t_min = std::min(t_min, ms);  // first launch warms up
+      }
+      if (ok && t_min < best_ms) {
+        best_ms = t_min;
+        best = tpb;
+      }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+  }
+  hipStreamSynchronize(st);
+  if (din) hipFree(din);
+  if (dout) hipFree(dout);
+  if (dv) hipFree(dv);
+  hipGetLastError();  // a failed candidate must not leak its error into the caller
+  tune_store(key, best);
+  return best;
 }
 
 bool all_finite(const double* v, size_t count) {
@@ -273,6 +410,12 @@ int vemb_create_problem(const vemb_hamiltonian* H, const vemb_lattice* lat, cons
   a.wk = p->wk;
   a.ops = p->ops;
   if ((rc = upload_initial_state(p))) return cleanup(rc);
+  if (o.tpb == 256 || o.tpb == 512 || o.tpb == 1024) {
+    p->tpb_pair = p->tpb_mom = o.tpb;
+  } else {
+    p->tpb_pair = tuned_tpb(n, false, o.precision, P, s);
+    p->tpb_mom = tuned_tpb(k, true, o.precision, Ku, s);
+  }
   *out = p;
   return VEMB_OK;
 }
@@ -307,7 +450,7 @@ int run_iterations(vemb_problem* p, int iters, int prec) {
         return launch_pair_projection_big(a.rho, a.Lam, a.rho_t, a.feas, a.n, a.P, a.mu, prec, ms, a.sweeps, a.Vpair,
                                           cold, a.wscr_pair, a.tscr_pair, s);
       return launch_pair_projection(a.rho, a.Lam, a.rho_t, a.feas, a.n, a.P, a.mu, prec, ms, a.sweeps, a.Vpair, cold,
-                                    s);
+                                    p->tpb_pair, s);
     }));
     VEMB_TRY(timed(p, VEMB_K_CLUSTER, "cluster update", [&] { return launch_cluster_update(a, s); }));
     VEMB_TRY(timed(p, VEMB_K_DFT_FWD, "forward DFT", [&] { return launch_dft_forward(a, s); }));
@@ -315,7 +458,7 @@ int run_iterations(vemb_problem* p, int iters, int prec) {
       if (a.n_op > 64)
         return launch_momentum_projection_big(a.Xh, a.n_op, a.Ku, prec, ms, a.sweeps + a.P, a.Vmom, cold, a.wscr_mom,
                                               a.tscr_mom, s);
-      return launch_momentum_projection(a.Xh, a.n_op, a.Ku, prec, ms, a.sweeps + a.P, a.Vmom, cold, s);
+      return launch_momentum_projection(a.Xh, a.n_op, a.Ku, prec, ms, a.sweeps + a.P, a.Vmom, cold, p->tpb_mom, s);
     }));
     VEMB_TRY(timed(p, VEMB_K_DFT_INV, "inverse DFT", [&] { return launch_dft_inverse(a, s); }));
     p->v_valid = true;
@@ -443,6 +586,18 @@ int vemb_set_state(vemb_problem* p, const vemb_state* st) {
   return VEMB_OK;
 }
 
+int vemb_tuned_threads(int n, int is_complex, int precision, int batch, void* hip_stream) {
+  if (n <= 0 || batch <= 0) return fail(VEMB_E_INVALID, "bad arguments to vemb_tuned_threads");
+  return tuned_tpb(n, is_complex != 0, precision, batch, static_cast<hipStream_t>(hip_stream));
+}
+
+int vemb_problem_threads(const vemb_problem* p, int* pair_tpb, int* momentum_tpb) {
+  if (!p) return fail(VEMB_E_INVALID, "NULL problem");
+  if (pair_tpb) *pair_tpb = p->tpb_pair;
+  if (momentum_tpb) *momentum_tpb = p->tpb_mom;
+  return VEMB_OK;
+}
+
 int vemb_last_sweeps(vemb_problem* p, int* pair_max, int* momentum_max) {
   if (!p) return fail(VEMB_E_INVALID, "NULL problem");
   std::vector<int> sw(p->P + p->Ku);
@@ -524,7 +679,9 @@ int vemb_psd_project_batched_ex(const double* in, double* out, int n, int batch,
   Scratch sc;
   if (need_v && hipMalloc(&sc.v, bytes) != hipSuccess) return fail(VEMB_E_NOMEM, "eigenvector scratch");
   if (lds) {
-    VEMB_TRY(hip_rc(launch_psd_batched(in, out, n, batch, is_complex != 0, precision, ms, sweeps, (double*)sc.v, st),
+    const int tpb = tuned_tpb(n, is_complex != 0, precision, batch, st);
+    VEMB_TRY(hip_rc(launch_psd_batched(in, out, n, batch, is_complex != 0, precision, ms, sweeps, (double*)sc.v, tpb,
+                                       st),
                     "batched projection"));
     return sc.v ? hip_rc(hipStreamSynchronize(st), "batched projection sync") : VEMB_OK;
   }

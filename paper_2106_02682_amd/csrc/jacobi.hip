@@ -31,21 +31,21 @@ namespace {
 // Core kernel.  S: compute scalar (double, float, cplx<double>, cplx<float>);
 // NMAX: capacity (n <= NMAX, NMAX even); Policy: load / store of one matrix.
 // ---------------------------------------------------------------------------
-template <typename S, int NMAX, int MODE, bool WARM, typename Policy>
-__global__ void __launch_bounds__(kThreads) jacobi_kernel(Policy pol, int n, int max_sweeps, void* vstore_raw,
+template <typename S, int NMAX, int MODE, bool WARM, int NT, typename Policy>
+__global__ void __launch_bounds__(NT) jacobi_kernel(Policy pol, int n, int max_sweeps, void* vstore_raw,
                                                           int cold) {
   using R = typename scalar_traits<S>::real;
   using D = typename wide<S>::type;  // FP64 storage type of V
   constexpr int LD = NMAX + 1;
   constexpr int NPAIR = NMAX / 2;
-  constexpr int G0 = kThreads / NPAIR;
+  constexpr int G0 = NT / NPAIR;
   constexpr int G = G0 > 64 ? 64 : G0;  // lanes per pair, within one wavefront
   constexpr int RPL = (NMAX + G - 1) / G;  // rows per lane
   __shared__ S W[NMAX * LD];
   __shared__ S V[WARM ? NMAX * LD : 1];
   D* vstore = static_cast<D*>(vstore_raw);
-  __shared__ R red[kThreads];
-  __shared__ double red_d[kThreads];
+  __shared__ R red[NT];
+  __shared__ double red_d[NT];
   __shared__ R colf[NMAX];
   __shared__ int active[NMAX];
   __shared__ int nact_s;
@@ -54,7 +54,7 @@ __global__ void __launch_bounds__(kThreads) jacobi_kernel(Policy pol, int n, int
   const int mat = blockIdx.x;
   const int tid = threadIdx.x;
   const int nn = n * n;
-  constexpr int NOUT = (NMAX * NMAX + kThreads - 1) / kThreads;
+  constexpr int NOUT = (NMAX * NMAX + NT - 1) / NT;
 
   // 0. cold == 2: the kept V comes from a lower-precision solve; restore its
   // orthonormality first with one Newton-Schulz step V <- V (3I - V^H V)/2
@@ -62,27 +62,27 @@ __global__ void __launch_bounds__(kThreads) jacobi_kernel(Policy pol, int n, int
   if constexpr (WARM) {
     if (cold == 2) {
       const D* vin = vstore + (size_t)mat * n * n;
-      for (int idx = tid; idx < nn; idx += kThreads) {
+      for (int idx = tid; idx < nn; idx += NT) {
         const int j = idx / n, i = idx - (idx / n) * n;
         V[j * LD + i] = narrow<S>(vin[idx]);
       }
       __syncthreads();
       S outv[NOUT];
       int c = 0;
-      for (int idx = tid; idx < nn; idx += kThreads, ++c) {
+      for (int idx = tid; idx < nn; idx += NT, ++c) {
         const int j = idx / n, i = idx - (idx / n) * n;
         S acc = s_zero<S>();
         for (int k = 0; k < n; ++k) acc = acc + conj_mul(V[i * LD + k], V[j * LD + k]);
         outv[c] = acc;  // G(i, j)
       }
       c = 0;
-      for (int idx = tid; idx < nn; idx += kThreads, ++c) {
+      for (int idx = tid; idx < nn; idx += NT, ++c) {
         const int j = idx / n, i = idx - (idx / n) * n;
         W[j * LD + i] = outv[c];
       }
       __syncthreads();
       c = 0;
-      for (int idx = tid; idx < nn; idx += kThreads, ++c) {
+      for (int idx = tid; idx < nn; idx += NT, ++c) {
         const int j = idx / n, i = idx - (idx / n) * n;
         S acc = s_zero<S>();
         for (int k = 0; k < n; ++k) acc = acc + V[k * LD + i] * W[j * LD + k];
@@ -90,7 +90,7 @@ __global__ void __launch_bounds__(kThreads) jacobi_kernel(Policy pol, int n, int
       }
       __syncthreads();
       c = 0;
-      for (int idx = tid; idx < nn; idx += kThreads, ++c) {
+      for (int idx = tid; idx < nn; idx += NT, ++c) {
         const int j = idx / n, i = idx - (idx / n) * n;
         V[j * LD + i] = outv[c];
       }
@@ -99,12 +99,12 @@ __global__ void __launch_bounds__(kThreads) jacobi_kernel(Policy pol, int n, int
   }
 
   // 1. load C (column j at W[j*LD]) and take its Hermitian part
-  for (int idx = tid; idx < nn; idx += kThreads) {
+  for (int idx = tid; idx < nn; idx += NT) {
     const int i = idx / n, j = idx - (idx / n) * n;
     W[j * LD + i] = pol.template load<S>(mat, i, j);
   }
   __syncthreads();
-  for (int idx = tid; idx < nn; idx += kThreads) {
+  for (int idx = tid; idx < nn; idx += NT) {
     const int i = idx / n, j = idx - (idx / n) * n;
     if (i < j) {
       const S h = hermitian_avg(W[j * LD + i], W[i * LD + j]);
@@ -120,7 +120,7 @@ __global__ void __launch_bounds__(kThreads) jacobi_kernel(Policy pol, int n, int
   R shift;
   {
     R v = R(0);
-    for (int i = tid; i < n; i += kThreads) {
+    for (int i = tid; i < n; i += NT) {
       R rad = R(0);
       for (int j = 0; j < n; ++j)
         if (j != i) rad += modulus(W[j * LD + i]);
@@ -135,7 +135,7 @@ __global__ void __launch_bounds__(kThreads) jacobi_kernel(Policy pol, int n, int
     shift = block_max(v, red);
     if constexpr (MODE != kEigvals) shift *= R(0.5);
   }
-  for (int i = tid; i < n; i += kThreads) W[i * LD + i] = add_real(W[i * LD + i], shift);
+  for (int i = tid; i < n; i += NT) W[i * LD + i] = add_real(W[i * LD + i], shift);
   __syncthreads();
   // Warm start: W = B V_prev, where V_prev holds the eigenvectors of the previous
   // solve of this matrix slot.  B V_prev is nearly column-orthogonal when the
@@ -143,13 +143,13 @@ __global__ void __launch_bounds__(kThreads) jacobi_kernel(Policy pol, int n, int
   if constexpr (WARM) {
     const D* vin = vstore + (size_t)mat * n * n;  // column-major: V(i, j) at [j*n + i]
     if (cold == 1) {
-      for (int idx = tid; idx < nn; idx += kThreads) {
+      for (int idx = tid; idx < nn; idx += NT) {
         const int j = idx / n, i = idx - (idx / n) * n;
         V[j * LD + i] = (i == j) ? one_of<S>() : s_zero<S>();
       }
     } else {
       if (cold != 2) {  // (cold == 2 loaded and orthonormalised V above)
-        for (int idx = tid; idx < nn; idx += kThreads) {
+        for (int idx = tid; idx < nn; idx += NT) {
           const int j = idx / n, i = idx - (idx / n) * n;
           V[j * LD + i] = narrow<S>(vin[idx]);
         }
@@ -157,7 +157,7 @@ __global__ void __launch_bounds__(kThreads) jacobi_kernel(Policy pol, int n, int
       __syncthreads();
       S outv[NOUT];
       int c = 0;
-      for (int idx = tid; idx < nn; idx += kThreads, ++c) {
+      for (int idx = tid; idx < nn; idx += NT, ++c) {
         const int j = idx / n, i = idx - (idx / n) * n;
         S acc = s_zero<S>();
         for (int k = 0; k < n; ++k) acc = acc + W[k * LD + i] * V[j * LD + k];
@@ -165,7 +165,7 @@ __global__ void __launch_bounds__(kThreads) jacobi_kernel(Policy pol, int n, int
       }
       __syncthreads();
       c = 0;
-      for (int idx = tid; idx < nn; idx += kThreads, ++c) {
+      for (int idx = tid; idx < nn; idx += NT, ++c) {
         const int j = idx / n, i = idx - (idx / n) * n;
         W[j * LD + i] = outv[c];
       }
@@ -180,7 +180,7 @@ __global__ void __launch_bounds__(kThreads) jacobi_kernel(Policy pol, int n, int
   R floor2;
   {
     R v = R(0);
-    for (int idx = tid; idx < nn; idx += kThreads) {
+    for (int idx = tid; idx < nn; idx += NT) {
       const int i = idx / n, j = idx - (idx / n) * n;
       v += abs2(W[j * LD + i]);
     }
@@ -264,7 +264,7 @@ __global__ void __launch_bounds__(kThreads) jacobi_kernel(Policy pol, int n, int
   if (tid == 0) pol.record_sweeps(mat, sweep);
   if constexpr (WARM) {
     D* vout = vstore + (size_t)mat * n * n;
-    for (int idx = tid; idx < nn; idx += kThreads) {
+    for (int idx = tid; idx < nn; idx += NT) {
       const int j = idx / n, i = idx - (idx / n) * n;
       vout[idx] = widen(V[j * LD + i]);
     }
@@ -272,7 +272,7 @@ __global__ void __launch_bounds__(kThreads) jacobi_kernel(Policy pol, int n, int
   if constexpr (MODE == kVectors) return;
 
   // 4. column norms sigma_j = lambda_j(B)
-  for (int j = tid; j < n; j += kThreads) {
+  for (int j = tid; j < n; j += NT) {
     R s2 = R(0);
     for (int i = 0; i < n; ++i) s2 += abs2(W[j * LD + i]);
     colf[j] = dev_sqrt(s2);
@@ -281,7 +281,7 @@ __global__ void __launch_bounds__(kThreads) jacobi_kernel(Policy pol, int n, int
 
   if constexpr (MODE == kEigvals) {
     // eigenvalues of C: sigma_j - s, sorted ascending by rank
-    for (int j = tid; j < n; j += kThreads) {
+    for (int j = tid; j < n; j += NT) {
       const R v = colf[j] - shift;
       int rank = 0;
       for (int k = 0; k < n; ++k) {
@@ -301,7 +301,7 @@ __global__ void __launch_bounds__(kThreads) jacobi_kernel(Policy pol, int n, int
     }
     __syncthreads();
     const int nact = nact_s;
-    for (int idx = tid; idx < nact * n; idx += kThreads) {
+    for (int idx = tid; idx < nact * n; idx += NT) {
       const int jj = idx / n, i = idx - (idx / n) * n;
       const int j = active[jj];
       const R sg = colf[j];
@@ -310,7 +310,7 @@ __global__ void __launch_bounds__(kThreads) jacobi_kernel(Policy pol, int n, int
     }
     __syncthreads();
     double part = 0.0;
-    for (int idx = tid; idx < nn; idx += kThreads) {
+    for (int idx = tid; idx < nn; idx += NT) {
       const int i = idx / n, k = idx - (idx / n) * n;
       S acc = s_zero<S>();
       for (int jj = 0; jj < nact; ++jj) {
@@ -327,32 +327,44 @@ __global__ void __launch_bounds__(kThreads) jacobi_kernel(Policy pol, int n, int
 
 // vstore == nullptr: cold solve without eigenvector storage.  Otherwise the
 // eigenvectors of every matrix slot are read (unless cold) and written back.
+// tpb: threads per workgroup (256, 512 or 1024; others fall back to 256).  More
+// threads give each column pair more lanes (fewer rows per lane) and put up to
+// four wavefronts on each SIMD to hide the latency of a round.
+template <typename S, int MODE, int NM, int NT, typename Policy>
+hipError_t launch_one(const Policy& pol, int n, int count, int max_sweeps, hipStream_t st, void* vstore, int cold) {
+  if (vstore)
+    hipLaunchKernelGGL((jacobi_kernel<S, NM, MODE, true, NT, Policy>), dim3(count), dim3(NT), 0, st, pol, n,
+                       max_sweeps, vstore, cold);
+  else
+    hipLaunchKernelGGL((jacobi_kernel<S, NM, MODE, false, NT, Policy>), dim3(count), dim3(NT), 0, st, pol, n,
+                       max_sweeps, nullptr, 1);
+  return hipGetLastError();
+}
+
+template <typename S, int MODE, int NM, typename Policy>
+hipError_t launch_tpb(const Policy& pol, int n, int count, int max_sweeps, hipStream_t st, void* vstore, int cold,
+                      int tpb) {
+  if constexpr (NM >= 16 && NM <= 64) {
+    if (tpb == 1024) return launch_one<S, MODE, NM, 1024>(pol, n, count, max_sweeps, st, vstore, cold);
+    if (tpb == 512) return launch_one<S, MODE, NM, 512>(pol, n, count, max_sweeps, st, vstore, cold);
+  }
+  return launch_one<S, MODE, NM, 256>(pol, n, count, max_sweeps, st, vstore, cold);
+}
+
 template <typename S, int MODE, typename Policy>
 hipError_t dispatch(const Policy& pol, int n, int count, int max_sweeps, hipStream_t st, void* vstore = nullptr,
-                    int cold = 1) {
+                    int cold = 1, int tpb = 256) {
   if (count <= 0) return hipSuccess;
   const int np = (n + 1) & ~1;
-  dim3 grid(count), block(kThreads);
-#define VEMB_CASE(NM)                                                                                     \
-  if (np <= NM) {                                                                                         \
-    if (vstore)                                                                                           \
-      hipLaunchKernelGGL((jacobi_kernel<S, NM, MODE, true, Policy>), grid, block, 0, st, pol, n, max_sweeps, \
-                         vstore, cold);                                                                   \
-    else                                                                                                  \
-      hipLaunchKernelGGL((jacobi_kernel<S, NM, MODE, false, Policy>), grid, block, 0, st, pol, n,         \
-                         max_sweeps, nullptr, 1);                                                         \
-    return hipGetLastError();                                                                             \
-  }
-  VEMB_CASE(4)
-  VEMB_CASE(8)
-  VEMB_CASE(16)
-  VEMB_CASE(32)
-  VEMB_CASE(64)
-#undef VEMB_CASE
+  if (np <= 4) return launch_tpb<S, MODE, 4>(pol, n, count, max_sweeps, st, vstore, cold, tpb);
+  if (np <= 8) return launch_tpb<S, MODE, 8>(pol, n, count, max_sweeps, st, vstore, cold, tpb);
+  if (np <= 16) return launch_tpb<S, MODE, 16>(pol, n, count, max_sweeps, st, vstore, cold, tpb);
+  if (np <= 32) return launch_tpb<S, MODE, 32>(pol, n, count, max_sweeps, st, vstore, cold, tpb);
+  if (np <= 64) return launch_tpb<S, MODE, 64>(pol, n, count, max_sweeps, st, vstore, cold, tpb);
   if constexpr (!scalar_traits<S>::is_complex) {
     if (np <= 128 && !vstore) {
-      hipLaunchKernelGGL((jacobi_kernel<S, 128, MODE, false, Policy>), grid, block, 0, st, pol, n, max_sweeps,
-                         nullptr, 1);
+      hipLaunchKernelGGL((jacobi_kernel<S, 128, MODE, false, 256, Policy>), dim3(count), dim3(256), 0, st, pol, n,
+                         max_sweeps, nullptr, 1);
       return hipGetLastError();
     }
   }
@@ -365,41 +377,41 @@ hipError_t dispatch(const Policy& pol, int n, int count, int max_sweeps, hipStre
 // then one FP64 sweep warm-started from them and the FP64 rebuild.
 template <typename S32, typename S64, typename Policy>
 hipError_t by_precision(const Policy& pol, const Policy& pol_quiet, int n, int count, int precision, int max_sweeps,
-                        double* vstore, int cold, hipStream_t st) {
-  if (precision == VEMB_FP32) return dispatch<S32, kProject>(pol, n, count, max_sweeps, st, vstore, cold);
+                        double* vstore, int cold, int tpb, hipStream_t st) {
+  if (precision == VEMB_FP32) return dispatch<S32, kProject>(pol, n, count, max_sweeps, st, vstore, cold, tpb);
   if (precision == VEMB_MIXED && vstore) {
-    hipError_t e = dispatch<S32, kVectors>(pol, n, count, max_sweeps, st, vstore, cold);
+    hipError_t e = dispatch<S32, kVectors>(pol, n, count, max_sweeps, st, vstore, cold, tpb);
     if (e != hipSuccess) return e;
-    return dispatch<S64, kProject>(pol_quiet, n, count, 2, st, vstore, 2);
+    return dispatch<S64, kProject>(pol_quiet, n, count, 2, st, vstore, 2, tpb);
   }
-  return dispatch<S64, kProject>(pol, n, count, max_sweeps, st, vstore, cold);
+  return dispatch<S64, kProject>(pol, n, count, max_sweeps, st, vstore, cold, tpb);
 }
 
 hipError_t launch_pair_projection(const double* rho, double* Lam, double* rho_t, double* feas, int n, int P,
                                   double mu, int precision, int max_sweeps, int* sweeps, double* vstore, int cold,
-                                  hipStream_t st) {
+                                  int tpb, hipStream_t st) {
   PairPolicy pol{rho, Lam, rho_t, feas, sweeps, n, mu};
   PairPolicy quiet{rho, Lam, rho_t, feas, nullptr, n, mu};
-  return by_precision<float, double>(pol, quiet, n, P, precision, max_sweeps, vstore, cold, st);
+  return by_precision<float, double>(pol, quiet, n, P, precision, max_sweeps, vstore, cold, tpb, st);
 }
 
 hipError_t launch_momentum_projection(double* Xh, int n_op, int K, int precision, int max_sweeps, int* sweeps,
-                                      double* vstore, int cold, hipStream_t st) {
+                                      double* vstore, int cold, int tpb, hipStream_t st) {
   MomentumPolicy pol{Xh, sweeps, n_op};
   MomentumPolicy quiet{Xh, nullptr, n_op};
-  return by_precision<cplx<float>, cplx<double>>(pol, quiet, n_op, K, precision, max_sweeps, vstore, cold, st);
+  return by_precision<cplx<float>, cplx<double>>(pol, quiet, n_op, K, precision, max_sweeps, vstore, cold, tpb, st);
 }
 
 hipError_t launch_psd_batched(const double* in, double* out, int n, int batch, bool is_complex, int precision,
-                              int max_sweeps, int* sweeps, double* vstore, hipStream_t st) {
+                              int max_sweeps, int* sweeps, double* vstore, int tpb, hipStream_t st) {
   if (is_complex) {
     ArrayPolicy<true> pol{in, out, nullptr, nullptr, sweeps, n};
     ArrayPolicy<true> quiet{in, out, nullptr, nullptr, nullptr, n};
-    return by_precision<cplx<float>, cplx<double>>(pol, quiet, n, batch, precision, max_sweeps, vstore, 1, st);
+    return by_precision<cplx<float>, cplx<double>>(pol, quiet, n, batch, precision, max_sweeps, vstore, 1, tpb, st);
   }
   ArrayPolicy<false> pol{in, out, nullptr, nullptr, sweeps, n};
   ArrayPolicy<false> quiet{in, out, nullptr, nullptr, nullptr, n};
-  return by_precision<float, double>(pol, quiet, n, batch, precision, max_sweeps, vstore, 1, st);
+  return by_precision<float, double>(pol, quiet, n, batch, precision, max_sweeps, vstore, 1, tpb, st);
 }
 
 hipError_t launch_eigvalsh_batched(const double* in, double* w, int n, int batch, bool is_complex, int max_sweeps,

@@ -82,13 +82,13 @@ template <typename S> __device__ inline S one_of() { return S(1); }
 template <> __device__ inline cplx<double> one_of<cplx<double>>() { return {1.0, 0.0}; }
 template <> __device__ inline cplx<float> one_of<cplx<float>>() { return {1.0f, 0.0f}; }
 
-// Block-wide reductions through LDS (kThreads threads).
+// Block-wide reductions through LDS (blockDim.x threads, a power of two; red holds blockDim.x).
 template <typename R>
 __device__ R block_max(R v, R* red) {
   const int t = threadIdx.x;
   red[t] = v;
   __syncthreads();
-  for (int s = kThreads / 2; s > 0; s >>= 1) {
+  for (int s = (int)blockDim.x / 2; s > 0; s >>= 1) {
     if (t < s) red[t] = red[t] > red[t + s] ? red[t] : red[t + s];
     __syncthreads();
   }
@@ -102,7 +102,7 @@ __device__ R block_sum_r(R v, R* red) {
   const int t = threadIdx.x;
   red[t] = v;
   __syncthreads();
-  for (int s = kThreads / 2; s > 0; s >>= 1) {
+  for (int s = (int)blockDim.x / 2; s > 0; s >>= 1) {
     if (t < s) red[t] += red[t + s];
     __syncthreads();
   }
@@ -115,7 +115,7 @@ __device__ double block_sum(double v, double* red) {
   const int t = threadIdx.x;
   red[t] = v;
   __syncthreads();
-  for (int s = kThreads / 2; s > 0; s >>= 1) {
+  for (int s = (int)blockDim.x / 2; s > 0; s >>= 1) {
     if (t < s) red[t] += red[t + s];
     __syncthreads();
   }

@@ -15,17 +15,18 @@ namespace vemb {
 // from it, cold = 2 first restores its orthonormality (kept V from an FP32 solve).
 hipError_t launch_pair_projection(const double* rho, double* Lam, double* rho_t, double* feas, int n, int P,
                                   double mu, int precision, int max_sweeps, int* sweeps, double* vstore, int cold,
-                                  hipStream_t st);
+                                  int tpb, hipStream_t st);
 
 // Steps 8: Y_k = Pi((Xh_k + Xh_k^H)/2), in place on K complex n_op x n_op blocks
 // (interleaved re/im doubles).
 hipError_t launch_momentum_projection(double* Xh, int n_op, int K, int precision, int max_sweeps, int* sweeps,
-                                      double* vstore, int cold, hipStream_t st);
+                                      double* vstore, int cold, int tpb, hipStream_t st);
 
 // Isolated batched projection / eigenvalues (ABI entry points).
 // vstore: eigenvector scratch (batch x n x n, complex doubles for Hermitian), needed by MIXED.
+// tpb: threads per workgroup of the LDS solver (256 / 512 / 1024), see the autotuner in api.cpp.
 hipError_t launch_psd_batched(const double* in, double* out, int n, int batch, bool is_complex, int precision,
-                              int max_sweeps, int* sweeps, double* vstore, hipStream_t st);
+                              int max_sweeps, int* sweeps, double* vstore, int tpb, hipStream_t st);
 hipError_t launch_eigvalsh_batched(const double* in, double* w, int n, int batch, bool is_complex,
                                    int max_sweeps, int* sweeps, hipStream_t st);
 

@@ -28,6 +28,7 @@ EXPORTS = [
     "vemb_primal_energy", "vemb_marginals", "vemb_get_state", "vemb_set_state", "vemb_destroy",
     "vemb_last_error", "vemb_psd_project_batched", "vemb_eigvalsh_batched", "vemb_last_sweeps",
     "vemb_psd_project_batched_ex", "vemb_set_profiling", "vemb_get_profile", "vemb_refine",
+    "vemb_tuned_threads", "vemb_problem_threads",
 ]
 KERNELS = ["pair_update", "pair_xstep", "pair_projection", "cluster_update", "dft_forward", "momentum_projection",
            "dft_inverse", "bound_build", "lambda_min"]
@@ -59,7 +60,7 @@ class vemb_clusters(ctypes.Structure):
 class vemb_options(ctypes.Structure):
     _fields_ = [("mu", ctypes.c_double), ("nu", ctypes.c_double), ("eps", ctypes.c_double),
                 ("opset", ctypes.c_int32), ("precision", ctypes.c_int32), ("max_sweeps", ctypes.c_int32),
-                ("sign", ctypes.c_int32), ("warm_refresh", ctypes.c_int32)]
+                ("sign", ctypes.c_int32), ("warm_refresh", ctypes.c_int32), ("tpb", ctypes.c_int32)]
 
 
 class vemb_info(ctypes.Structure):
@@ -100,6 +101,8 @@ def lib():
     L.vemb_problem_info.argtypes = [vp, ctypes.POINTER(vemb_info)]
     L.vemb_step.argtypes = [vp, ctypes.c_int]
     L.vemb_refine.argtypes = [vp, ctypes.c_int]
+    L.vemb_tuned_threads.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp]
+    L.vemb_problem_threads.argtypes = [vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
     L.vemb_dual_bound.argtypes = [vp, _DP]
     L.vemb_primal_energy.argtypes = [vp, _DP, _DP]
     L.vemb_marginals.argtypes = [vp, ctypes.c_int, _DP, _DP]
@@ -152,7 +155,7 @@ def default_options():
 
 
 def create_problem(terms, extent, cluster, opset="complete", precision="fp64", mu=10.0, nu=10.0, eps=2.0,
-                   max_sweeps=40, sign=-1, warm_refresh=64, stream=None):
+                   max_sweeps=40, sign=-1, warm_refresh=64, tpb=0, stream=None):
     """Terms in the ``synth`` format: (coeff, ((pauli, (ox, oy)), ...))."""
     arr = (vemb_term * max(1, len(terms)))()
     for t, (coeff, factors) in enumerate(terms):
@@ -173,6 +176,7 @@ def create_problem(terms, extent, cluster, opset="complete", precision="fp64", m
     o.max_sweeps = max_sweeps
     o.sign = sign
     o.warm_refresh = warm_refresh
+    o.tpb = tpb
     h = ctypes.c_void_p()
     st = stream if stream is not None else current_stream()
     _check(lib().vemb_create_problem(ctypes.byref(H), ctypes.byref(lat), ctypes.byref(cl), ctypes.byref(o), st,
@@ -281,6 +285,20 @@ def get_profile(h):
     pr = vemb_profile()
     _check(lib().vemb_get_profile(h, ctypes.byref(pr)))
     return {k: (pr.ms[i], pr.launches[i]) for i, k in enumerate(KERNELS)}
+
+
+def tuned_threads(n, is_complex=False, precision="fp64", batch=1, stream=None):
+    st = stream if stream is not None else current_stream()
+    rc = lib().vemb_tuned_threads(int(n), int(is_complex), PRECISION[precision], int(batch), st)
+    if rc < 0:
+        _check(rc)
+    return rc
+
+
+def problem_threads(h):
+    a, b = ctypes.c_int(), ctypes.c_int()
+    _check(lib().vemb_problem_threads(h, ctypes.byref(a), ctypes.byref(b)))
+    return a.value, b.value
 
 
 def last_sweeps(h):
