@@ -231,6 +231,36 @@ int vemb_psd_project_batched_ex(const double* in, double* out, int n, int batch,
  * w receives batch*n doubles in ascending order), by the same Jacobi solver. */
 int vemb_eigvalsh_batched(const double* in, double* w, int n, int batch, int is_complex, void* hip_stream);
 
+/* ---- Batches: many independent problems stepped together --------------------
+ * Parameter sweeps (Section 4's tables: one solve per field value or coupling)
+ * and uneven mixes of cluster sizes.  A batch refers to existing problems (it
+ * does not own them; destroy the batch first).  One iteration of a batch issues
+ * one launch per step kernel for all instances and one eigensolver launch per
+ * (kind, size, precision) class, with threads per workgroup from the autotuner,
+ * and is captured in HIP graphs (an all-warm and a cold-refresh iteration) that
+ * vemb_batch_step replays.  Every instance computes exactly what vemb_step
+ * would compute for it alone, except that an iteration starts all eigensolves
+ * cold when any instance needs a cold start (t % warm_refresh == 0, or no kept
+ * eigenvectors).  All problems must be on the same device and share max_sweeps
+ * and warm_refresh.  Errors: VEMB_E_INVALID, VEMB_E_NOMEM, VEMB_E_HIP. */
+typedef struct vemb_batch vemb_batch;
+
+/* use_graph = 0 launches the kernels directly each iteration (same results). */
+int vemb_batch_create(vemb_problem* const* problems, int count, int use_graph, vemb_batch** out);
+/* Enqueues `iters` iterations on the batch's own stream, ordered after work
+ * already queued on each problem's stream; later work on a problem's stream
+ * is ordered after them.  Asynchronous. */
+int vemb_batch_step(vemb_batch* b, int iters);
+/* Host arrays of length count: per-problem vemb_dual_bound results and status
+ * codes (status may be NULL).  Synchronises; returns the last failing status. */
+int vemb_batch_dual_bounds(vemb_batch* b, double* lb_per_site, int* status);
+/* Host arrays of length count (either may be NULL): vemb_primal_energy per problem. */
+int vemb_batch_primal_energies(vemb_batch* b, double* e_per_site, double* feas_err);
+/* Number of eigensolver size classes and kernel launches per iteration. */
+int vemb_batch_info(const vemb_batch* b, int* classes, int* launches_per_iteration);
+int vemb_batch_sync(vemb_batch* b);
+void vemb_batch_destroy(vemb_batch* b);
+
 #ifdef __cplusplus
 }
 #endif

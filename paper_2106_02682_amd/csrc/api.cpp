@@ -12,8 +12,7 @@
 #include <string>
 #include <vector>
 
-#include "host_model.h"
-#include "kernels.h"
+#include "problem.h"
 
 namespace vemb {
 
@@ -24,37 +23,21 @@ void set_error(const std::string& msg) { g_last_error = msg; }
 
 using namespace vemb;
 
-struct vemb_problem {
-  Geometry g;
-  int P = 0, n_op = 0, Ku = 0;
-  vemb_options opt{};
-  hipStream_t stream = nullptr;
-  int64_t t = 0;
-  HostModel host;
-  OpTables ops_host{};
-  StepArgs a{};
-  std::vector<void*> allocations;
-  // device fixed data
-  double *H0 = nullptr, *Hd = nullptr, *tw = nullptr, *wk = nullptr;
-  int* hd_index = nullptr;
-  OpTables* ops = nullptr;
-  // kernel timing (vemb_set_profiling)
-  bool profiling = false;
-  struct Mark { int id; hipEvent_t start, stop; };
-  std::vector<Mark> marks;
-  std::vector<hipEvent_t> free_events;
-  double prof_ms[VEMB_K_COUNT] = {};
-  bool v_valid = false;  // Vpair / Vmom hold eigenvectors of the previous iteration
-  int tpb_pair = 256, tpb_mom = 256;  // threads per workgroup of the LDS solver (autotuned)
-  int64_t prof_n[VEMB_K_COUNT] = {};
-};
 
-namespace {
 
+namespace vemb {
 int fail(int code, const std::string& msg) {
   set_error(msg);
   return code;
 }
+
+int hip_rc(hipError_t e, const char* what) {
+  if (e == hipSuccess) return VEMB_OK;
+  return fail(VEMB_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+}  // namespace vemb
+
+namespace {
 
 template <typename T>
 int dalloc(vemb_problem* p, T** ptr, size_t count) {
@@ -66,16 +49,6 @@ int dalloc(vemb_problem* p, T** ptr, size_t count) {
   return VEMB_OK;
 }
 
-#define VEMB_TRY(expr)          \
-  do {                          \
-    int rc_ = (expr);           \
-    if (rc_ != VEMB_OK) return rc_; \
-  } while (0)
-
-int hip_rc(hipError_t e, const char* what) {
-  if (e == hipSuccess) return VEMB_OK;
-  return fail(VEMB_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
-}
 
 int upload_initial_state(vemb_problem* p) {
   const int m = p->g.m, n = p->g.n, M = p->g.M, P = p->P, k = p->n_op;
@@ -218,7 +191,9 @@ void synth_batch(std::vector<double>& h, int n, int count, bool cplx) {
       }
 }
 
-int tuned_tpb(int n, bool cplx, int precision, int count, hipStream_t st) {
+}  // namespace
+
+int vemb::tuned_tpb(int n, bool cplx, int precision, int count, hipStream_t st) {
   const int np = (n + 1) & ~1;
   if (np < 16 || np > 64 || count <= 0) return 256;  // one variant only
   int bucket = 1;
@@ -274,6 +249,8 @@ int tuned_tpb(int n, bool cplx, int precision, int count, hipStream_t st) {
   tune_store(key, best);
   return best;
 }
+
+namespace {
 
 bool all_finite(const double* v, size_t count) {
   for (size_t i = 0; i < count; ++i)

@@ -43,7 +43,6 @@ __global__ void __launch_bounds__(NT) jacobi_kernel(Policy pol, int n, int max_s
   constexpr int RPL = (NMAX + G - 1) / G;  // rows per lane
   __shared__ S W[NMAX * LD];
   __shared__ S V[WARM ? NMAX * LD : 1];
-  D* vstore = static_cast<D*>(vstore_raw);
   __shared__ R red[NT];
   __shared__ double red_d[NT];
   __shared__ R colf[NMAX];
@@ -61,7 +60,7 @@ __global__ void __launch_bounds__(NT) jacobi_kernel(Policy pol, int n, int max_s
   // (defect E -> O(E^2)), using W as the buffer for G = V^H V.
   if constexpr (WARM) {
     if (cold == 2) {
-      const D* vin = vstore + (size_t)mat * n * n;
+      const D* vin = pol.template vslot<D>(vstore_raw, mat, (size_t)nn);
       for (int idx = tid; idx < nn; idx += NT) {
         const int j = idx / n, i = idx - (idx / n) * n;
         V[j * LD + i] = narrow<S>(vin[idx]);
@@ -141,7 +140,7 @@ __global__ void __launch_bounds__(NT) jacobi_kernel(Policy pol, int n, int max_s
   // solve of this matrix slot.  B V_prev is nearly column-orthogonal when the
   // matrix moved little, so few sweeps remain.  V accumulates the rotations.
   if constexpr (WARM) {
-    const D* vin = vstore + (size_t)mat * n * n;  // column-major: V(i, j) at [j*n + i]
+    const D* vin = pol.template vslot<D>(vstore_raw, mat, (size_t)nn);  // column-major: V(i, j) at [j*n + i]
     if (cold == 1) {
       for (int idx = tid; idx < nn; idx += NT) {
         const int j = idx / n, i = idx - (idx / n) * n;
@@ -263,7 +262,7 @@ __global__ void __launch_bounds__(NT) jacobi_kernel(Policy pol, int n, int max_s
   }
   if (tid == 0) pol.record_sweeps(mat, sweep);
   if constexpr (WARM) {
-    D* vout = vstore + (size_t)mat * n * n;
+    D* vout = pol.template vslot<D>(vstore_raw, mat, (size_t)nn);
     for (int idx = tid; idx < nn; idx += NT) {
       const int j = idx / n, i = idx - (idx / n) * n;
       vout[idx] = widen(V[j * LD + i]);
@@ -412,6 +411,19 @@ hipError_t launch_psd_batched(const double* in, double* out, int n, int batch, b
   ArrayPolicy<false> pol{in, out, nullptr, nullptr, sweeps, n};
   ArrayPolicy<false> quiet{in, out, nullptr, nullptr, nullptr, n};
   return by_precision<float, double>(pol, quiet, n, batch, precision, max_sweeps, vstore, 1, tpb, st);
+}
+
+hipError_t launch_projection_group_lds(int kind, int n, int count, int precision, int max_sweeps, int cold, int tpb,
+                                       const int2* item, const void* ptrs, void* vstore_any, hipStream_t st) {
+  double* vs = static_cast<double*>(vstore_any);
+  if (kind == 0) {
+    BatchedPairPolicy pol{item, static_cast<const PairPtrs*>(ptrs), n, 1};
+    BatchedPairPolicy quiet{item, static_cast<const PairPtrs*>(ptrs), n, 0};
+    return by_precision<float, double>(pol, quiet, n, count, precision, max_sweeps, vs, cold, tpb, st);
+  }
+  BatchedMomentumPolicy pol{item, static_cast<const MomPtrs*>(ptrs), n, 1};
+  BatchedMomentumPolicy quiet{item, static_cast<const MomPtrs*>(ptrs), n, 0};
+  return by_precision<cplx<float>, cplx<double>>(pol, quiet, n, count, precision, max_sweeps, vs, cold, tpb, st);
 }
 
 hipError_t launch_eigvalsh_batched(const double* in, double* w, int n, int batch, bool is_complex, int max_sweeps,

@@ -149,7 +149,7 @@ __global__ void __launch_bounds__(kThreads) jacobi_big_kernel(Policy pol, int n,
   const size_t nn = (size_t)n * n;
   S* W = wscr + mat * nn;  // column-major: W(i, j) = W[j*n + i]
   S* T = tscr + mat * nn;
-  D* Vg = TRACKV ? static_cast<D*>(vstore_raw) + mat * nn : nullptr;
+  D* Vg = TRACKV ? pol.template vslot<D>(vstore_raw, mat, nn) : nullptr;
 
   // 0. cold == 2: orthonormalise the kept V (from a lower-precision solve) by one
   // Newton-Schulz step V <- V (3I - V^H V)/2, with G in T and the result via W.
@@ -401,6 +401,26 @@ hipError_t launch_psd_batched_big(const double* in, double* out, int n, int batc
   ArrayPolicy<false> pol{in, out, nullptr, nullptr, sweeps, n};
   ArrayPolicy<false> quiet{in, out, nullptr, nullptr, nullptr, n};
   return big_by_precision<float, double>(pol, quiet, n, batch, precision, max_sweeps, vstore, 1, wscr, tscr, st);
+}
+
+hipError_t launch_projection_group_lds(int kind, int n, int count, int precision, int max_sweeps, int cold, int tpb,
+                                       const int2* item, const void* ptrs, void* vstore_any, hipStream_t st);
+
+hipError_t launch_projection_group(int kind, int n, int count, int precision, int max_sweeps, int cold, int tpb,
+                                   const int2* item, const void* ptrs, void* vstore_any, void* wscr, void* tscr,
+                                   hipStream_t st) {
+  const bool lds = n <= 64;
+  if (lds) return launch_projection_group_lds(kind, n, count, precision, max_sweeps, cold, tpb, item, ptrs, vstore_any, st);
+  double* vs = static_cast<double*>(vstore_any);
+  if (kind == 0) {
+    BatchedPairPolicy pol{item, static_cast<const PairPtrs*>(ptrs), n, 1};
+    BatchedPairPolicy quiet{item, static_cast<const PairPtrs*>(ptrs), n, 0};
+    return big_by_precision<float, double>(pol, quiet, n, count, precision, max_sweeps, vs, cold, wscr, tscr, st);
+  }
+  BatchedMomentumPolicy pol{item, static_cast<const MomPtrs*>(ptrs), n, 1};
+  BatchedMomentumPolicy quiet{item, static_cast<const MomPtrs*>(ptrs), n, 0};
+  return big_by_precision<cplx<float>, cplx<double>>(pol, quiet, n, count, precision, max_sweeps, vs, cold, wscr,
+                                                     tscr, st);
 }
 
 hipError_t launch_eigvals_big(const double* in, double* w, double* wmin, int n, int count, bool is_complex,

@@ -150,6 +150,7 @@ template <> __device__ inline float from_double<float>(double v) { return (float
 __device__ inline double to_double(double v) { return v; }
 __device__ inline double to_double(float v) { return (double)v; }
 
+// Every policy also names where matrix `mat` keeps its eigenvectors (vslot).
 struct PairPolicy {
   const double* rho;
   double* Lam;
@@ -176,6 +177,9 @@ struct PairPolicy {
     if (sweeps) sweeps[mat] = s;
   }
   __device__ void store_eig(int, int, double) const {}
+  template <typename D> __device__ D* vslot(void* base, int mat, size_t nn) const {
+    return static_cast<D*>(base) + (size_t)mat * nn;
+  }
 };
 
 struct MomentumPolicy {
@@ -198,6 +202,9 @@ struct MomentumPolicy {
     if (sweeps) sweeps[mat] = s;
   }
   __device__ void store_eig(int, int, double) const {}
+  template <typename D> __device__ D* vslot(void* base, int mat, size_t nn) const {
+    return static_cast<D*>(base) + (size_t)mat * nn;
+  }
 };
 
 // Real or complex matrices in plain arrays (isolated entry points and the bound).
@@ -235,6 +242,80 @@ struct ArrayPolicy {
   __device__ void store_eig(int mat, int rank, double v) const {
     if (w) w[(size_t)mat * n + rank] = v;
     if (wmin && rank == 0) wmin[mat] = v;
+  }
+  template <typename D> __device__ D* vslot(void* base, int mat, size_t nn) const {
+    return static_cast<D*>(base) + (size_t)mat * nn;
+  }
+};
+
+// Batched policies: one launch covers the matrices of many problems of the same
+// size; item[mat] = (instance, local index), per-instance pointers in `inst`.
+struct BatchedPairPolicy {
+  const int2* item;
+  const PairPtrs* inst;
+  int n;
+  int record;  // write sweep counts
+  template <typename S> __device__ S load(int mat, int i, int j) const {
+    const int2 w = item[mat];
+    const PairPtrs& P = inst[w.x];
+    const size_t o = (size_t)w.y * n * n + (size_t)i * n + j;
+    return from_double<S>(P.rho[o] - P.Lam[o] / P.mu);
+  }
+  template <typename S> __device__ double store(int mat, int i, int k, S v) const {
+    const int2 w = item[mat];
+    const PairPtrs& P = inst[w.x];
+    const size_t o = (size_t)w.y * n * n + (size_t)i * n + k;
+    const double pv = to_double(v);
+    const double r = P.rho[o];
+    P.rho_t[o] = pv;
+    P.Lam[o] = P.Lam[o] + P.mu * (pv - r);
+    const double dlt = r - pv;
+    return dlt * dlt;
+  }
+  __device__ void finish(int mat, double tot) const {
+    const int2 w = item[mat];
+    inst[w.x].feas[w.y] = tot;
+  }
+  __device__ void record_sweeps(int mat, int s) const {
+    const int2 w = item[mat];
+    if (record && inst[w.x].sweeps) inst[w.x].sweeps[w.y] = s;
+  }
+  __device__ void store_eig(int, int, double) const {}
+  template <typename D> __device__ D* vslot(void*, int mat, size_t nn) const {
+    const int2 w = item[mat];
+    return reinterpret_cast<D*>(inst[w.x].vstore) + (size_t)w.y * nn;
+  }
+};
+
+struct BatchedMomentumPolicy {
+  const int2* item;
+  const MomPtrs* inst;
+  int n;
+  int record;
+  template <typename S> __device__ S load(int mat, int i, int j) const {
+    const int2 w = item[mat];
+    const size_t o = 2 * ((size_t)w.y * n * n + (size_t)i * n + j);
+    using R = typename scalar_traits<S>::real;
+    const double* X = inst[w.x].Xh;
+    return S{(R)X[o], (R)X[o + 1]};
+  }
+  template <typename S> __device__ double store(int mat, int i, int k, S v) const {
+    const int2 w = item[mat];
+    const size_t o = 2 * ((size_t)w.y * n * n + (size_t)i * n + k);
+    double* X = inst[w.x].Xh;
+    X[o] = (double)v.re;
+    X[o + 1] = (double)v.im;
+    return 0.0;
+  }
+  __device__ void finish(int, double) const {}
+  __device__ void record_sweeps(int mat, int s) const {
+    const int2 w = item[mat];
+    if (record && inst[w.x].sweeps) inst[w.x].sweeps[w.y] = s;
+  }
+  __device__ void store_eig(int, int, double) const {}
+  template <typename D> __device__ D* vslot(void*, int mat, size_t nn) const {
+    const int2 w = item[mat];
+    return reinterpret_cast<D*>(inst[w.x].vstore) + (size_t)w.y * nn;
   }
 };
 

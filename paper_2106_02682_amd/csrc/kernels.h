@@ -6,6 +6,28 @@
 namespace vemb {
 
 // ----- Jacobi PSD projection / eigenvalues (jacobi.hip) -------------------
+// Per-instance pointers for batched projections (one launch over many problems).
+struct PairPtrs {
+  const double* rho;
+  double* Lam;
+  double* rho_t;
+  double* feas;
+  int* sweeps;
+  double* vstore;
+  double mu;
+};
+struct MomPtrs {
+  double* Xh;
+  int* sweeps;
+  double* vstore;
+};
+// kind 0: pair projections (PairPtrs), kind 1: momentum projections (MomPtrs).
+// item: device array count x int2 (instance, local index); ptrs: device array of
+// PairPtrs / MomPtrs; vstore_any: any non-null pointer when eigenvectors are kept.
+// Matrices above the LDS capacity use wscr / tscr (count x n x n, batch-owned).
+hipError_t launch_projection_group(int kind, int n, int count, int precision, int max_sweeps, int cold, int tpb,
+                                   const int2* item, const void* ptrs, void* vstore_any, void* wscr, void* tscr,
+                                   hipStream_t st);
 // All launchers enqueue on `st` and return hipSuccess or the launch error.
 
 // Pair step 3 + Lambda update: C = rho - Lam/mu; rho_t = Pi(C); Lam += mu (rho_t - rho);
@@ -86,6 +108,18 @@ struct StepArgs {
   void* wscr_mom;   // (n_op > 64): Ku x n_op x n_op complex doubles each
   void* tscr_mom;
 };
+
+// Batched step kernels: work[b] = {instance, local block x, local block y}.
+struct WorkItem {
+  int inst, bx, by, pad;
+};
+// Local grid (x, y) of the five step kernels of one instance, in the order
+// 0 pair update, 1 X step, 2 cluster update, 3 forward DFT, 4 inverse DFT.
+void local_grids(const StepArgs& a, int grid[5][2]);
+// One launch of step kernel `which` (numbering above) over all work items;
+// args is a device array of per-instance StepArgs.  which = 2 takes one block
+// per instance (nwork = instance count, work unused).
+hipError_t launch_step_batched(int which, const StepArgs* args, const WorkItem* work, int nwork, hipStream_t st);
 
 hipError_t launch_pair_update(const StepArgs& a, hipStream_t st);
 hipError_t launch_pair_xstep(const StepArgs& a, hipStream_t st);

@@ -1,0 +1,47 @@
+// Internal definition of a problem (shared by the C ABI in api.cpp and the batch in batch.cpp).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "host_model.h"
+#include "kernels.h"
+
+struct vemb_problem {
+  vemb::Geometry g;
+  int P = 0, n_op = 0, Ku = 0;
+  vemb_options opt{};
+  hipStream_t stream = nullptr;
+  int64_t t = 0;
+  vemb::HostModel host;
+  vemb::OpTables ops_host{};
+  vemb::StepArgs a{};
+  std::vector<void*> allocations;
+  // device fixed data
+  double *H0 = nullptr, *Hd = nullptr, *tw = nullptr, *wk = nullptr;
+  int* hd_index = nullptr;
+  vemb::OpTables* ops = nullptr;
+  // kernel timing (vemb_set_profiling)
+  bool profiling = false;
+  struct Mark { int id; hipEvent_t start, stop; };
+  std::vector<Mark> marks;
+  std::vector<hipEvent_t> free_events;
+  double prof_ms[VEMB_K_COUNT] = {};
+  bool v_valid = false;  // Vpair / Vmom hold eigenvectors of the previous iteration
+  int tpb_pair = 256, tpb_mom = 256;  // threads per workgroup of the LDS solver (autotuned)
+  int64_t prof_n[VEMB_K_COUNT] = {};
+};
+
+namespace vemb {
+int fail(int code, const std::string& msg);
+int hip_rc(hipError_t e, const char* what);
+int tuned_tpb(int n, bool cplx, int precision, int count, hipStream_t st);
+}  // namespace vemb
+
+#define VEMB_TRY(expr)              \
+  do {                              \
+    int rc_ = (expr);               \
+    if (rc_ != VEMB_OK) return rc_; \
+  } while (0)

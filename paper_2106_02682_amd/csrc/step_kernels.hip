@@ -59,8 +59,8 @@ __device__ double rhs_value(const StepArgs& A, int pd, int i, int j) {
 // ---------------------------------------------------------------------------
 // Steps 1-2 and X'_0d.  One workgroup per offset d.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(kBlock) pair_update_kernel(StepArgs A) {
-  const int pd = blockIdx.x;  // offset d = pd + 1
+__device__ void pair_update_body(const StepArgs& A, int bx) {
+  const int pd = bx;  // offset d = pd + 1
   const int m = A.m, n = A.n, mm = m * m;
   const int tid = threadIdx.x;
   __shared__ double T2[kMaxM * kMaxM];  // Tr_2 R
@@ -125,10 +125,10 @@ __global__ void __launch_bounds__(kBlock) pair_update_kernel(StepArgs A) {
 }
 
 // X'_0d = X_0d + sign eps G_0d(rho_0d) for d = 1..M-1, one thread per entry.
-__global__ void __launch_bounds__(kBlock) pair_xstep_kernel(StepArgs A) {
-  const int pd = blockIdx.y;
+__device__ void pair_xstep_body(const StepArgs& A, int bx, int by) {
+  const int pd = by;
   const int k = A.n_op, m = A.m, n = A.n;
-  const int e = blockIdx.x * kBlock + threadIdx.x;
+  const int e = bx * kBlock + threadIdx.x;
   if (e >= k * k) return;
   const size_t xo = (size_t)(pd + 1) * k * k + e;
   const double* rho = A.rho + (size_t)pd * n * n;
@@ -177,7 +177,7 @@ __device__ double c0_value(const StepArgs& A, int b, int e) {
 
 constexpr int kClusterBlock = 1024;
 
-__global__ void __launch_bounds__(kClusterBlock) cluster_update_kernel(StepArgs A) {
+__device__ void cluster_update_body(const StepArgs& A) {
   const int m = A.m, mm = m * m, P = A.P, k = A.n_op;
   const int tid = threadIdx.x;
   __shared__ double r0[kMaxM * kMaxM];
@@ -257,10 +257,10 @@ __global__ void __launch_bounds__(kClusterBlock) cluster_update_kernel(StepArgs 
 // ---------------------------------------------------------------------------
 constexpr int KC = 8;
 
-__global__ void __launch_bounds__(kBlock) dft_forward_kernel(StepArgs A) {
+__device__ void dft_forward_body(const StepArgs& A, int bx, int by) {
   const int E = A.n_op * A.n_op;
-  const int e = blockIdx.x * kBlock + threadIdx.x;
-  const int k0 = blockIdx.y * KC;
+  const int e = bx * kBlock + threadIdx.x;
+  const int k0 = by * KC;
   if (e >= E) return;
   const int kc = min(KC, A.Ku - k0);
   double re[KC], im[KC];
@@ -287,10 +287,10 @@ __global__ void __launch_bounds__(kBlock) dft_forward_kernel(StepArgs A) {
 // Step 9: X_d = sum_k w_k Re(conj(tw[k][d]) Y_k), thread per entry, DC offsets per thread.
 constexpr int DC = 8;
 
-__global__ void __launch_bounds__(kBlock) dft_inverse_kernel(StepArgs A) {
+__device__ void dft_inverse_body(const StepArgs& A, int bx, int by) {
   const int E = A.n_op * A.n_op;
-  const int e = blockIdx.x * kBlock + threadIdx.x;
-  const int d0 = blockIdx.y * DC;
+  const int e = bx * kBlock + threadIdx.x;
+  const int d0 = by * DC;
   if (e >= E) return;
   const int dc = min(DC, A.M - d0);
   double acc[DC];
@@ -310,6 +310,34 @@ __global__ void __launch_bounds__(kBlock) dft_inverse_kernel(StepArgs A) {
     }
   }
   for (int c = 0; c < dc; ++c) A.X[(size_t)(d0 + c) * E + e] = acc[c];
+}
+
+// Single-instance kernels and batched kernels.  A batched launch covers every
+// instance of a batch: work[blockIdx.x] names the instance and its local block.
+__global__ void __launch_bounds__(kBlock) pair_update_kernel(StepArgs A) { pair_update_body(A, blockIdx.x); }
+__global__ void __launch_bounds__(kBlock) pair_xstep_kernel(StepArgs A) { pair_xstep_body(A, blockIdx.x, blockIdx.y); }
+__global__ void __launch_bounds__(kClusterBlock) cluster_update_kernel(StepArgs A) { cluster_update_body(A); }
+__global__ void __launch_bounds__(kBlock) dft_forward_kernel(StepArgs A) { dft_forward_body(A, blockIdx.x, blockIdx.y); }
+__global__ void __launch_bounds__(kBlock) dft_inverse_kernel(StepArgs A) { dft_inverse_body(A, blockIdx.x, blockIdx.y); }
+
+__global__ void __launch_bounds__(kBlock) pair_update_batched(const StepArgs* args, const WorkItem* work) {
+  const WorkItem w = work[blockIdx.x];
+  pair_update_body(args[w.inst], w.bx);
+}
+__global__ void __launch_bounds__(kBlock) pair_xstep_batched(const StepArgs* args, const WorkItem* work) {
+  const WorkItem w = work[blockIdx.x];
+  pair_xstep_body(args[w.inst], w.bx, w.by);
+}
+__global__ void __launch_bounds__(kClusterBlock) cluster_update_batched(const StepArgs* args) {
+  cluster_update_body(args[blockIdx.x]);
+}
+__global__ void __launch_bounds__(kBlock) dft_forward_batched(const StepArgs* args, const WorkItem* work) {
+  const WorkItem w = work[blockIdx.x];
+  dft_forward_body(args[w.inst], w.bx, w.by);
+}
+__global__ void __launch_bounds__(kBlock) dft_inverse_batched(const StepArgs* args, const WorkItem* work) {
+  const WorkItem w = work[blockIdx.x];
+  dft_inverse_body(args[w.inst], w.bx, w.by);
 }
 
 // ---------------------------------------------------------------------------
@@ -376,6 +404,45 @@ hipError_t launch_dft_inverse(const StepArgs& a, hipStream_t st) {
   const int E = a.n_op * a.n_op;
   hipLaunchKernelGGL(dft_inverse_kernel, dim3((E + kBlock - 1) / kBlock, (a.M + DC - 1) / DC), dim3(kBlock), 0,
                      st, a);
+  return hipGetLastError();
+}
+
+void local_grids(const StepArgs& a, int grid[5][2]) {
+  const int E = a.n_op * a.n_op;
+  const int ebx = (E + kBlock - 1) / kBlock;
+  grid[0][0] = a.P;  // pair update
+  grid[0][1] = 1;
+  grid[1][0] = ebx;  // X step
+  grid[1][1] = a.P;
+  grid[2][0] = 1;  // cluster update
+  grid[2][1] = 1;
+  grid[3][0] = ebx;  // forward DFT
+  grid[3][1] = (a.Ku + KC - 1) / KC;
+  grid[4][0] = ebx;  // inverse DFT
+  grid[4][1] = (a.M + DC - 1) / DC;
+}
+
+hipError_t launch_step_batched(int which, const StepArgs* args, const WorkItem* work, int nwork, hipStream_t st) {
+  if (nwork <= 0) return hipSuccess;
+  switch (which) {
+    case 0:
+      hipLaunchKernelGGL(pair_update_batched, dim3(nwork), dim3(kBlock), 0, st, args, work);
+      break;
+    case 1:
+      hipLaunchKernelGGL(pair_xstep_batched, dim3(nwork), dim3(kBlock), 0, st, args, work);
+      break;
+    case 2:
+      hipLaunchKernelGGL(cluster_update_batched, dim3(nwork), dim3(kClusterBlock), 0, st, args);
+      break;
+    case 3:
+      hipLaunchKernelGGL(dft_forward_batched, dim3(nwork), dim3(kBlock), 0, st, args, work);
+      break;
+    case 4:
+      hipLaunchKernelGGL(dft_inverse_batched, dim3(nwork), dim3(kBlock), 0, st, args, work);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

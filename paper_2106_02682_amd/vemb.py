@@ -28,7 +28,8 @@ EXPORTS = [
     "vemb_primal_energy", "vemb_marginals", "vemb_get_state", "vemb_set_state", "vemb_destroy",
     "vemb_last_error", "vemb_psd_project_batched", "vemb_eigvalsh_batched", "vemb_last_sweeps",
     "vemb_psd_project_batched_ex", "vemb_set_profiling", "vemb_get_profile", "vemb_refine",
-    "vemb_tuned_threads", "vemb_problem_threads",
+    "vemb_tuned_threads", "vemb_problem_threads", "vemb_batch_create", "vemb_batch_step", "vemb_batch_dual_bounds",
+    "vemb_batch_primal_energies", "vemb_batch_info", "vemb_batch_sync", "vemb_batch_destroy",
 ]
 KERNELS = ["pair_update", "pair_xstep", "pair_projection", "cluster_update", "dft_forward", "momentum_projection",
            "dft_inverse", "bound_build", "lambda_min"]
@@ -119,8 +120,16 @@ def lib():
     L.vemb_last_sweeps.argtypes = [vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
     L.vemb_psd_project_batched_ex.argtypes = [vp, vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                               ctypes.c_int, vp, vp]
+    L.vemb_batch_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int, ctypes.c_int, ctypes.POINTER(vp)]
+    L.vemb_batch_step.argtypes = [vp, ctypes.c_int]
+    L.vemb_batch_dual_bounds.argtypes = [vp, _DP, ctypes.POINTER(ctypes.c_int)]
+    L.vemb_batch_primal_energies.argtypes = [vp, _DP, _DP]
+    L.vemb_batch_info.argtypes = [vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
+    L.vemb_batch_sync.argtypes = [vp]
+    L.vemb_batch_destroy.argtypes = [vp]
+    L.vemb_batch_destroy.restype = None
     for name in EXPORTS:
-        if name not in ("vemb_default_options", "vemb_destroy", "vemb_last_error"):
+        if name not in ("vemb_default_options", "vemb_destroy", "vemb_last_error", "vemb_batch_destroy"):
             getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -363,6 +372,63 @@ class Problem:
     def close(self):
         if self.h:
             destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+class Batch:
+    """Several problems stepped together (one launch per step kernel and per
+    eigensolver size class, replayed from HIP graphs).  Holds references to the
+    Problem objects so they outlive the batch."""
+
+    def __init__(self, problems, use_graph=True):
+        self.problems = list(problems)
+        if not self.problems or any(p.h is None for p in self.problems):
+            raise ValueError("a batch needs open problems")
+        arr = (ctypes.c_void_p * len(self.problems))(*[p.h for p in self.problems])
+        out = ctypes.c_void_p()
+        _check(lib().vemb_batch_create(arr, len(self.problems), int(bool(use_graph)), ctypes.byref(out)))
+        self.h = out
+
+    def step(self, iters=1):
+        _check(lib().vemb_batch_step(self.h, int(iters)))
+
+    def sync(self):
+        _check(lib().vemb_batch_sync(self.h))
+
+    def dual_bounds(self):
+        lb = np.zeros(len(self.problems))
+        st = (ctypes.c_int * len(self.problems))()
+        lib().vemb_batch_dual_bounds(self.h, _ptr(lb), st)
+        for rc in st:
+            _check(rc)
+        return lb
+
+    def primal_energies(self):
+        e = np.zeros(len(self.problems))
+        f = np.zeros(len(self.problems))
+        _check(lib().vemb_batch_primal_energies(self.h, _ptr(e), _ptr(f)))
+        return e, f
+
+    def info(self):
+        a, b = ctypes.c_int(), ctypes.c_int()
+        _check(lib().vemb_batch_info(self.h, ctypes.byref(a), ctypes.byref(b)))
+        return {"classes": a.value, "launches_per_iteration": b.value}
+
+    def close(self):
+        if self.h:
+            lib().vemb_batch_destroy(self.h)
             self.h = None
 
     def __del__(self):

@@ -4,6 +4,7 @@
 * argument validation happens before any device work, so invalid problem
   specifications return their error codes on a machine without a GPU.
 """
+import ctypes
 import os
 import re
 
@@ -58,3 +59,10 @@ def test_null_arguments():
     assert lib.vemb_dual_bound(None, None) == -1
     assert lib.vemb_psd_project_batched(None, None, 4, 1, 0, 0, None) == -1
     lib.vemb_destroy(None)  # no-op
+    assert lib.vemb_batch_create(None, 0, 1, None) == -1
+    arr = (ctypes.c_void_p * 2)(None, None)
+    out = ctypes.c_void_p()
+    assert lib.vemb_batch_create(arr, 2, 1, ctypes.byref(out)) == -1
+    assert lib.vemb_batch_step(None, 1) == -1
+    assert lib.vemb_batch_dual_bounds(None, None, None) == -1
+    lib.vemb_batch_destroy(None)  # no-op
