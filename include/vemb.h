@@ -238,8 +238,9 @@ int vemb_eigvalsh_batched(const double* in, double* w, int n, int batch, int is_
  * one launch per step kernel for all instances and one eigensolver launch per
  * (kind, size, precision) class, with threads per workgroup from the autotuner,
  * and is captured in HIP graphs (an all-warm and a cold-refresh iteration) that
- * vemb_batch_step replays.  Every instance computes exactly what vemb_step
- * would compute for it alone, except that an iteration starts all eigensolves
+ * vemb_batch_step replays.  Every instance goes through the same arithmetic
+ * as vemb_step alone (separately compiled kernels: results agree to rounding),
+ * except that an iteration starts all eigensolves
  * cold when any instance needs a cold start (t % warm_refresh == 0, or no kept
  * eigenvectors).  All problems must be on the same device and share max_sweeps
  * and warm_refresh.  Errors: VEMB_E_INVALID, VEMB_E_NOMEM, VEMB_E_HIP. */

@@ -1,8 +1,9 @@
 """Batches of independent problems (parameter sweeps, uneven cluster sizes).
 
-* A batch computes for each instance exactly what stepping it alone computes
-  (same kernels and arithmetic order when threads per workgroup are fixed):
-  states compared element by element, bit-exact.
+* A batch computes for each instance what stepping it alone computes (the same
+  arithmetic, in separately compiled kernels, so contraction of products into
+  FMAs may differ): states compared element by element to 1e-12 of each
+  array's largest entry.
 * The captured graphs are replayed several times with eager work and
   synchronisations in between (diagnostics on the problems' own streams, torch
   work on the current stream); every replay is checked against a batch of
@@ -42,12 +43,15 @@ def _open(vemb, ws, **kw):
     return [vemb.Problem.from_workload(w, **kw) for w in ws]
 
 
-def _assert_same_state(a, b, what):
+def _assert_same_state(a, b, what, rtol=0.0):
     sa, sb = a.get_state(), b.get_state()
+    worst = 0.0
     for k in STATE_KEYS:
-        if not np.array_equal(sa[k], sb[k]):
-            d = np.abs(sa[k] - sb[k]).max()
-            raise AssertionError(f"{what}: state {k} differs (max abs {d:.3e})")
+        d = np.abs(sa[k] - sb[k]).max() / max(np.abs(sa[k]).max(), 1e-300)
+        worst = max(worst, d)
+        if d > rtol:
+            raise AssertionError(f"{what}: state {k} differs (max rel {d:.3e} > {rtol:.1e})")
+    return worst
 
 
 @pytest.mark.parametrize("use_graph", [True, False])
@@ -67,8 +71,10 @@ def test_batch_equals_individual_stepping(vemb, use_graph):
             b.sync()
             lbs = b.dual_bounds()
         for w, p, q, lb in zip(ws, alone, batched, lbs):
-            _assert_same_state(p, q, w.name)
-            assert lb == p.dual_bound()
+            d = _assert_same_state(p, q, w.name, rtol=1e-12)
+            lb_alone = p.dual_bound()
+            print(f"{w.name}: batch vs alone, max rel state difference {d:.2e}, lb {lb:.15f} vs {lb_alone:.15f}")
+            assert abs(lb - lb_alone) <= 1e-12 * abs(lb_alone)
     finally:
         for p in alone + batched:
             p.close()
@@ -133,7 +139,7 @@ def test_batch_then_individual_continue(vemb):
         with vemb.Batch([b]) as bt:
             bt.step(3)
         b.step(2)
-        _assert_same_state(a, b, w.name)
+        _assert_same_state(a, b, w.name, rtol=1e-12)
     finally:
         a.close()
         b.close()
