@@ -85,16 +85,17 @@ hipEvent_t take_event(vemb_problem* p) {
 
 // Runs one launcher, bracketed by events when profiling is on.
 template <typename F>
-int timed(vemb_problem* p, int id, const char* what, F&& launch) {
+int timed(vemb_problem* p, int id, const char* what, F&& launch, hipStream_t st = nullptr) {
+  if (!st) st = p->stream;
   hipEvent_t a = nullptr, b = nullptr;
   if (p->profiling) {
     a = take_event(p);
     b = take_event(p);
-    if (a) hipEventRecord(a, p->stream);
+    if (a) hipEventRecord(a, st);
   }
   int rc = hip_rc(launch(), what);
   if (p->profiling && a && b) {
-    hipEventRecord(b, p->stream);
+    hipEventRecord(b, st);
     p->marks.push_back({id, a, b});
   }
   return rc;
@@ -319,10 +320,16 @@ int vemb_create_problem(const vemb_hamiltonian* H, const vemb_lattice* lat, cons
   p->n_op = n_op;
   p->opt = o;
   p->stream = static_cast<hipStream_t>(hip_stream);
+  if (hipStreamCreateWithFlags(&p->side, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&p->fork_ev, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&p->join_ev, hipEventDisableTiming) != hipSuccess) {
+    vemb_destroy(p);
+    return fail(VEMB_E_HIP, "side stream / events");
+  }
   std::string err;
   int rc = build_model(*H, g, p->host, err);
   if (rc != VEMB_OK) {
-    delete p;
+    vemb_destroy(p);
     return fail(rc, err);
   }
   std::vector<double> tw, wk;
@@ -422,13 +429,19 @@ int run_iterations(vemb_problem* p, int iters, int prec) {
     const int cold = (!p->v_valid || refresh < 0 || p->t % refresh == 0) ? 1 : 0;
     VEMB_TRY(timed(p, VEMB_K_PAIR_UPDATE, "pair update", [&] { return launch_pair_update(a, s); }));
     VEMB_TRY(timed(p, VEMB_K_PAIR_XSTEP, "pair X step", [&] { return launch_pair_xstep(a, s); }));
+    // fork: pair projection on the side stream (reads rho, Lambda; writes rho_t,
+    // Lambda, feas, Vpair -- nothing the main branch touches)
+    hipStream_t s2 = p->side;
+    VEMB_TRY(hip_rc(hipEventRecord(p->fork_ev, s), "fork"));
+    VEMB_TRY(hip_rc(hipStreamWaitEvent(s2, p->fork_ev, 0), "fork"));
     VEMB_TRY(timed(p, VEMB_K_PAIR_PROJ, "pair projection", [&] {
       if (a.n > 64)
         return launch_pair_projection_big(a.rho, a.Lam, a.rho_t, a.feas, a.n, a.P, a.mu, prec, ms, a.sweeps, a.Vpair,
-                                          cold, a.wscr_pair, a.tscr_pair, s);
+                                          cold, a.wscr_pair, a.tscr_pair, s2);
       return launch_pair_projection(a.rho, a.Lam, a.rho_t, a.feas, a.n, a.P, a.mu, prec, ms, a.sweeps, a.Vpair, cold,
-                                    p->tpb_pair, s);
-    }));
+                                    p->tpb_pair, s2);
+    }, s2));
+    VEMB_TRY(hip_rc(hipEventRecord(p->join_ev, s2), "join"));
     VEMB_TRY(timed(p, VEMB_K_CLUSTER, "cluster update", [&] { return launch_cluster_update(a, s); }));
     VEMB_TRY(timed(p, VEMB_K_DFT_FWD, "forward DFT", [&] { return launch_dft_forward(a, s); }));
     VEMB_TRY(timed(p, VEMB_K_MOM_PROJ, "momentum projection", [&] {
@@ -438,6 +451,7 @@ int run_iterations(vemb_problem* p, int iters, int prec) {
       return launch_momentum_projection(a.Xh, a.n_op, a.Ku, prec, ms, a.sweeps + a.P, a.Vmom, cold, p->tpb_mom, s);
     }));
     VEMB_TRY(timed(p, VEMB_K_DFT_INV, "inverse DFT", [&] { return launch_dft_inverse(a, s); }));
+    VEMB_TRY(hip_rc(hipStreamWaitEvent(s, p->join_ev, 0), "join"));
     p->v_valid = true;
     ++p->t;
   }
@@ -620,6 +634,9 @@ void vemb_destroy(vemb_problem* p) {
   }
   for (hipEvent_t e : p->free_events) hipEventDestroy(e);
   for (void* ptr : p->allocations) hipFree(ptr);
+  if (p->fork_ev) hipEventDestroy(p->fork_ev);
+  if (p->join_ev) hipEventDestroy(p->join_ev);
+  if (p->side) hipStreamDestroy(p->side);
   delete p;
 }
 

@@ -4,7 +4,9 @@
 // (work tables map a block to (instance, local block)) and one launch per size
 // class of eigensolves (all pair matrices of the same n in one launch, all
 // momentum blocks of the same n_op in another), with threads per workgroup
-// chosen by the autotuner per class.  The iteration is captured twice in HIP
+// chosen by the autotuner per class.  Pair projections run on a side stream,
+// concurrently with the cluster update, the DFTs and the momentum projections.
+// The iteration is captured twice in HIP
 // graphs -- all eigensolves warm-started, and the periodic cold refresh -- and
 // replayed.  Each instance keeps its own state and kept eigenvectors, so a
 // problem can be stepped alone or in a batch interchangeably.
@@ -20,7 +22,8 @@ using namespace vemb;
 struct vemb_batch {
   std::vector<vemb_problem*> probs;
   hipStream_t stream = nullptr;  // own non-blocking stream (capturable), default priority
-  hipEvent_t ev = nullptr;
+  hipStream_t side = nullptr;    // pair projections, concurrent with the momentum branch
+  hipEvent_t ev = nullptr, fork_ev = nullptr, join_ev = nullptr;
   int refresh = 64;
   StepArgs* d_args = nullptr;
   WorkItem* d_work[5] = {};
@@ -59,11 +62,15 @@ int enqueue_iteration(vemb_batch* b, int cold) {
   const int max_sweeps = b->probs[0]->opt.max_sweeps;
   VEMB_TRY(hip_rc(launch_step_batched(0, b->d_args, b->d_work[0], b->nwork[0], s), "batched pair update"));
   VEMB_TRY(hip_rc(launch_step_batched(1, b->d_args, b->d_work[1], b->nwork[1], s), "batched X step"));
+  // fork: pair projections on the side stream (they feed only the next iteration)
+  VEMB_TRY(hip_rc(hipEventRecord(b->fork_ev, s), "fork"));
+  VEMB_TRY(hip_rc(hipStreamWaitEvent(b->side, b->fork_ev, 0), "fork"));
   for (const auto& g : b->groups)
     if (g.kind == 0)
       VEMB_TRY(hip_rc(launch_projection_group(0, g.n, g.count, g.precision, max_sweeps, cold, g.tpb, g.d_item,
-                                              b->d_pair, g.vstore_any, g.wscr, g.tscr, s),
+                                              b->d_pair, g.vstore_any, g.wscr, g.tscr, b->side),
                       "batched pair projection"));
+  VEMB_TRY(hip_rc(hipEventRecord(b->join_ev, b->side), "join"));
   VEMB_TRY(hip_rc(launch_step_batched(2, b->d_args, nullptr, n_inst, s), "batched cluster update"));
   VEMB_TRY(hip_rc(launch_step_batched(3, b->d_args, b->d_work[3], b->nwork[3], s), "batched forward DFT"));
   for (const auto& g : b->groups)
@@ -72,6 +79,7 @@ int enqueue_iteration(vemb_batch* b, int cold) {
                                               b->d_mom, g.vstore_any, g.wscr, g.tscr, s),
                       "batched momentum projection"));
   VEMB_TRY(hip_rc(launch_step_batched(4, b->d_args, b->d_work[4], b->nwork[4], s), "batched inverse DFT"));
+  VEMB_TRY(hip_rc(hipStreamWaitEvent(s, b->join_ev, 0), "join"));
   return VEMB_OK;
 }
 
@@ -115,7 +123,10 @@ int vemb_batch_create(vemb_problem* const* problems, int count, int use_graph, v
   };
   int rc;
   if ((rc = hip_rc(hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking), "batch stream")) ||
-      (rc = hip_rc(hipEventCreateWithFlags(&b->ev, hipEventDisableTiming), "batch event")))
+      (rc = hip_rc(hipStreamCreateWithFlags(&b->side, hipStreamNonBlocking), "batch stream")) ||
+      (rc = hip_rc(hipEventCreateWithFlags(&b->ev, hipEventDisableTiming), "batch event")) ||
+      (rc = hip_rc(hipEventCreateWithFlags(&b->fork_ev, hipEventDisableTiming), "batch event")) ||
+      (rc = hip_rc(hipEventCreateWithFlags(&b->join_ev, hipEventDisableTiming), "batch event")))
     return cleanup(rc);
   // per-instance arguments, pointers and work tables
   std::vector<StepArgs> args(count);
@@ -262,6 +273,9 @@ void vemb_batch_destroy(vemb_batch* b) {
     if (e) hipGraphExecDestroy(e);
   for (void* p : b->allocs) hipFree(p);
   if (b->ev) hipEventDestroy(b->ev);
+  if (b->fork_ev) hipEventDestroy(b->fork_ev);
+  if (b->join_ev) hipEventDestroy(b->join_ev);
+  if (b->side) hipStreamDestroy(b->side);
   if (b->stream) hipStreamDestroy(b->stream);
   delete b;
 }

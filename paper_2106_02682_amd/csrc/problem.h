@@ -14,6 +14,11 @@ struct vemb_problem {
   int P = 0, n_op = 0, Ku = 0;
   vemb_options opt{};
   hipStream_t stream = nullptr;
+  // The pair projection feeds only the next iteration (rho_t, Lambda), so it runs on
+  // a side stream concurrently with the cluster update, the DFTs and the momentum
+  // projections: fork after the X step, join at the end of the iteration.
+  hipStream_t side = nullptr;
+  hipEvent_t fork_ev = nullptr, join_ev = nullptr;
   int64_t t = 0;
   vemb::HostModel host;
   vemb::OpTables ops_host{};
