@@ -320,16 +320,10 @@ int vemb_create_problem(const vemb_hamiltonian* H, const vemb_lattice* lat, cons
   p->n_op = n_op;
   p->opt = o;
   p->stream = static_cast<hipStream_t>(hip_stream);
-  if (hipStreamCreateWithFlags(&p->side, hipStreamNonBlocking) != hipSuccess ||
-      hipEventCreateWithFlags(&p->fork_ev, hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&p->join_ev, hipEventDisableTiming) != hipSuccess) {
-    vemb_destroy(p);
-    return fail(VEMB_E_HIP, "side stream / events");
-  }
   std::string err;
   int rc = build_model(*H, g, p->host, err);
   if (rc != VEMB_OK) {
-    vemb_destroy(p);
+    delete p;  // nothing on the device yet
     return fail(rc, err);
   }
   std::vector<double> tw, wk;
@@ -356,6 +350,10 @@ int vemb_create_problem(const vemb_hamiltonian* H, const vemb_lattice* lat, cons
     vemb_destroy(p);
     return code;
   };
+  if (hipStreamCreateWithFlags(&p->side, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&p->fork_ev, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&p->join_ev, hipEventDisableTiming) != hipSuccess)
+    return cleanup(fail(VEMB_E_HIP, "side stream / events"));
   const size_t nh = p->host.Hd.size() / ((size_t)n * n);
   if ((rc = dalloc(p, &p->H0, (size_t)m * m)) || (rc = dalloc(p, &p->Hd, nh * n * n)) ||
       (rc = dalloc(p, &p->hd_index, (size_t)P)) || (rc = dalloc(p, &p->tw, tw.size())) ||
