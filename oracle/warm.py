@@ -1,0 +1,127 @@
+"""FP64 reference of the learned warm start's state encoding (test infrastructure).
+
+A converged state of Algorithm 6 on a ring of M clusters is summarised by a
+fixed-size vector that does not depend on M, and any such vector is turned back
+into a valid starting state for a ring of any M.
+
+Offsets d = 1..M-1 are read as a direction and a distance: d <= M/2 is direction
+'+' at distance r = d, otherwise direction '-' at distance r = M - d.  Distances
+1, 2, 3 have blocks of their own; every distance >= 4 shares one 'far' block
+(the converged blocks level off with distance).  Per (direction, slot):
+    X_0d (n_op x n_op), Lambda_d (n x n), Lambda1_d (m x m), Lambda2_d (m x m), rho~_d (n x n).
+The vector is [X_00, rho_0, then for direction '+', '-': slots r=1, r=2, r=3, far],
+each matrix row-major.
+
+Encoding (rings of M >= 8 clusters) takes the blocks at d = r (direction '+') and
+d = M - r (direction '-') and, for the far slot, the mean over the distances
+4 <= r <= M/2.
+
+Decoding assigns each offset its slot's blocks and makes the state valid:
+  * X_00 symmetrised; X_0d and X_0,M-d made transposes of each other (X symmetric),
+    then X is projected onto the PSD cone through its momentum blocks (Section 3.3),
+    so the Lagrangian bound of the decoded point is a valid lower bound;
+  * rho_0 symmetrised and shifted along the identity to unit trace;
+  * rho~_d, Lambda_d, Lambda1_d, Lambda2_d symmetrised;  rho_d = rho~_d;  t = 0.
+
+Pins (tests/test_oracle_warm.py): decode(encode(s)) = s for a converged state on a
+ring whose only far offset is d = M/2 (M = 8); invariants of decoded random vectors (X PSD,
+unit trace of rho_0, symmetry); the bound at a decoded random point lies below the
+Jordan-Wigner ground-state energy.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from .alg6 import Problem, State, project_X
+
+NEAR = 3
+SLOTS = NEAR + 1  # distances 1..NEAR and 'far'
+
+
+def sizes(p: Problem):
+    n_op, n, m = p.n_op, p.n, p.m
+    block = n_op * n_op + 2 * n * n + 2 * m * m
+    return n_op * n_op + m * m + 2 * SLOTS * block, block
+
+
+def slot_of(d: int, M: int):
+    """(direction 0 for '+' / 1 for '-', slot 0..SLOTS-1) of offset d."""
+    if 2 * d <= M:
+        direction, r = 0, d
+    else:
+        direction, r = 1, M - d
+    return direction, min(r, SLOTS) - 1
+
+
+def _block_views(p: Problem, vec):
+    n_op, n, m = p.n_op, p.n, p.m
+    X00 = vec[:n_op * n_op].reshape(n_op, n_op)
+    o = n_op * n_op
+    rho0 = vec[o:o + m * m].reshape(m, m)
+    o += m * m
+    blocks = []
+    for _ in range(2 * SLOTS):
+        parts = []
+        for shape in ((n_op, n_op), (n, n), (m, m), (m, m), (n, n)):
+            k = shape[0] * shape[1]
+            parts.append(vec[o:o + k].reshape(shape))
+            o += k
+        blocks.append(parts)
+    return X00, rho0, blocks
+
+
+def encode(p: Problem, s: State) -> np.ndarray:
+    if p.My != 1:
+        raise ValueError("the warm-start encoding covers rings (one-dimensional cluster lattices)")
+    if p.M < 2 * NEAR + 2:
+        raise ValueError(f"encoding needs M >= {2 * NEAR + 2} clusters (distinct near offsets and a far offset)")
+    total, _ = sizes(p)
+    vec = np.zeros(total)
+    X00, rho0, blocks = _block_views(p, vec)
+    X00[...] = s.X[0]
+    rho0[...] = s.rho0
+    M = p.M
+
+    def grab(d):
+        return (s.X[d], s.Lam[d - 1], s.Lam1[d - 1], s.Lam2[d - 1], s.rho_t[d - 1])
+
+    for direction in (0, 1):
+        for r in range(1, NEAR + 1):
+            d = r if direction == 0 else M - r
+            for dst, src in zip(blocks[direction * SLOTS + r - 1], grab(d)):
+                dst[...] = src
+        far = range(NEAR + 1, M // 2 + 1)
+        for k, dst in enumerate(blocks[direction * SLOTS + NEAR]):
+            dst[...] = np.mean([grab(r if direction == 0 else M - r)[k] for r in far], axis=0)
+    return vec
+
+
+def _sym(a):
+    return 0.5 * (a + a.T)
+
+
+def _unit_trace(a):
+    k = a.shape[0]
+    return a + (1.0 - np.trace(a)) / k * np.eye(k)
+
+
+def decode(p: Problem, vec) -> State:
+    if p.My != 1:
+        raise ValueError("the warm-start encoding covers rings (one-dimensional cluster lattices)")
+    vec = np.asarray(vec, np.float64)
+    X00, rho0, blocks = _block_views(p, vec)
+    M, P = p.M, p.P
+    raw = {}
+    for d in range(1, M):
+        direction, slot = slot_of(d, M)
+        raw[d] = blocks[direction * SLOTS + slot]
+    Xp = np.zeros((M, p.n_op, p.n_op))
+    Xp[0] = _sym(X00)
+    for d in range(1, M):
+        Xp[d] = 0.5 * (raw[d][0] + raw[M - d][0].T)
+    X, _ = project_X(p, Xp)
+    Lam = np.stack([_sym(raw[d][1]) for d in range(1, M)]) if P else np.zeros((0, p.n, p.n))
+    Lam1 = np.stack([_sym(raw[d][2]) for d in range(1, M)]) if P else np.zeros((0, p.m, p.m))
+    Lam2 = np.stack([_sym(raw[d][3]) for d in range(1, M)]) if P else np.zeros((0, p.m, p.m))
+    rho_t = np.stack([_sym(raw[d][4]) for d in range(1, M)]) if P else np.zeros((0, p.n, p.n))
+    return State(0, X, _unit_trace(_sym(rho0)), rho_t.copy(), rho_t, Lam, Lam1, Lam2)

@@ -186,3 +186,31 @@ def hermitian_batch(n: int, batch: int, tag: int = 1) -> np.ndarray:
     rng = np.random.default_rng([BASE_SEED, tag, n, batch, 7])
     A = rng.standard_normal((batch, n, n)) + 1j * rng.standard_normal((batch, n, n))
     return (A + np.conj(np.swapaxes(A, 1, 2))) / (2.0 * np.sqrt(n))
+
+
+# ---------------------------------------------------------------------------
+# Learned warm start: seeded initial network parameters and input features
+# ---------------------------------------------------------------------------
+
+def mlp_init(dims, tag: int = 0) -> np.ndarray:
+    """Initial parameters, flat FP32 in the layout W_0 (out x in, row-major), b_0, W_1, b_1, ...
+    drawn uniform in +-1/sqrt(fan_in) from a seeded stream."""
+    rng = np.random.default_rng([BASE_SEED, 13, tag])
+    parts = []
+    for l in range(len(dims) - 1):
+        k = 1.0 / np.sqrt(dims[l])
+        parts.append(rng.uniform(-k, k, size=dims[l + 1] * dims[l]))
+        parts.append(rng.uniform(-k, k, size=dims[l + 1]))
+    return np.concatenate(parts).astype(np.float32)
+
+
+def mlp_features(d: dict) -> np.ndarray:
+    """Network input of one instance draw: (TFI?, XXZ?, h for TFI, J_z for XXZ, k / 8) with k = 2L."""
+    tfi = d["model"] == "tfi"
+    return np.array([1.0 if tfi else 0.0, 0.0 if tfi else 1.0, d["h"] if tfi else 0.0,
+                     0.0 if tfi else d["Jz"], 2 * d["L"] / 8.0], dtype=np.float32)
+
+
+def mlp_batch(n_in: int, batch: int, tag: int = 0) -> np.ndarray:
+    """Seeded FP32 inputs for network parity tests."""
+    return np.random.default_rng([BASE_SEED, 14, tag]).standard_normal((batch, n_in)).astype(np.float32)
