@@ -262,6 +262,65 @@ int vemb_batch_info(const vemb_batch* b, int* classes, int* launches_per_iterati
 int vemb_batch_sync(vemb_batch* b);
 void vemb_batch_destroy(vemb_batch* b);
 
+/* ---- Learned warm start ------------------------------------------------------
+ * A multilayer perceptron maps Hamiltonian parameters to a fixed-size encoding
+ * of a converged state, and the encoding becomes the starting point of a new
+ * solve.  Any decoded point is valid: X is projected onto the PSD cone, so the
+ * Lagrangian bound (Section 2.4) at it is a lower bound, and the plain cold
+ * start stays the reference the network is judged against.
+ *
+ * Encoding of a ring of M clusters (vemb_warm_size floats, FP32, row-major
+ * matrices): [X_00, rho_0, then for direction '+' and '-' the slots of distance
+ * 1..near and 'far' (> near), each X_0d, Lambda_d, Lambda1_d, Lambda2_d, rho~_d].
+ * Offset d is direction '+' at distance d when 2d <= M, else '-' at M - d.  With
+ * near >= M/2 the encoding is exact; a smaller near gives a size independent of
+ * M, the far slot averaging distances near+1..M/2. */
+int vemb_warm_size(const vemb_problem* p, int near, int64_t* count);
+/* vec (DEVICE, vemb_warm_size floats) <- the problem's current state.  Needs
+ * M >= near + 1.  Asynchronous.  VEMB_E_UNSUPPORTED for 2-D lattices. */
+int vemb_warm_encode(vemb_problem* p, int near, float* vec);
+/* The problem's state <- decode(vec) (DEVICE): every offset takes its slot's
+ * blocks, X_0,M-d = X_0d^T and X_00, rho_0, rho~, Lambdas symmetrised, Tr rho_0
+ * = 1, rho = rho~, then X projected onto the PSD cone through its momentum
+ * blocks (FP64).  Resets the iteration count (eigensolves restart cold).
+ * Asynchronous. */
+int vemb_warm_start(vemb_problem* p, int near, const float* vec);
+
+/* Network: dims[0] inputs, dims[1..n_dims-2] silu hidden layers, dims[n_dims-1]
+ * outputs.  Parameters flat FP32 in the order W_0 (dims[1] x dims[0], row-major),
+ * b_0, W_1, b_1, ...; the passes read the weights rounded to bfloat16 (nearest
+ * even) and compute in FP32.  Targets are learned normalised per output,
+ * t_hat = (t - mean) / std; the loss is the mean of (y - t_hat)^2 over batch and
+ * outputs; Adam (b1 0.9, b2 0.999, eps 1e-8) updates the FP32 parameters.
+ * All x / y / target / row arrays below are DEVICE pointers, row-major. */
+typedef struct vemb_mlp vemb_mlp;
+/* params: host array of vemb_mlp_num_params floats, or NULL for zeros.  Work
+ * buffers are sized for up to max_batch rows.  Synchronises hip_stream. */
+int vemb_mlp_create(const int32_t* dims, int n_dims, const float* params, int max_batch, void* hip_stream,
+                    vemb_mlp** out);
+int vemb_mlp_num_params(const vemb_mlp* n, int64_t* count);
+int vemb_mlp_set_params(vemb_mlp* n, const float* params_host);
+int vemb_mlp_get_params(vemb_mlp* n, float* params_host);
+/* mean / std per output over `count` target rows (FP64 sums); std floored at
+ * max(1e-6, rel_floor * largest std) so that near-constant outputs are not
+ * magnified into noise. */
+int vemb_mlp_fit_normalization(vemb_mlp* n, const float* targets, int count, float rel_floor);
+int vemb_mlp_get_normalization(vemb_mlp* n, float* mean_host, float* std_host);
+int vemb_mlp_set_normalization(vemb_mlp* n, const float* mean_host, const float* std_host);
+/* y (batch x outputs) = denormalised network output for x (batch x inputs). */
+int vemb_mlp_forward(vemb_mlp* n, const float* x, float* y, int batch);
+/* Loss and gradient for one batch; grad (DEVICE, num_params floats) may be NULL;
+ * loss (host) may be NULL, else the call synchronises. */
+int vemb_mlp_gradients(vemb_mlp* n, const float* x, const float* targets, int batch, double* loss, float* grad);
+/* One Adam step with the gradient of the last vemb_mlp_gradients / train step. */
+int vemb_mlp_adam_step(vemb_mlp* n, float lr);
+/* Gradient + Adam on the rows `rows[0..batch)` (DEVICE int32, indices into the
+ * count rows of X and T; NULL = the first batch rows).  Rows outside 0..count-1
+ * read as zeros.  loss (host) may be NULL, else the call synchronises. */
+int vemb_mlp_train_step(vemb_mlp* n, const float* X, const float* T, int count, const int32_t* rows, int batch,
+                        float lr, double* loss);
+void vemb_mlp_destroy(vemb_mlp* n);
+
 #ifdef __cplusplus
 }
 #endif

@@ -92,12 +92,14 @@ def forward(params, x, rounding=True):
     return a, (P, zs, acts)
 
 
-def normalisation(targets):
-    """Per-output mean and standard deviation (floored) of a training set."""
+def normalisation(targets, rel_floor=0.0):
+    """Per-output mean and standard deviation of a training set, the deviation floored at
+    max(STD_FLOOR, rel_floor * largest deviation): outputs that barely vary are not blown up
+    into noise the network would have to fit."""
     t = np.asarray(targets, np.float64)
     mean = t.mean(axis=0)
     std = np.sqrt(((t - mean) ** 2).mean(axis=0))
-    return mean, np.maximum(std, STD_FLOOR)
+    return mean, np.maximum(std, max(STD_FLOOR, rel_floor * std.max()))
 
 
 def loss_and_grads(params, x, t, mean, std, rounding=True):

@@ -457,6 +457,54 @@ int run_iterations(vemb_problem* p, int iters, int prec) {
 }
 }  // namespace
 
+namespace {
+// X <- Pi(X') through the momentum blocks (steps 7-9 alone), FP64, cold eigensolves.
+int project_x(vemb_problem* p) {
+  const StepArgs& a = p->a;
+  hipStream_t s = p->stream;
+  const int ms = p->opt.max_sweeps;
+  VEMB_TRY(hip_rc(launch_dft_forward(a, s), "forward DFT"));
+  if (a.n_op > 64)
+    VEMB_TRY(hip_rc(launch_momentum_projection_big(a.Xh, a.n_op, a.Ku, VEMB_FP64, ms, a.sweeps + a.P, a.Vmom, 1,
+                                                   a.wscr_mom, a.tscr_mom, s),
+                    "momentum projection"));
+  else
+    VEMB_TRY(hip_rc(launch_momentum_projection(a.Xh, a.n_op, a.Ku, VEMB_FP64, ms, a.sweeps + a.P, a.Vmom, 1,
+                                               p->tpb_mom, s),
+                    "momentum projection"));
+  return hip_rc(launch_dft_inverse(a, s), "inverse DFT");
+}
+
+int check_ring(const vemb_problem* p) {
+  if (p->g.My != 1) return fail(VEMB_E_UNSUPPORTED, "the warm-start encoding covers rings (one-dimensional cluster lattices)");
+  return VEMB_OK;
+}
+}  // namespace
+
+int vemb_warm_size(const vemb_problem* p, int near, int64_t* count) {
+  if (!p || !count || near < 1) return fail(VEMB_E_INVALID, "bad arguments to vemb_warm_size");
+  VEMB_TRY(check_ring(p));
+  *count = warm_layout(p->a, near).total;
+  return VEMB_OK;
+}
+
+int vemb_warm_encode(vemb_problem* p, int near, float* vec) {
+  if (!p || !vec || near < 1) return fail(VEMB_E_INVALID, "bad arguments to vemb_warm_encode");
+  VEMB_TRY(check_ring(p));
+  if (p->g.M < near + 1) return fail(VEMB_E_UNSUPPORTED, "encoding needs more clusters than near distances");
+  return hip_rc(launch_warm_encode(p->a, near, vec, p->stream), "warm-start encode");
+}
+
+int vemb_warm_start(vemb_problem* p, int near, const float* vec) {
+  if (!p || !vec || near < 1) return fail(VEMB_E_INVALID, "bad arguments to vemb_warm_start");
+  VEMB_TRY(check_ring(p));
+  VEMB_TRY(hip_rc(launch_warm_decode(p->a, near, vec, p->stream), "warm-start decode"));
+  VEMB_TRY(project_x(p));
+  p->t = 0;
+  p->v_valid = false;
+  return VEMB_OK;
+}
+
 int vemb_step(vemb_problem* p, int iters) {
   if (!p || iters < 0) return fail(VEMB_E_INVALID, "bad arguments to vemb_step");
   return run_iterations(p, iters, p->opt.precision);

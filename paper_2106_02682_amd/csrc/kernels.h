@@ -128,4 +128,17 @@ hipError_t launch_dft_forward(const StepArgs& a, hipStream_t st);
 hipError_t launch_dft_inverse(const StepArgs& a, hipStream_t st);
 hipError_t launch_bound_build(const StepArgs& a, hipStream_t st);
 
+// ----- Learned warm start: fixed-size state encoding of rings (warm.hip) -----
+// `near` distances have blocks of their own, larger distances share a 'far' block.
+struct WarmLayout {
+  int near;
+  long x00, rho0, block0, bsz, total;  // offsets / sizes in floats
+  long oX, oL, oL1, oL2, oR;           // parts of a block
+};
+WarmLayout warm_layout(const StepArgs& a, int near);
+// vec (device, warm_layout(a, near).total floats) <- state; needs M >= near + 1.
+hipError_t launch_warm_encode(const StepArgs& a, int near, float* vec, hipStream_t st);
+// State <- vec: X' (in Xp, to be projected), rho0, rho~ = rho, Lambda, Lambda1, Lambda2.
+hipError_t launch_warm_decode(const StepArgs& a, int near, const float* vec, hipStream_t st);
+
 }  // namespace vemb

@@ -30,6 +30,10 @@ EXPORTS = [
     "vemb_psd_project_batched_ex", "vemb_set_profiling", "vemb_get_profile", "vemb_refine",
     "vemb_tuned_threads", "vemb_problem_threads", "vemb_batch_create", "vemb_batch_step", "vemb_batch_dual_bounds",
     "vemb_batch_primal_energies", "vemb_batch_info", "vemb_batch_sync", "vemb_batch_destroy",
+    "vemb_warm_size", "vemb_warm_encode", "vemb_warm_start", "vemb_mlp_create", "vemb_mlp_num_params",
+    "vemb_mlp_set_params", "vemb_mlp_get_params", "vemb_mlp_fit_normalization", "vemb_mlp_get_normalization",
+    "vemb_mlp_set_normalization", "vemb_mlp_forward", "vemb_mlp_gradients", "vemb_mlp_adam_step",
+    "vemb_mlp_train_step", "vemb_mlp_destroy",
 ]
 KERNELS = ["pair_update", "pair_xstep", "pair_projection", "cluster_update", "dft_forward", "momentum_projection",
            "dft_inverse", "bound_build", "lambda_min"]
@@ -128,8 +132,28 @@ def lib():
     L.vemb_batch_sync.argtypes = [vp]
     L.vemb_batch_destroy.argtypes = [vp]
     L.vemb_batch_destroy.restype = None
+    _FP = ctypes.POINTER(ctypes.c_float)
+    _I64 = ctypes.POINTER(ctypes.c_int64)
+    L.vemb_warm_size.argtypes = [vp, ctypes.c_int, _I64]
+    L.vemb_warm_encode.argtypes = [vp, ctypes.c_int, vp]
+    L.vemb_warm_start.argtypes = [vp, ctypes.c_int, vp]
+    L.vemb_mlp_create.argtypes = [ctypes.POINTER(ctypes.c_int32), ctypes.c_int, _FP, ctypes.c_int, vp,
+                                  ctypes.POINTER(vp)]
+    L.vemb_mlp_num_params.argtypes = [vp, _I64]
+    L.vemb_mlp_set_params.argtypes = [vp, _FP]
+    L.vemb_mlp_get_params.argtypes = [vp, _FP]
+    L.vemb_mlp_fit_normalization.argtypes = [vp, vp, ctypes.c_int, ctypes.c_float]
+    L.vemb_mlp_get_normalization.argtypes = [vp, _FP, _FP]
+    L.vemb_mlp_set_normalization.argtypes = [vp, _FP, _FP]
+    L.vemb_mlp_forward.argtypes = [vp, vp, vp, ctypes.c_int]
+    L.vemb_mlp_gradients.argtypes = [vp, vp, vp, ctypes.c_int, _DP, vp]
+    L.vemb_mlp_adam_step.argtypes = [vp, ctypes.c_float]
+    L.vemb_mlp_train_step.argtypes = [vp, vp, vp, ctypes.c_int, vp, ctypes.c_int, ctypes.c_float, _DP]
+    L.vemb_mlp_destroy.argtypes = [vp]
+    L.vemb_mlp_destroy.restype = None
     for name in EXPORTS:
-        if name not in ("vemb_default_options", "vemb_destroy", "vemb_last_error", "vemb_batch_destroy"):
+        if name not in ("vemb_default_options", "vemb_destroy", "vemb_last_error", "vemb_batch_destroy",
+                        "vemb_mlp_destroy"):
             getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -429,6 +453,115 @@ class Batch:
     def close(self):
         if self.h:
             lib().vemb_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+# ---------------------------------------------------------------------------
+# Learned warm start
+# ---------------------------------------------------------------------------
+
+def _dev(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _fp(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+
+
+WARM_NEAR = 3
+
+
+def warm_size(h, near=WARM_NEAR):
+    c = ctypes.c_int64()
+    _check(lib().vemb_warm_size(h, int(near), ctypes.byref(c)))
+    return c.value
+
+
+def warm_encode(h, out, near=WARM_NEAR):
+    """out: device float32 tensor of warm_size(h, near) elements."""
+    _check(lib().vemb_warm_encode(h, int(near), _dev(out)))
+
+
+def warm_start(h, vec, near=WARM_NEAR):
+    """vec: device float32 tensor of warm_size(h, near) elements."""
+    _check(lib().vemb_warm_start(h, int(near), _dev(vec)))
+
+
+class MLP:
+    """The warm-start network (parameters and work buffers on the device)."""
+
+    def __init__(self, dims, params=None, max_batch=512, stream=None):
+        self.dims = [int(d) for d in dims]
+        arr = (ctypes.c_int32 * len(self.dims))(*self.dims)
+        out = ctypes.c_void_p()
+        p = None
+        if params is not None:
+            params = np.ascontiguousarray(params, dtype=np.float32)
+            p = _fp(params)
+        st = current_stream() if stream is None else stream
+        _check(lib().vemb_mlp_create(arr, len(self.dims), p, int(max_batch), st, ctypes.byref(out)))
+        self.h = out
+        c = ctypes.c_int64()
+        _check(lib().vemb_mlp_num_params(self.h, ctypes.byref(c)))
+        self.num_params = c.value
+
+    def set_params(self, params):
+        params = np.ascontiguousarray(params, dtype=np.float32)
+        assert params.size == self.num_params
+        _check(lib().vemb_mlp_set_params(self.h, _fp(params)))
+
+    def get_params(self):
+        out = np.empty(self.num_params, np.float32)
+        _check(lib().vemb_mlp_get_params(self.h, _fp(out)))
+        return out
+
+    def fit_normalization(self, targets, rel_floor=0.0):
+        _check(lib().vemb_mlp_fit_normalization(self.h, _dev(targets), int(targets.shape[0]), float(rel_floor)))
+
+    def get_normalization(self):
+        O = self.dims[-1]
+        mean, std = np.empty(O, np.float32), np.empty(O, np.float32)
+        _check(lib().vemb_mlp_get_normalization(self.h, _fp(mean), _fp(std)))
+        return mean, std
+
+    def set_normalization(self, mean, std):
+        mean = np.ascontiguousarray(mean, np.float32)
+        std = np.ascontiguousarray(std, np.float32)
+        _check(lib().vemb_mlp_set_normalization(self.h, _fp(mean), _fp(std)))
+
+    def forward(self, x, y):
+        _check(lib().vemb_mlp_forward(self.h, _dev(x), _dev(y), int(x.shape[0])))
+
+    def gradients(self, x, t, grad=None):
+        loss = ctypes.c_double()
+        _check(lib().vemb_mlp_gradients(self.h, _dev(x), _dev(t), int(x.shape[0]), ctypes.byref(loss), _dev(grad)))
+        return loss.value
+
+    def adam_step(self, lr):
+        _check(lib().vemb_mlp_adam_step(self.h, float(lr)))
+
+    def train_step(self, X, T, rows=None, batch=None, lr=1e-3, want_loss=False):
+        batch = int(batch if batch is not None else (rows.shape[0] if rows is not None else X.shape[0]))
+        loss = ctypes.c_double()
+        _check(lib().vemb_mlp_train_step(self.h, _dev(X), _dev(T), int(X.shape[0]), _dev(rows), batch, float(lr),
+                                         ctypes.byref(loss) if want_loss else None))
+        return loss.value if want_loss else None
+
+    def close(self):
+        if self.h:
+            lib().vemb_mlp_destroy(self.h)
             self.h = None
 
     def __del__(self):

@@ -1,0 +1,205 @@
+"""Learned warm start: training data from the solver, training, and the cold / warm comparison.
+
+Every numerical step runs in the library's kernels (batched Algorithm 6 iterations,
+state encoding and decoding, the network's forward / backward / Adam); this module
+only sequences the calls and keeps the host-side bookkeeping (which instance is in
+which row, when each run reached the gap).
+
+Gap.  The Lagrangian bound LB_t of every iterate is a certified lower bound (X PSD).
+For an instance, LB_ref is the best bound seen over a long cold reference run and the
+warm run; the relative gap of iterate t is (LB_ref - LB_t) / |LB_ref|, and a run has
+converged when it stays at or below the tolerance from then on (every later check).
+"""
+from __future__ import annotations
+
+import math
+import time
+
+import numpy as np
+
+import synth
+from . import vemb
+
+HIDDEN = (256, 256, 256)
+
+
+def _torch():
+    import torch
+
+    return torch
+
+
+def open_problems(draws, precision="fp64"):
+    return [vemb.Problem.from_workload(synth.instance_workload(d, name=f"i{k}"), precision=precision)
+            for k, d in enumerate(draws)]
+
+
+def features(draws) -> np.ndarray:
+    return np.stack([synth.mlp_features(d) for d in draws]).astype(np.float32)
+
+
+def converged_targets(draws, iters, near, chunk=64, log=None):
+    """Solve every draw for `iters` iterations (batched, graph-replayed) and encode its state
+    (`near` distances exact).  Returns (features, targets), targets a device float32 tensor."""
+    torch = _torch()
+    size = None
+    rows = []
+    for c0 in range(0, len(draws), chunk):
+        part = draws[c0:c0 + chunk]
+        probs = open_problems(part)
+        try:
+            with vemb.Batch(probs) as b:
+                done = 0
+                while done < iters:
+                    k = min(2000, iters - done)
+                    b.step(k)
+                    b.sync()
+                    done += k
+                    if log:
+                        log(f"training data: instances {c0}..{c0 + len(part) - 1}: {done}/{iters} iterations")
+            for p in probs:
+                s = vemb.warm_size(p.h, near)
+                if size is None:
+                    size = s
+                if s != size:
+                    raise ValueError("all instances of a training set must share the cluster size")
+                v = torch.empty(s, dtype=torch.float32, device="cuda")
+                vemb.warm_encode(p.h, v, near)
+                rows.append(v)
+            torch.cuda.synchronize()
+        finally:
+            for p in probs:
+                p.close()
+    return features(draws), torch.stack(rows)
+
+
+STD_REL_FLOOR = 1e-3
+
+
+def make_network(n_out, max_batch=512, tag=0):
+    dims = [synth.N_FEATURES, *HIDDEN, n_out]
+    return vemb.MLP(dims, synth.mlp_init(dims, tag=tag), max_batch=max_batch)
+
+
+def train(net, X, T, steps=3000, batch=64, lr=1e-3, lr_min=1e-5, seed=0, log=None):
+    """Adam on random minibatches (seeded), cosine learning-rate decay.  X, T device tensors."""
+    torch = _torch()
+    count = X.shape[0]
+    batch = min(batch, count)
+    net.fit_normalization(T, STD_REL_FLOOR)
+    rng = np.random.default_rng([synth.BASE_SEED, 15, seed])
+    losses = []
+    for s in range(steps):
+        rows = torch.from_numpy(rng.choice(count, size=batch, replace=False).astype(np.int32)).cuda()
+        lr_s = lr_min + 0.5 * (lr - lr_min) * (1 + math.cos(math.pi * s / max(1, steps - 1)))
+        want = (s % 250 == 0) or s == steps - 1
+        loss = net.train_step(X, T, rows=rows, lr=lr_s, want_loss=want)
+        if want:
+            losses.append((s, loss))
+            if log:
+                log(f"train step {s}: loss {loss:.3e} lr {lr_s:.2e}")
+    return losses
+
+
+def predict(net, X):
+    torch = _torch()
+    Y = torch.empty((X.shape[0], net.dims[-1]), dtype=torch.float32, device="cuda")
+    net.forward(X, Y)
+    return Y
+
+
+def bound_trajectory(probs, iters, every, warm_vecs=None, near=None, log=None, tag=""):
+    """Step a batch of problems `iters` iterations, reading the bounds every `every`.
+    Returns (its, lbs[len(its), count], secs[len(its)]) with wall-clock seconds since the
+    start (the start includes decoding the warm vectors, if given)."""
+    torch = _torch()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    if warm_vecs is not None:
+        for p, v in zip(probs, warm_vecs):
+            vemb.warm_start(p.h, v, near)
+    its, lbs, secs = [], [], []
+    with vemb.Batch(probs) as b:
+        done = 0
+        while done < iters:
+            b.step(every)
+            done += every
+            lbs.append(b.dual_bounds())
+            its.append(done)
+            secs.append(time.perf_counter() - t0)
+            if log and done % 2000 == 0:
+                log(f"{tag}: {done}/{iters} iterations")
+    return np.array(its), np.array(lbs), np.array(secs)
+
+
+def first_converged(its, lbs, secs, lb_ref, tol):
+    """Per instance: (iterations, seconds) from which the gap stays <= tol, or (None, None)."""
+    gap = (lb_ref[None, :] - lbs) / np.abs(lb_ref)[None, :]
+    out = []
+    for j in range(lbs.shape[1]):
+        ok = gap[:, j] <= tol
+        if not ok[-1]:
+            out.append((None, None))
+            continue
+        k = len(ok) - 1
+        while k > 0 and ok[k - 1]:
+            k -= 1
+        out.append((int(its[k]), float(secs[k])))
+    return out
+
+
+def compare(draws, net, near, iters, ref_iters, every=20, tol=1e-6, log=None):
+    """Cold reference run (ref_iters) and warm run (iters) on the same instances."""
+    torch = _torch()
+    probs = open_problems(draws)
+    try:
+        c_its, c_lbs, c_secs = bound_trajectory(probs, ref_iters, every, log=log, tag="cold")
+    finally:
+        for p in probs:
+            p.close()
+    probs = open_problems(draws)
+    try:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        Xh = torch.from_numpy(features(draws)).cuda()
+        V = predict(net, Xh)
+        torch.cuda.synchronize()
+        t_pred = time.perf_counter() - t0
+        w_its, w_lbs, w_secs = bound_trajectory(probs, iters, every, warm_vecs=[V[i] for i in range(len(probs))],
+                                                near=near, log=log, tag="warm")
+        w_secs = w_secs + t_pred
+    finally:
+        for p in probs:
+            p.close()
+    lb_ref = np.maximum(c_lbs.max(axis=0), w_lbs.max(axis=0))
+    cold = first_converged(c_its[c_its <= iters], c_lbs[c_its <= iters], c_secs[c_its <= iters], lb_ref, tol)
+    warm = first_converged(w_its, w_lbs, w_secs, lb_ref, tol)
+    w0 = (lb_ref - w_lbs[0]) / np.abs(lb_ref)
+    c0 = (lb_ref - c_lbs[0]) / np.abs(lb_ref)
+    return {
+        "lb_ref": lb_ref, "cold": cold, "warm": warm, "predict_seconds": t_pred,
+        "first_gap_cold": c0, "first_gap_warm": w0,
+        "cold_traj": (c_its, c_lbs), "warm_traj": (w_its, w_lbs),
+    }
+
+
+def summarise(res, iters):
+    """Medians over instances; a run that never reached the gap counts as `iters` (censored)."""
+    def med(pairs, k):
+        vals = [p[k] if p[k] is not None else math.inf for p in pairs]
+        return float(np.median(vals))
+
+    n = len(res["cold"])
+    return {
+        "instances": n,
+        "cold_reached": sum(p[0] is not None for p in res["cold"]),
+        "warm_reached": sum(p[0] is not None for p in res["warm"]),
+        "median_iters_cold": med(res["cold"], 0),
+        "median_iters_warm": med(res["warm"], 0),
+        "median_seconds_cold": med(res["cold"], 1),
+        "median_seconds_warm": med(res["warm"], 1),
+        "horizon_iters": iters,
+        "predict_seconds": res["predict_seconds"],
+        "median_first_gap_cold": float(np.median(res["first_gap_cold"])),
+        "median_first_gap_warm": float(np.median(res["first_gap_warm"])),
+    }

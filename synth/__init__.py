@@ -192,6 +192,17 @@ def hermitian_batch(n: int, batch: int, tag: int = 1) -> np.ndarray:
 # Learned warm start: seeded initial network parameters and input features
 # ---------------------------------------------------------------------------
 
+def family_draws(count: int, N: int, L: int, split: int = 0) -> list:
+    """Draws of the learned-start recipe (model, h, J_z from the same streams as the
+    training / held-out draws) on one ring: N sites in clusters of L (a parameter sweep)."""
+    out = []
+    for i in range(count):
+        d = draw_instance(np.random.default_rng([BASE_SEED, 5, split, i]))
+        d["N"], d["L"] = N, L
+        out.append(d)
+    return out
+
+
 def mlp_init(dims, tag: int = 0) -> np.ndarray:
     """Initial parameters, flat FP32 in the layout W_0 (out x in, row-major), b_0, W_1, b_1, ...
     drawn uniform in +-1/sqrt(fan_in) from a seeded stream."""
@@ -205,10 +216,16 @@ def mlp_init(dims, tag: int = 0) -> np.ndarray:
 
 
 def mlp_features(d: dict) -> np.ndarray:
-    """Network input of one instance draw: (TFI?, XXZ?, h for TFI, J_z for XXZ, k / 8) with k = 2L."""
+    """Network input of one instance draw, a fixed featurisation of (model, h, J_z, k = 2L):
+    one-hot model, the model's parameter p (h for TFI, J_z for XXZ), p^2, |p - 1|,
+    tanh(4 (p - 1)) (both models change phase at p = 1) and k / 8."""
     tfi = d["model"] == "tfi"
-    return np.array([1.0 if tfi else 0.0, 0.0 if tfi else 1.0, d["h"] if tfi else 0.0,
-                     0.0 if tfi else d["Jz"], 2 * d["L"] / 8.0], dtype=np.float32)
+    p = d["h"] if tfi else d["Jz"]
+    return np.array([1.0 if tfi else 0.0, 0.0 if tfi else 1.0, p, p * p, abs(p - 1.0), np.tanh(4.0 * (p - 1.0)),
+                     2 * d["L"] / 8.0], dtype=np.float32)
+
+
+N_FEATURES = 7
 
 
 def mlp_batch(n_in: int, batch: int, tag: int = 0) -> np.ndarray:

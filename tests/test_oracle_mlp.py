@@ -85,3 +85,10 @@ def test_normalisation_of_constant_column_is_floored():
     mean, std = mlp.normalisation(t)
     assert mean.tolist() == [1.0, 4.0]
     assert std[0] == mlp.STD_FLOOR and abs(std[1] - np.sqrt(8.0 / 3.0)) < 1e-15
+
+
+def test_relative_std_floor():
+    t = np.array([[0.0, 0.0, 1.0, 0.0], [0.0, 2e-3, -1.0, 2e-4], [0.0, -2e-3, 1.0, -2e-4], [0.0, 0.0, -1.0, 0.0]])
+    _, std = mlp.normalisation(t, rel_floor=1e-3)
+    # floor = 1e-3 * 1: column 0 (constant) and column 3 (std 1.4e-4) are lifted to it
+    assert np.allclose(std, [1e-3, np.sqrt(2e-6), 1.0, 1e-3], rtol=1e-15, atol=0)

@@ -31,12 +31,26 @@ def test_round_trip_on_solver_state(ring8):
 def test_slot_assignment():
     assert [warm.slot_of(d, 8) for d in range(1, 8)] == [(0, 0), (0, 1), (0, 2), (0, 3), (1, 2), (1, 1), (1, 0)]
     assert [warm.slot_of(d, 11) for d in (1, 4, 5, 6, 7, 10)] == [(0, 0), (0, 3), (0, 3), (1, 3), (1, 3), (1, 0)]
+    assert [warm.slot_of(d, 11, 5) for d in (4, 5, 6, 7)] == [(0, 3), (0, 4), (1, 4), (1, 3)]
 
 
-def test_encoding_needs_eight_clusters():
-    p = alg6.Problem.from_workload(synth.tfi_ring(12, 2, 1.0))  # M = 6
+def test_encoding_needs_more_clusters_than_near_distances():
+    p = alg6.Problem.from_workload(synth.tfi_ring(6, 2, 1.0))  # M = 3
     with pytest.raises(ValueError):
-        warm.encode(p, alg6.initial_state(p))
+        warm.encode(p, alg6.initial_state(p), near=3)
+    warm.encode(p, alg6.initial_state(p), near=1)
+
+
+@pytest.mark.parametrize("N", [22, 32])
+def test_exact_round_trip_with_all_distances(N):
+    w = synth.tfi_ring(N, 2, 1.3)  # M = 11 (odd) and 16 (even)
+    p = alg6.Problem.from_workload(w)
+    s, _ = alg6.solve(p, 60)
+    near = p.M // 2
+    s2 = warm.decode(p, warm.encode(p, s, near), near)
+    for k in ("X", "rho0", "rho_t", "Lam", "Lam1", "Lam2"):
+        a, b = getattr(s, k), getattr(s2, k)
+        assert np.abs(a - b).max() <= 1e-11 * max(1.0, np.abs(a).max()), k
 
 
 def _random_vec(p, seed):
