@@ -11,6 +11,12 @@ clusters of 3 sites (M = 128 clusters): 127 pair marginals of 64 x 64 and 65
 unique 64 x 64 complex momentum blocks per step.
 
 Prints ONE JSON line.  ``value`` = pair PSD projections per second (64 x 64).
+
+The second half of the metric, time to a 1e-6 certified-bound gap with the learned
+warm start against the cold start, is measured after the throughput run (object
+``warm_start``): a parameter-sweep family (TFI or XXZ ring, N = 64, 2-site clusters,
+seeded draws of model, h, J_z) provides solver-generated training states; the network
+is trained with the library's kernels; held-out draws are then run cold and warm.
 """
 import argparse
 import hashlib
@@ -93,6 +99,52 @@ def cpu_baseline(workload, seconds):
     }
 
 
+def log(msg):
+    """Progress on stderr (the JSON line is the only stdout output)."""
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
+def warm_start_leg(args):
+    """Learned warm start vs cold start on held-out draws of one ring family (see module doc)."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2106_02682_amd import warmstart as ws
+
+    N, L = 64, 2
+    near = N // L // 2
+    train = synth.family_draws(args.warm_train, N, L, split=0)
+    held = synth.family_draws(args.warm_heldout, N, L, split=1)
+    t0 = time.perf_counter()
+    log(f"warm start: solving {len(train)} training draws for {args.warm_train_iters} iterations")
+    X, T = ws.converged_targets(train, args.warm_train_iters, near, log=log)
+    t_data = time.perf_counter() - t0
+    net = ws.make_network(T.shape[1], max_batch=max(64, args.warm_heldout))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    log(f"warm start: training {args.warm_steps} steps")
+    losses = ws.train(net, torch.from_numpy(X).cuda(), T, steps=args.warm_steps, batch=64, lr=2e-3)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    log(f"warm start: {len(held)} held-out draws, cold {args.warm_ref} / warm {args.warm_horizon} iterations")
+    res = ws.compare(held, net, near, iters=args.warm_horizon, ref_iters=args.warm_ref, every=50, tol=1e-6, log=log)
+    net.close()
+    out = {
+        "family": f"TFI/XXZ ring N={N}, {L}-site clusters (M={N // L}); model, h, Jz from the seeded draws",
+        "train_instances": args.warm_train, "train_solver_iters": args.warm_train_iters,
+        "train_steps": args.warm_steps, "final_train_loss": losses[-1][1], "data_seconds": t_data,
+        "train_seconds": t_train, "heldout": args.warm_heldout, "horizon_iters": args.warm_horizon,
+        "reference_iters_cold": args.warm_ref, "predict_seconds": res["predict_seconds"],
+        "median_first_gap_cold": float(np.median(res["first_gap_cold"])),
+        "median_first_gap_warm": float(np.median(res["first_gap_warm"])),
+    }
+    for tol in (1e-6, 1e-5):
+        r = ws.gap_report(res, tol, args.warm_horizon)
+        out[f"gap_{tol:.0e}"] = {k: v for k, v in r.items() if k not in ("tol", "horizon_iters")}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -102,6 +154,13 @@ def main():
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
     ap.add_argument("--lb-every", type=int, default=10)
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="oracle sample length (0 disables)")
+    ap.add_argument("--warm", type=int, default=1, help="run the learned warm-start leg (0 skips it)")
+    ap.add_argument("--warm-train", type=int, default=256)
+    ap.add_argument("--warm-train-iters", type=int, default=30000)
+    ap.add_argument("--warm-steps", type=int, default=20000)
+    ap.add_argument("--warm-heldout", type=int, default=16)
+    ap.add_argument("--warm-horizon", type=int, default=30000)
+    ap.add_argument("--warm-ref", type=int, default=60000)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (this build has no multi-GPU path); got --gpus {args.gpus}",
@@ -118,6 +177,7 @@ def main():
     w = synth.config_c2(args.h)[1]
     g = vemb.Problem.from_workload(w, precision=args.precision)
     info = g.info
+    log(f"throughput: {w.name}, {args.warmup} warm-up + {args.steps} timed steps")
     g.step(args.warmup)
     torch.cuda.synchronize()
     g.set_profiling(True)
@@ -177,7 +237,10 @@ def main():
         "max_sweeps_last_step": {"pair": sweeps[0], "momentum": sweeps[1]},
         "final": {"lb_per_site": lb, "energy_per_site": e, "feas": feas},
     }
+    if args.warm:
+        out["warm_start"] = warm_start_leg(args)
     if args.cpu_seconds > 0:
+        log(f"cpu baseline: the oracle for {args.cpu_seconds} s")
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
     print(json.dumps(out), flush=True)
 

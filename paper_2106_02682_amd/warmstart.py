@@ -179,27 +179,30 @@ def compare(draws, net, near, iters, ref_iters, every=20, tol=1e-6, log=None):
     return {
         "lb_ref": lb_ref, "cold": cold, "warm": warm, "predict_seconds": t_pred,
         "first_gap_cold": c0, "first_gap_warm": w0,
-        "cold_traj": (c_its, c_lbs), "warm_traj": (w_its, w_lbs),
+        "cold_traj": (c_its, c_lbs, c_secs), "warm_traj": (w_its, w_lbs, w_secs),
     }
 
 
-def summarise(res, iters):
-    """Medians over instances; a run that never reached the gap counts as `iters` (censored)."""
+def gap_report(res, tol, horizon):
+    """Counts and medians of (iterations, seconds) to the gap `tol` within `horizon`
+    iterations for the cold and warm runs of `compare`; None where the median run never
+    reached it (censored)."""
+    c_its, c_lbs, c_secs = res["cold_traj"]
+    w_its, w_lbs, w_secs = res["warm_traj"]
+    kc, kw = c_its <= horizon, w_its <= horizon
+    cold = first_converged(c_its[kc], c_lbs[kc], c_secs[kc], res["lb_ref"], tol)
+    warm = first_converged(w_its[kw], w_lbs[kw], w_secs[kw], res["lb_ref"], tol)
+
     def med(pairs, k):
-        vals = [p[k] if p[k] is not None else math.inf for p in pairs]
-        return float(np.median(vals))
+        v = float(np.median([p[k] if p[k] is not None else math.inf for p in pairs]))
+        return v if math.isfinite(v) else None
 
-    n = len(res["cold"])
     return {
-        "instances": n,
-        "cold_reached": sum(p[0] is not None for p in res["cold"]),
-        "warm_reached": sum(p[0] is not None for p in res["warm"]),
-        "median_iters_cold": med(res["cold"], 0),
-        "median_iters_warm": med(res["warm"], 0),
-        "median_seconds_cold": med(res["cold"], 1),
-        "median_seconds_warm": med(res["warm"], 1),
-        "horizon_iters": iters,
-        "predict_seconds": res["predict_seconds"],
-        "median_first_gap_cold": float(np.median(res["first_gap_cold"])),
-        "median_first_gap_warm": float(np.median(res["first_gap_warm"])),
+        "tol": tol, "horizon_iters": horizon,
+        "cold_reached": sum(p[0] is not None for p in cold), "warm_reached": sum(p[0] is not None for p in warm),
+        "median_iters_cold": med(cold, 0), "median_iters_warm": med(warm, 0),
+        "median_seconds_cold": med(cold, 1), "median_seconds_warm": med(warm, 1),
+        "iters_cold": [p[0] for p in cold], "iters_warm": [p[0] for p in warm],
     }
+
+
