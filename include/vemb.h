@@ -92,7 +92,11 @@ typedef struct {
   int32_t warm_refresh; /* eigensolves start from the previous iteration's eigenvectors; every
                            warm_refresh-th iteration (t % warm_refresh == 0) starts cold.
                            0 = default 64; negative = always cold. */
-  int32_t tpb;          /* threads per workgroup of the LDS eigensolver: 256, 512 or 1024;
+  int32_t tpb;          /* LDS eigensolver variant: 256, 512 or 1024 threads per workgroup
+                           (columns round-trip through LDS every round); or, for 64 x 64
+                           matrices, columns held in registers: 64 = 8-column blocks on 4
+                           wavefronts, 128 = 4-column blocks on 8 wavefronts (blocks move
+                           through LDS once per block round); other sizes then use 256.
                            0 = chosen by the autotuner (vemb_tuned_threads). */
 } vemb_options;
 
@@ -197,7 +201,8 @@ typedef struct {
 int vemb_set_profiling(vemb_problem* p, int enable);
 int vemb_get_profile(vemb_problem* p, vemb_profile* out);
 
-/* Autotuner of the LDS eigensolver's threads per workgroup (256 / 512 / 1024) for
+/* Autotuner of the LDS eigensolver variant (256 / 512 / 1024 threads, and the
+ * register-resident 64 / 128 for n = 64) for
  * batches of `batch` n x n matrices: times the candidates on seeded synthetic
  * matrices with HIP events on hip_stream and returns the fastest (>0), or a
  * negative status.  Results are cached per (device, n, real/complex, precision,
@@ -222,10 +227,11 @@ const char* vemb_last_error(void);
 int vemb_psd_project_batched(const double* in, double* out, int n, int batch, int is_complex, int precision,
                              void* hip_stream);
 
-/* As vemb_psd_project_batched, with an explicit sweep cap (0 = default 40) and
- * an optional DEVICE array sweeps[batch] receiving the sweeps each matrix used. */
+/* As vemb_psd_project_batched, with an explicit sweep cap (0 = default 40), an
+ * optional DEVICE array sweeps[batch] receiving the sweeps each matrix used, and
+ * the LDS solver variant tpb (as vemb_options.tpb; 0 = autotuned). */
 int vemb_psd_project_batched_ex(const double* in, double* out, int n, int batch, int is_complex, int precision,
-                                int max_sweeps, int* sweeps, void* hip_stream);
+                                int max_sweeps, int* sweeps, int tpb, void* hip_stream);
 
 /* Eigenvalues of a batch of symmetric / Hermitian matrices (device pointers;
  * w receives batch*n doubles in ascending order), by the same Jacobi solver. */

@@ -205,7 +205,7 @@ int vemb::tuned_tpb(int n, bool cplx, int precision, int count, hipStream_t st) 
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return 256;
   char key[256];
-  std::snprintf(key, sizeof(key), "%s:cu%d:n%d:%s:p%d:b%d", prop.gcnArchName, prop.multiProcessorCount, n,
+  std::snprintf(key, sizeof(key), "v2:%s:cu%d:n%d:%s:p%d:b%d", prop.gcnArchName, prop.multiProcessorCount, n,
                 cplx ? "c" : "r", precision, bucket);
   std::lock_guard<std::mutex> lock(g_tune_mu);
   tune_load();
@@ -222,7 +222,9 @@ int vemb::tuned_tpb(int n, bool cplx, int precision, int count, hipStream_t st) 
     hipEventCreate(&e0);
     hipEventCreate(&e1);
     float best_ms = 1e30f;
-    for (int tpb : {256, 512, 1024}) {
+    std::vector<int> cand = {256, 512, 1024};
+    if (n == 64) cand.insert(cand.begin(), {kTpbRegister8, kTpbRegister4});
+    for (int tpb : cand) {
       float t_min = 1e30f;
       bool ok = true;
       for (int rep = 0; rep < 3 && ok; ++rep) {
@@ -392,7 +394,7 @@ int vemb_create_problem(const vemb_hamiltonian* H, const vemb_lattice* lat, cons
   a.wk = p->wk;
   a.ops = p->ops;
   if ((rc = upload_initial_state(p))) return cleanup(rc);
-  if (o.tpb == 256 || o.tpb == 512 || o.tpb == 1024) {
+  if (o.tpb == kTpbRegister8 || o.tpb == kTpbRegister4 || o.tpb == 256 || o.tpb == 512 || o.tpb == 1024) {
     p->tpb_pair = p->tpb_mom = o.tpb;
   } else {
     p->tpb_pair = tuned_tpb(n, false, o.precision, P, s);
@@ -688,7 +690,7 @@ void vemb_destroy(vemb_problem* p) {
 
 int vemb_psd_project_batched(const double* in, double* out, int n, int batch, int is_complex, int precision,
                              void* hip_stream) {
-  return vemb_psd_project_batched_ex(in, out, n, batch, is_complex, precision, 0, nullptr, hip_stream);
+  return vemb_psd_project_batched_ex(in, out, n, batch, is_complex, precision, 0, nullptr, 0, hip_stream);
 }
 
 namespace {
@@ -707,7 +709,7 @@ struct Scratch {
 }  // namespace
 
 int vemb_psd_project_batched_ex(const double* in, double* out, int n, int batch, int is_complex, int precision,
-                                int max_sweeps, int* sweeps, void* hip_stream) {
+                                int max_sweeps, int* sweeps, int tpb, void* hip_stream) {
   if (!in || !out || n <= 0 || batch < 0) return fail(VEMB_E_INVALID, "bad arguments to vemb_psd_project_batched_ex");
   if (precision < VEMB_FP64 || precision > VEMB_FP32) return fail(VEMB_E_INVALID, "unknown precision");
   if (n > 256) return fail(VEMB_E_UNSUPPORTED, "matrices above 256 x 256 are not supported");
@@ -719,8 +721,8 @@ int vemb_psd_project_batched_ex(const double* in, double* out, int n, int batch,
   Scratch sc;
   if (need_v && hipMalloc(&sc.v, bytes) != hipSuccess) return fail(VEMB_E_NOMEM, "eigenvector scratch");
   if (lds) {
-    const int tpb = tuned_tpb(n, is_complex != 0, precision, batch, st);
-    VEMB_TRY(hip_rc(launch_psd_batched(in, out, n, batch, is_complex != 0, precision, ms, sweeps, (double*)sc.v, tpb,
+    const int t = tpb > 0 ? tpb : tuned_tpb(n, is_complex != 0, precision, batch, st);
+    VEMB_TRY(hip_rc(launch_psd_batched(in, out, n, batch, is_complex != 0, precision, ms, sweeps, (double*)sc.v, t,
                                        st),
                     "batched projection"));
     return sc.v ? hip_rc(hipStreamSynchronize(st), "batched projection sync") : VEMB_OK;

@@ -10,6 +10,11 @@
 
 namespace vemb {
 
+// Threads-per-workgroup codes naming the register-resident n = 64 Jacobi kernels
+// (jacobi_rr.h): 8-column blocks on 4 wavefronts, 4-column blocks on 8.
+constexpr int kTpbRegister8 = 64;
+constexpr int kTpbRegister4 = 128;
+
 // Thread-local last-error message (set on every failing ABI call).
 void set_error(const std::string& msg);
 

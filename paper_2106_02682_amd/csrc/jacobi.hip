@@ -23,6 +23,7 @@
 // columns of negligible norm (rounding noise left by an exactly singular B) are
 // not rotated, see below.
 #include "jacobi_common.h"
+#include "jacobi_rr.h"
 
 namespace vemb {
 namespace {
@@ -31,9 +32,10 @@ namespace {
 // Core kernel.  S: compute scalar (double, float, cplx<double>, cplx<float>);
 // NMAX: capacity (n <= NMAX, NMAX even); Policy: load / store of one matrix.
 // ---------------------------------------------------------------------------
-template <typename S, int NMAX, int MODE, bool WARM, int NT, typename Policy>
+template <typename S, int NMAX, int MODE, bool WARM, int NT, typename Policy, bool REG = false>
 __global__ void __launch_bounds__(NT) jacobi_kernel(Policy pol, int n, int max_sweeps, void* vstore_raw,
                                                           int cold) {
+  static_assert(!REG || (NMAX == 64 && (NT == 256 || NT == 512)), "register-resident sweeps: n = 64, 4 or 8 waves");
   using R = typename scalar_traits<S>::real;
   using D = typename wide<S>::type;  // FP64 storage type of V
   constexpr int LD = NMAX + 1;
@@ -49,6 +51,7 @@ __global__ void __launch_bounds__(NT) jacobi_kernel(Policy pol, int n, int max_s
   __shared__ int active[NMAX];
   __shared__ int nact_s;
   __shared__ int rotated;
+  __shared__ int rr_flags[8];
 
   const int mat = blockIdx.x;
   const int tid = threadIdx.x;
@@ -67,29 +70,37 @@ __global__ void __launch_bounds__(NT) jacobi_kernel(Policy pol, int n, int max_s
       }
       __syncthreads();
       S outv[NOUT];
-      int c = 0;
-      for (int idx = tid; idx < nn; idx += NT, ++c) {
+      #pragma unroll
+      for (int c = 0; c < NOUT; ++c) {  // compile-time c keeps outv in registers
+        const int idx = tid + c * NT;
+        if (idx >= nn) break;
         const int j = idx / n, i = idx - (idx / n) * n;
         S acc = s_zero<S>();
         for (int k = 0; k < n; ++k) acc = acc + conj_mul(V[i * LD + k], V[j * LD + k]);
         outv[c] = acc;  // G(i, j)
       }
-      c = 0;
-      for (int idx = tid; idx < nn; idx += NT, ++c) {
+      #pragma unroll
+      for (int c = 0; c < NOUT; ++c) {  // compile-time c keeps outv in registers
+        const int idx = tid + c * NT;
+        if (idx >= nn) break;
         const int j = idx / n, i = idx - (idx / n) * n;
         W[j * LD + i] = outv[c];
       }
       __syncthreads();
-      c = 0;
-      for (int idx = tid; idx < nn; idx += NT, ++c) {
+      #pragma unroll
+      for (int c = 0; c < NOUT; ++c) {  // compile-time c keeps outv in registers
+        const int idx = tid + c * NT;
+        if (idx >= nn) break;
         const int j = idx / n, i = idx - (idx / n) * n;
         S acc = s_zero<S>();
         for (int k = 0; k < n; ++k) acc = acc + V[k * LD + i] * W[j * LD + k];
         outv[c] = scale_by(R(1.5), V[j * LD + i]) - scale_by(R(0.5), acc);
       }
       __syncthreads();
-      c = 0;
-      for (int idx = tid; idx < nn; idx += NT, ++c) {
+      #pragma unroll
+      for (int c = 0; c < NOUT; ++c) {  // compile-time c keeps outv in registers
+        const int idx = tid + c * NT;
+        if (idx >= nn) break;
         const int j = idx / n, i = idx - (idx / n) * n;
         V[j * LD + i] = outv[c];
       }
@@ -155,16 +166,20 @@ __global__ void __launch_bounds__(NT) jacobi_kernel(Policy pol, int n, int max_s
       }
       __syncthreads();
       S outv[NOUT];
-      int c = 0;
-      for (int idx = tid; idx < nn; idx += NT, ++c) {
+      #pragma unroll
+      for (int c = 0; c < NOUT; ++c) {  // compile-time c keeps outv in registers
+        const int idx = tid + c * NT;
+        if (idx >= nn) break;
         const int j = idx / n, i = idx - (idx / n) * n;
         S acc = s_zero<S>();
         for (int k = 0; k < n; ++k) acc = acc + W[k * LD + i] * V[j * LD + k];
         outv[c] = acc;
       }
       __syncthreads();
-      c = 0;
-      for (int idx = tid; idx < nn; idx += NT, ++c) {
+      #pragma unroll
+      for (int c = 0; c < NOUT; ++c) {  // compile-time c keeps outv in registers
+        const int idx = tid + c * NT;
+        if (idx >= nn) break;
         const int j = idx / n, i = idx - (idx / n) * n;
         W[j * LD + i] = outv[c];
       }
@@ -188,77 +203,81 @@ __global__ void __launch_bounds__(NT) jacobi_kernel(Policy pol, int n, int max_s
   }
 
   // 3. sweeps
-  const int np = (n + 1) & ~1;
-  const int npair = np / 2;
   const R tol = R(n > 16 ? n : 16) * eps_of<R>::v;
-  const int g = tid / G;   // pair slot
-  const int l = tid % G;   // lane within the group
   int sweep = 0;
-  for (; sweep < max_sweeps; ++sweep) {
-    if (tid == 0) rotated = 0;
-    __syncthreads();
-    for (int round = 0; round < np - 1; ++round) {
-      int p = 0, q = 0;
-      bool live = g < npair;
-      if (live) {
-        rr_pair(round, g, np, p, q);
-        live = p < n && q < n;
-      }
-      S a[RPL], b[RPL];
-      R alpha = R(0), beta = R(0);
-      S gam = s_zero<S>();
-#pragma unroll
-      for (int r = 0; r < RPL; ++r) {
-        const int i = l + r * G;
-        if (live && i < n) {
-          a[r] = W[p * LD + i];
-          b[r] = W[q * LD + i];
-        } else {
-          a[r] = s_zero<S>();
-          b[r] = s_zero<S>();
+  if constexpr (REG) {
+    sweep = rr_sweeps<S, WARM, (NT == 256 ? 8 : 4)>(W, V, LD, max_sweeps, tol, floor2, rr_flags);
+  } else {
+    const int np = (n + 1) & ~1;
+    const int npair = np / 2;
+    const int g = tid / G;   // pair slot
+    const int l = tid % G;   // lane within the group
+    for (; sweep < max_sweeps; ++sweep) {
+      if (tid == 0) rotated = 0;
+      __syncthreads();
+      for (int round = 0; round < np - 1; ++round) {
+        int p = 0, q = 0;
+        bool live = g < npair;
+        if (live) {
+          rr_pair(round, g, np, p, q);
+          live = p < n && q < n;
         }
-        alpha += abs2(a[r]);
-        beta += abs2(b[r]);
-        gam = gam + conj_mul(a[r], b[r]);
-      }
-#pragma unroll
-      for (int off = G / 2; off > 0; off >>= 1) {
-        alpha += shfl_x(alpha, off);
-        beta += shfl_x(beta, off);
-        gam = gam + shfl_x(gam, off);
-      }
-      const R ag = modulus(gam);
-      const R small = alpha < beta ? alpha : beta;
-      if (live && small > floor2 && ag > tol * dev_sqrt(alpha * beta) && ag > R(0)) {
-        const R zeta = (beta - alpha) / (R(2) * ag);
-        const R az = dev_abs(zeta);
-        R t = R(1) / (az + dev_sqrt(R(1) + zeta * zeta));
-        if (zeta < R(0)) t = -t;
-        const R c = R(1) / dev_sqrt(R(1) + t * t);
-        const R s = c * t;
-        const S ph = conj_phase(gam, ag);  // conj(e)
-#pragma unroll
+        S a[RPL], b[RPL];
+        R alpha = R(0), beta = R(0);
+        S gam = s_zero<S>();
+  #pragma unroll
         for (int r = 0; r < RPL; ++r) {
           const int i = l + r * G;
-          if (i < n) {
-            const S bq = mul_phase(ph, b[r]);
-            W[p * LD + i] = scale_by(c, a[r]) - scale_by(s, bq);
-            W[q * LD + i] = scale_by(s, a[r]) + scale_by(c, bq);
-            if constexpr (WARM) {
-              const S va = V[p * LD + i];
-              const S vb = mul_phase(ph, V[q * LD + i]);
-              V[p * LD + i] = scale_by(c, va) - scale_by(s, vb);
-              V[q * LD + i] = scale_by(s, va) + scale_by(c, vb);
+          if (live && i < n) {
+            a[r] = W[p * LD + i];
+            b[r] = W[q * LD + i];
+          } else {
+            a[r] = s_zero<S>();
+            b[r] = s_zero<S>();
+          }
+          alpha += abs2(a[r]);
+          beta += abs2(b[r]);
+          gam = gam + conj_mul(a[r], b[r]);
+        }
+  #pragma unroll
+        for (int off = G / 2; off > 0; off >>= 1) {
+          alpha += shfl_x(alpha, off);
+          beta += shfl_x(beta, off);
+          gam = gam + shfl_x(gam, off);
+        }
+        const R ag = modulus(gam);
+        const R small = alpha < beta ? alpha : beta;
+        if (live && small > floor2 && ag > tol * dev_sqrt(alpha * beta) && ag > R(0)) {
+          const R zeta = (beta - alpha) / (R(2) * ag);
+          const R az = dev_abs(zeta);
+          R t = R(1) / (az + dev_sqrt(R(1) + zeta * zeta));
+          if (zeta < R(0)) t = -t;
+          const R c = R(1) / dev_sqrt(R(1) + t * t);
+          const R s = c * t;
+          const S ph = conj_phase(gam, ag);  // conj(e)
+  #pragma unroll
+          for (int r = 0; r < RPL; ++r) {
+            const int i = l + r * G;
+            if (i < n) {
+              const S bq = mul_phase(ph, b[r]);
+              W[p * LD + i] = scale_by(c, a[r]) - scale_by(s, bq);
+              W[q * LD + i] = scale_by(s, a[r]) + scale_by(c, bq);
+              if constexpr (WARM) {
+                const S va = V[p * LD + i];
+                const S vb = mul_phase(ph, V[q * LD + i]);
+                V[p * LD + i] = scale_by(c, va) - scale_by(s, vb);
+                V[q * LD + i] = scale_by(s, va) + scale_by(c, vb);
+              }
             }
           }
+          if (l == 0) rotated = 1;
         }
-        if (l == 0) rotated = 1;
+        __syncthreads();
       }
+      const int any = rotated;
       __syncthreads();
+      if (!any) break;
     }
-    const int any = rotated;
-    __syncthreads();
-    if (!any) break;
   }
   if (tid == 0) pol.record_sweeps(mat, sweep);
   if constexpr (WARM) {
@@ -329,13 +348,13 @@ __global__ void __launch_bounds__(NT) jacobi_kernel(Policy pol, int n, int max_s
 // tpb: threads per workgroup (256, 512 or 1024; others fall back to 256).  More
 // threads give each column pair more lanes (fewer rows per lane) and put up to
 // four wavefronts on each SIMD to hide the latency of a round.
-template <typename S, int MODE, int NM, int NT, typename Policy>
+template <typename S, int MODE, int NM, int NT, typename Policy, bool REG = false>
 hipError_t launch_one(const Policy& pol, int n, int count, int max_sweeps, hipStream_t st, void* vstore, int cold) {
   if (vstore)
-    hipLaunchKernelGGL((jacobi_kernel<S, NM, MODE, true, NT, Policy>), dim3(count), dim3(NT), 0, st, pol, n,
+    hipLaunchKernelGGL((jacobi_kernel<S, NM, MODE, true, NT, Policy, REG>), dim3(count), dim3(NT), 0, st, pol, n,
                        max_sweeps, vstore, cold);
   else
-    hipLaunchKernelGGL((jacobi_kernel<S, NM, MODE, false, NT, Policy>), dim3(count), dim3(NT), 0, st, pol, n,
+    hipLaunchKernelGGL((jacobi_kernel<S, NM, MODE, false, NT, Policy, REG>), dim3(count), dim3(NT), 0, st, pol, n,
                        max_sweeps, nullptr, 1);
   return hipGetLastError();
 }
@@ -343,6 +362,12 @@ hipError_t launch_one(const Policy& pol, int n, int count, int max_sweeps, hipSt
 template <typename S, int MODE, int NM, typename Policy>
 hipError_t launch_tpb(const Policy& pol, int n, int count, int max_sweeps, hipStream_t st, void* vstore, int cold,
                       int tpb) {
+  if constexpr (NM == 64) {  // register-resident kernels (n = 64 exactly)
+    if (tpb == kTpbRegister8 && n == 64)
+      return launch_one<S, MODE, 64, 256, Policy, true>(pol, n, count, max_sweeps, st, vstore, cold);
+    if (tpb == kTpbRegister4 && n == 64)
+      return launch_one<S, MODE, 64, 512, Policy, true>(pol, n, count, max_sweeps, st, vstore, cold);
+  }
   if constexpr (NM >= 16 && NM <= 64) {
     if (tpb == 1024) return launch_one<S, MODE, NM, 1024>(pol, n, count, max_sweeps, st, vstore, cold);
     if (tpb == 512) return launch_one<S, MODE, NM, 512>(pol, n, count, max_sweeps, st, vstore, cold);

@@ -123,7 +123,7 @@ def lib():
     L.vemb_get_profile.argtypes = [vp, ctypes.POINTER(vemb_profile)]
     L.vemb_last_sweeps.argtypes = [vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
     L.vemb_psd_project_batched_ex.argtypes = [vp, vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
-                                              ctypes.c_int, vp, vp]
+                                              ctypes.c_int, vp, ctypes.c_int, vp]
     L.vemb_batch_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int, ctypes.c_int, ctypes.POINTER(vp)]
     L.vemb_batch_step.argtypes = [vp, ctypes.c_int]
     L.vemb_batch_dual_bounds.argtypes = [vp, _DP, ctypes.POINTER(ctypes.c_int)]
@@ -299,14 +299,17 @@ def psd_project_batched(inp, out, is_complex=False, precision="fp64", stream=Non
                                           batch, int(is_complex), PRECISION[precision], st))
 
 
-def psd_project_batched_ex(inp, out, is_complex=False, precision="fp64", max_sweeps=0, sweeps=None, stream=None):
-    """As psd_project_batched; ``sweeps`` is an optional int32 device tensor of length batch."""
+def psd_project_batched_ex(inp, out, is_complex=False, precision="fp64", max_sweeps=0, sweeps=None, tpb=0,
+                           stream=None):
+    """As psd_project_batched; ``sweeps`` is an optional int32 device tensor of length batch, ``tpb`` the
+    LDS solver variant (0 = autotuned; 64 / 128 = register-resident for n = 64)."""
     n = inp.shape[-2]
     batch = inp.numel() // (n * n * (2 if is_complex else 1))
     st = stream if stream is not None else current_stream()
     sp = ctypes.c_void_p(sweeps.data_ptr()) if sweeps is not None else ctypes.c_void_p(None)
     _check(lib().vemb_psd_project_batched_ex(ctypes.c_void_p(inp.data_ptr()), ctypes.c_void_p(out.data_ptr()), n,
-                                             batch, int(is_complex), PRECISION[precision], int(max_sweeps), sp, st))
+                                             batch, int(is_complex), PRECISION[precision], int(max_sweeps), sp,
+                                             int(tpb), st))
 
 
 def set_profiling(h, enable=True):
