@@ -183,12 +183,22 @@ __device__ void cluster_update_body(const StepArgs& A) {
   __shared__ double r0[kMaxM * kMaxM];
   __shared__ double red[kClusterBlock];
   __shared__ double z_s;
-  // rho'_0 = [sum_d (nu A_1 rho_d + Lambda1_d) - H'_0] / (nu (M-1))
-  for (int e = tid; e < mm; e += kClusterBlock) {
-    double acc = 0.0;
-    for (int d = 0; d < P; ++d) acc += A.nu * A.tr2[(size_t)d * mm + e] + A.Lam1[(size_t)d * mm + e];
-    const double h0p = A.H0[e] - c0_value(A, e / m, e % m);
-    r0[e] = (acc - h0p) / (A.nu * (A.M - 1));
+  // rho'_0 = [sum_d (nu A_1 rho_d + Lambda1_d) - H'_0] / (nu (M-1)); the sum over d
+  // is split over kSplit lanes of one wavefront per entry, then reduced by shuffles
+  {
+    constexpr int kSplit = 16;
+    for (int base = 0; base < mm; base += kClusterBlock / kSplit) {
+      const int e = base + tid / kSplit, part = tid % kSplit;
+      double acc = 0.0;
+      if (e < mm)
+        for (int d = part; d < P; d += kSplit) acc += A.nu * A.tr2[(size_t)d * mm + e] + A.Lam1[(size_t)d * mm + e];
+#pragma unroll
+      for (int off = kSplit / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+      if (e < mm && part == 0) {
+        const double h0p = A.H0[e] - c0_value(A, e / m, e % m);
+        r0[e] = (acc - h0p) / (A.nu * (A.M - 1));
+      }
+    }
   }
   __syncthreads();
   if (tid == 0) {
@@ -253,9 +263,10 @@ __device__ void cluster_update_body(const StepArgs& A) {
 
 // ---------------------------------------------------------------------------
 // Step 7: Xh_k = sum_d tw[k][d] X'_d over the unique momenta (tw includes M^{-1/2}).
-// Thread per entry e of the n_op x n_op block, KC momenta per thread.
+// Thread per entry e of the n_op x n_op block, KC momenta per thread (few, so that
+// many workgroups keep the loads of X' in flight; X' is re-read from L2).
 // ---------------------------------------------------------------------------
-constexpr int KC = 8;
+constexpr int KC = 2;
 
 __device__ void dft_forward_body(const StepArgs& A, int bx, int by) {
   const int E = A.n_op * A.n_op;
@@ -266,6 +277,7 @@ __device__ void dft_forward_body(const StepArgs& A, int bx, int by) {
   double re[KC], im[KC];
 #pragma unroll
   for (int c = 0; c < KC; ++c) re[c] = im[c] = 0.0;
+#pragma unroll 8
   for (int d = 0; d < A.M; ++d) {
     const double v = A.Xp[(size_t)d * E + e];
 #pragma unroll
@@ -285,7 +297,7 @@ __device__ void dft_forward_body(const StepArgs& A, int bx, int by) {
 }
 
 // Step 9: X_d = sum_k w_k Re(conj(tw[k][d]) Y_k), thread per entry, DC offsets per thread.
-constexpr int DC = 8;
+constexpr int DC = 4;
 
 __device__ void dft_inverse_body(const StepArgs& A, int bx, int by) {
   const int E = A.n_op * A.n_op;
@@ -296,6 +308,7 @@ __device__ void dft_inverse_body(const StepArgs& A, int bx, int by) {
   double acc[DC];
 #pragma unroll
   for (int c = 0; c < DC; ++c) acc[c] = 0.0;
+#pragma unroll 8
   for (int k = 0; k < A.Ku; ++k) {
     const double* y = A.Xh + 2 * ((size_t)k * E + e);
     const double yr = y[0], yi = y[1];
