@@ -24,6 +24,7 @@
 // not rotated, see below.
 #include "jacobi_common.h"
 #include "jacobi_rr.h"
+#include "mfma_tile.h"
 
 namespace vemb {
 namespace {
@@ -57,6 +58,12 @@ __global__ void __launch_bounds__(NT) jacobi_kernel(Policy pol, int n, int max_s
   const int tid = threadIdx.x;
   const int nn = n * n;
   constexpr int NOUT = (NMAX * NMAX + NT - 1) / NT;
+  // dense products on matrix cores: 16 x 16 tiles, n a multiple of 16
+  constexpr int NWAVE = NT / 64;
+  constexpr int TMAX = NMAX >= 16 ? (NMAX / 16) * (NMAX / 16) : 0;
+  constexpr int TPW = TMAX > 0 ? (TMAX + NWAVE - 1) / NWAVE : 0;
+  const bool use_mfma = TMAX > 0 && n % 16 == 0;
+  const int wv = tid >> 6, ln = tid & 63;
 
   // 0. cold == 2: the kept V comes from a lower-precision solve; restore its
   // orthonormality first with one Newton-Schulz step V <- V (3I - V^H V)/2
@@ -165,23 +172,48 @@ __global__ void __launch_bounds__(NT) jacobi_kernel(Policy pol, int n, int max_s
         }
       }
       __syncthreads();
-      S outv[NOUT];
-      #pragma unroll
-      for (int c = 0; c < NOUT; ++c) {  // compile-time c keeps outv in registers
-        const int idx = tid + c * NT;
-        if (idx >= nn) break;
-        const int j = idx / n, i = idx - (idx / n) * n;
-        S acc = s_zero<S>();
-        for (int k = 0; k < n; ++k) acc = acc + W[k * LD + i] * V[j * LD + k];
-        outv[c] = acc;
+      if constexpr (TPW > 0) {
+        if (use_mfma) {  // W <- B V on matrix cores
+          const int nt = n / 16, T = nt * nt;
+          TileAcc<S> acc[TPW];
+#pragma unroll
+          for (int q = 0; q < TPW; ++q) {
+            const int t = wv + q * NWAVE;
+            if (t < T)
+              acc[q] = tile_gemm<S>([&](int i, int k) { return W[k * LD + i]; },
+                                    [&](int k, int j) { return V[j * LD + k]; }, n, (t / nt) * 16, (t % nt) * 16,
+                                    ln);
+          }
+          __syncthreads();
+#pragma unroll
+          for (int q = 0; q < TPW; ++q) {
+            const int t = wv + q * NWAVE;
+            if (t < T)
+#pragma unroll
+              for (int r = 0; r < 4; ++r)
+                W[((t % nt) * 16 + (ln & 15)) * LD + (t / nt) * 16 + mfma_row<R>(ln, r)] = tile_value(acc[q], r);
+          }
+        }
       }
-      __syncthreads();
-      #pragma unroll
-      for (int c = 0; c < NOUT; ++c) {  // compile-time c keeps outv in registers
-        const int idx = tid + c * NT;
-        if (idx >= nn) break;
-        const int j = idx / n, i = idx - (idx / n) * n;
-        W[j * LD + i] = outv[c];
+      if (!use_mfma) {
+        S outv[NOUT];
+        #pragma unroll
+        for (int c = 0; c < NOUT; ++c) {  // compile-time c keeps outv in registers
+          const int idx = tid + c * NT;
+          if (idx >= nn) break;
+          const int j = idx / n, i = idx - (idx / n) * n;
+          S acc = s_zero<S>();
+          for (int k = 0; k < n; ++k) acc = acc + W[k * LD + i] * V[j * LD + k];
+          outv[c] = acc;
+        }
+        __syncthreads();
+        #pragma unroll
+        for (int c = 0; c < NOUT; ++c) {  // compile-time c keeps outv in registers
+          const int idx = tid + c * NT;
+          if (idx >= nn) break;
+          const int j = idx / n, i = idx - (idx / n) * n;
+          W[j * LD + i] = outv[c];
+        }
       }
     }
     __syncthreads();
@@ -318,24 +350,51 @@ __global__ void __launch_bounds__(NT) jacobi_kernel(Policy pol, int n, int max_s
       nact_s = k;
     }
     __syncthreads();
-    const int nact = nact_s;
-    for (int idx = tid; idx < nact * n; idx += NT) {
-      const int jj = idx / n, i = idx - (idx / n) * n;
-      const int j = active[jj];
-      const R sg = colf[j];
-      const R f = dev_sqrt((sg - shift)) / sg;
-      W[j * LD + i] = scale_by(f, W[j * LD + i]);
-    }
-    __syncthreads();
     double part = 0.0;
-    for (int idx = tid; idx < nn; idx += NT) {
-      const int i = idx / n, k = idx - (idx / n) * n;
-      S acc = s_zero<S>();
-      for (int jj = 0; jj < nact; ++jj) {
-        const int j = active[jj];
-        acc = acc + conj_mul(W[j * LD + k], W[j * LD + i]);  // U(i,j) conj(U(k,j))
+    bool done = false;
+    if constexpr (TPW > 0) {
+      if (use_mfma) {  // U U^H on matrix cores over all n columns, inactive ones zeroed
+        for (int idx = tid; idx < nn; idx += NT) {
+          const int j = idx / n, i = idx - (idx / n) * n;
+          const R sg = colf[j];
+          W[j * LD + i] = sg > shift ? scale_by(dev_sqrt(sg - shift) / sg, W[j * LD + i]) : s_zero<S>();
+        }
+        __syncthreads();
+        const int nt = n / 16, T = nt * nt;
+#pragma unroll
+        for (int q = 0; q < TPW; ++q) {
+          const int t = wv + q * NWAVE;
+          if (t < T) {
+            const int i0 = (t / nt) * 16, k0 = (t % nt) * 16;
+            const TileAcc<S> acc = tile_gemm<S>([&](int i, int j) { return W[j * LD + i]; },
+                                                [&](int j, int k) { return conjugate(W[j * LD + k]); }, n, i0, k0,
+                                                ln);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) part += pol.store(mat, i0 + mfma_row<R>(ln, r), k0 + (ln & 15), tile_value(acc, r));
+          }
+        }
+        done = true;
       }
-      part += pol.store(mat, i, k, acc);
+    }
+    if (!done) {
+      const int nact = nact_s;
+      for (int idx = tid; idx < nact * n; idx += NT) {
+        const int jj = idx / n, i = idx - (idx / n) * n;
+        const int j = active[jj];
+        const R sg = colf[j];
+        const R f = dev_sqrt((sg - shift)) / sg;
+        W[j * LD + i] = scale_by(f, W[j * LD + i]);
+      }
+      __syncthreads();
+      for (int idx = tid; idx < nn; idx += NT) {
+        const int i = idx / n, k = idx - (idx / n) * n;
+        S acc = s_zero<S>();
+        for (int jj = 0; jj < nact; ++jj) {
+          const int j = active[jj];
+          acc = acc + conj_mul(W[j * LD + k], W[j * LD + i]);  // U(i,j) conj(U(k,j))
+        }
+        part += pol.store(mat, i, k, acc);
+      }
     }
     const double tot = block_sum(part, red_d);
     if (tid == 0) pol.finish(mat, tot);
