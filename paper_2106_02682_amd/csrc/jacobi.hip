@@ -39,7 +39,7 @@ __global__ void __launch_bounds__(NT) jacobi_kernel(Policy pol, int n, int max_s
   static_assert(!REG || (NMAX == 64 && (NT == 256 || NT == 512)), "register-resident sweeps: n = 64, 4 or 8 waves");
   using R = typename scalar_traits<S>::real;
   using D = typename wide<S>::type;  // FP64 storage type of V
-  constexpr int LD = NMAX + 1;
+  constexpr int LD = NMAX + 1;  // padded column stride (wider padding measured no faster)
   constexpr int NPAIR = NMAX / 2;
   constexpr int G0 = NT / NPAIR;
   constexpr int G = G0 > 64 ? 64 : G0;  // lanes per pair, within one wavefront
@@ -49,6 +49,7 @@ __global__ void __launch_bounds__(NT) jacobi_kernel(Policy pol, int n, int max_s
   __shared__ R red[NT];
   __shared__ double red_d[NT];
   __shared__ R colf[NMAX];
+  __shared__ R cn[NMAX];  // squared column norms carried through a sweep
   __shared__ int active[NMAX];
   __shared__ int nact_s;
   __shared__ int rotated;
@@ -245,7 +246,15 @@ __global__ void __launch_bounds__(NT) jacobi_kernel(Policy pol, int n, int max_s
     const int g = tid / G;   // pair slot
     const int l = tid % G;   // lane within the group
     for (; sweep < max_sweeps; ++sweep) {
+      // squared column norms, recomputed exactly once per sweep and carried through the
+      // rotations in between (|w_p'|^2 = |w_p|^2 - t|gamma|, |w_q'|^2 = |w_q|^2 + t|gamma|),
+      // so a round reduces only the inner products
       if (tid == 0) rotated = 0;
+      for (int j = tid; j < n; j += NT) {
+        R s2 = R(0);
+        for (int i = 0; i < n; ++i) s2 += abs2(W[j * LD + i]);
+        cn[j] = s2;
+      }
       __syncthreads();
       for (int round = 0; round < np - 1; ++round) {
         int p = 0, q = 0;
@@ -255,7 +264,6 @@ __global__ void __launch_bounds__(NT) jacobi_kernel(Policy pol, int n, int max_s
           live = p < n && q < n;
         }
         S a[RPL], b[RPL];
-        R alpha = R(0), beta = R(0);
         S gam = s_zero<S>();
   #pragma unroll
         for (int r = 0; r < RPL; ++r) {
@@ -267,16 +275,11 @@ __global__ void __launch_bounds__(NT) jacobi_kernel(Policy pol, int n, int max_s
             a[r] = s_zero<S>();
             b[r] = s_zero<S>();
           }
-          alpha += abs2(a[r]);
-          beta += abs2(b[r]);
           gam = gam + conj_mul(a[r], b[r]);
         }
   #pragma unroll
-        for (int off = G / 2; off > 0; off >>= 1) {
-          alpha += shfl_x(alpha, off);
-          beta += shfl_x(beta, off);
-          gam = gam + shfl_x(gam, off);
-        }
+        for (int off = G / 2; off > 0; off >>= 1) gam = gam + shfl_x(gam, off);
+        const R alpha = live ? cn[p] : R(0), beta = live ? cn[q] : R(0);
         const R ag = modulus(gam);
         const R small = alpha < beta ? alpha : beta;
         if (live && small > floor2 && ag > tol * dev_sqrt(alpha * beta) && ag > R(0)) {
@@ -287,6 +290,11 @@ __global__ void __launch_bounds__(NT) jacobi_kernel(Policy pol, int n, int max_s
           const R c = R(1) / dev_sqrt(R(1) + t * t);
           const R s = c * t;
           const S ph = conj_phase(gam, ag);  // conj(e)
+          if (l == 0) {
+            const R da = t * ag;
+            cn[p] = alpha - da > R(0) ? alpha - da : R(0);
+            cn[q] = beta + da;
+          }
   #pragma unroll
           for (int r = 0; r < RPL; ++r) {
             const int i = l + r * G;
