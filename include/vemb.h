@@ -136,6 +136,16 @@ int vemb_refine(vemb_problem* p, int iters);
  * Synchronises the stream.  VEMB_E_NUMERIC on non-finite results. */
 int vemb_dual_bound(vemb_problem* p, double* lb_per_site);
 
+/* vemb_dual_bound and vemb_primal_energy in one call with one synchronisation
+ * (lb required; e_per_site / feas_err may be NULL). */
+int vemb_diagnostics(vemb_problem* p, double* lb_per_site, double* e_per_site, double* feas_err);
+/* The same diagnostics without stopping the stream: _enqueue queues the bound
+ * kernels and copies of the current state's diagnostics into pinned host memory
+ * (later iterations queued after it do not change what it reports); _collect
+ * waits for the last enqueued set and returns it (VEMB_E_INVALID if none). */
+int vemb_diagnostics_enqueue(vemb_problem* p);
+int vemb_diagnostics_collect(vemb_problem* p, double* lb_per_site, double* e_per_site, double* feas_err);
+
 /* Primal energy per site [Tr H_0 rho_0 + 1/2 sum_d Tr H_0d rho_0d]/L of the
  * latest pair update and the feasibility error of eq. feasErr.  Synchronises. */
 int vemb_primal_energy(vemb_problem* p, double* e_per_site, double* feas_err);
@@ -199,12 +209,17 @@ typedef struct {
 } vemb_profile;
 
 int vemb_set_profiling(vemb_problem* p, int enable);
+/* As vemb_set_profiling with a bit mask of the kernels to time (bit vemb_kernel_id);
+ * 0 turns timing off.  Fewer events per iteration disturb the timed run less. */
+int vemb_set_profiling_mask(vemb_problem* p, uint32_t kernels);
 int vemb_get_profile(vemb_problem* p, vemb_profile* out);
 
 /* Autotuner of the LDS eigensolver variant (256 / 512 / 1024 threads, and the
  * register-resident 64 / 128 for n = 64) for
- * batches of `batch` n x n matrices: times the candidates on seeded synthetic
- * matrices with HIP events on hip_stream and returns the fastest (>0), or a
+ * batches of `batch` n x n matrices: times the candidates with HIP events on
+ * hip_stream on warm-started solves (a cold solve of seeded synthetic matrices,
+ * then the timed solve of the same matrices moved by 1e-3, started from the kept
+ * eigenvectors, as in the iteration) and returns the fastest (>0), or a
  * negative status.  Results are cached per (device, n, real/complex, precision,
  * batch rounded up to a power of two) in memory and in the text file
  * $VEMB_TUNE_CACHE (default $HOME/.cache/vemb_tune.txt; "none" = memory only).

@@ -88,13 +88,14 @@ template <typename F>
 int timed(vemb_problem* p, int id, const char* what, F&& launch, hipStream_t st = nullptr) {
   if (!st) st = p->stream;
   hipEvent_t a = nullptr, b = nullptr;
-  if (p->profiling) {
+  const bool on = p->profiling && ((p->prof_mask >> id) & 1u);
+  if (on) {
     a = take_event(p);
     b = take_event(p);
     if (a) hipEventRecord(a, st);
   }
   int rc = hip_rc(launch(), what);
-  if (p->profiling && a && b) {
+  if (on && a && b) {
     hipEventRecord(b, st);
     p->marks.push_back({id, a, b});
   }
@@ -205,7 +206,7 @@ int vemb::tuned_tpb(int n, bool cplx, int precision, int count, hipStream_t st) 
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return 256;
   char key[256];
-  std::snprintf(key, sizeof(key), "v2:%s:cu%d:n%d:%s:p%d:b%d", prop.gcnArchName, prop.multiProcessorCount, n,
+  std::snprintf(key, sizeof(key), "v3:%s:cu%d:n%d:%s:p%d:b%d", prop.gcnArchName, prop.multiProcessorCount, n,
                 cplx ? "c" : "r", precision, bucket);
   std::lock_guard<std::mutex> lock(g_tune_mu);
   tune_load();
@@ -213,11 +214,29 @@ int vemb::tuned_tpb(int n, bool cplx, int precision, int count, hipStream_t st) 
   if (it != g_tune.end()) return it->second;
   std::vector<double> h;
   synth_batch(h, n, bucket, cplx);
+  // the iteration's solves are warm-started from the previous eigenvectors: time a warm
+  // solve of a slightly moved batch (relative change 1e-3) after a cold solve of the first
+  std::vector<double> h2(h);
+  {
+    std::vector<double> pert;
+    synth_batch(pert, n, bucket, cplx);
+    for (size_t i = 0; i < h2.size(); ++i) h2[i] += 1e-3 * pert[(i * 7919) % pert.size()];
+    const int w = cplx ? 2 : 1;  // keep the moved batch symmetric / Hermitian
+    for (int b = 0; b < bucket; ++b)
+      for (int i = 0; i < n; ++i)
+        for (int j = 0; j < i; ++j)
+          for (int c = 0; c < w; ++c) {
+            const size_t lo = (((size_t)b * n + i) * n + j) * w + c, up = (((size_t)b * n + j) * n + i) * w + c;
+            h2[lo] = c == 0 ? h2[up] : -h2[up];
+          }
+  }
   const size_t bytes = h.size() * sizeof(double);
-  double *din = nullptr, *dout = nullptr, *dv = nullptr;
+  double *din = nullptr, *din2 = nullptr, *dout = nullptr, *dv = nullptr;
   int best = 256;
-  if (hipMalloc(&din, bytes) == hipSuccess && hipMalloc(&dout, bytes) == hipSuccess &&
-      hipMalloc(&dv, bytes) == hipSuccess && hipMemcpyAsync(din, h.data(), bytes, hipMemcpyHostToDevice, st) == hipSuccess) {
+  if (hipMalloc(&din, bytes) == hipSuccess && hipMalloc(&din2, bytes) == hipSuccess &&
+      hipMalloc(&dout, bytes) == hipSuccess && hipMalloc(&dv, bytes) == hipSuccess &&
+      hipMemcpyAsync(din, h.data(), bytes, hipMemcpyHostToDevice, st) == hipSuccess &&
+      hipMemcpyAsync(din2, h2.data(), bytes, hipMemcpyHostToDevice, st) == hipSuccess) {
     hipEvent_t e0, e1;
     hipEventCreate(&e0);
     hipEventCreate(&e1);
@@ -228,8 +247,10 @@ int vemb::tuned_tpb(int n, bool cplx, int precision, int count, hipStream_t st) 
       float t_min = 1e30f;
       bool ok = true;
       for (int rep = 0; rep < 3 && ok; ++rep) {
+        ok = launch_psd_batched(din, dout, n, bucket, cplx, precision, 40, nullptr, dv, tpb, st, 1) == hipSuccess;
         hipEventRecord(e0, st);
-        ok = launch_psd_batched(din, dout, n, bucket, cplx, precision, 40, nullptr, dv, tpb, st) == hipSuccess;
+        ok = ok && launch_psd_batched(din2, dout, n, bucket, cplx, precision, 40, nullptr, dv, tpb, st, 0) ==
+                       hipSuccess;
         hipEventRecord(e1, st);
         hipEventSynchronize(e1);
         float ms = 0.f;
@@ -246,6 +267,7 @@ int vemb::tuned_tpb(int n, bool cplx, int precision, int count, hipStream_t st) 
   }
   hipStreamSynchronize(st);
   if (din) hipFree(din);
+  if (din2) hipFree(din2);
   if (dout) hipFree(dout);
   if (dv) hipFree(dv);
   hipGetLastError();  // a failed candidate must not leak its error into the caller
@@ -368,6 +390,7 @@ int vemb_create_problem(const vemb_hamiltonian* H, const vemb_lattice* lat, cons
       (rc = dalloc(p, &a.tr1, (size_t)P * m * m)) || (rc = dalloc(p, &a.e_pair, (size_t)P)) ||
       (rc = dalloc(p, &a.feas, (size_t)P)) || (rc = dalloc(p, &a.scal, 4)) ||
       (rc = dalloc(p, &a.Kbuf, (size_t)P * n * n + (size_t)m * m)) || (rc = dalloc(p, &a.lmin, (size_t)P + 1)) ||
+      (n <= 128 && (rc = dalloc(p, &p->Kv, (size_t)P * n * n))) ||
       (rc = dalloc(p, &a.sweeps, (size_t)(2 * P + Ku + 1))) ||
       (rc = dalloc(p, &a.Vpair, (size_t)P * n * n)) || (rc = dalloc(p, &a.Vmom, (size_t)2 * Ku * k * k)) ||
       (n > 64 && ((rc = dalloc(p, (double**)&a.wscr_pair, (size_t)P * n * n)) ||
@@ -504,6 +527,7 @@ int vemb_warm_start(vemb_problem* p, int near, const float* vec) {
   VEMB_TRY(project_x(p));
   p->t = 0;
   p->v_valid = false;
+  p->k_valid = false;
   return VEMB_OK;
 }
 
@@ -537,8 +561,10 @@ int vemb_primal_energy(vemb_problem* p, double* e_per_site, double* feas_err) {
   return VEMB_OK;
 }
 
-int vemb_dual_bound(vemb_problem* p, double* lb) {
-  if (!p || !lb) return fail(VEMB_E_INVALID, "NULL argument");
+namespace {
+// Bound matrices and their smallest eigenvalues (enqueued); the pair solves start from the
+// eigenvectors of the previous bound evaluation.
+int enqueue_bound(vemb_problem* p) {
   const StepArgs& a = p->a;
   hipStream_t s = p->stream;
   const int P = p->P, n = a.n, m = a.m;
@@ -547,21 +573,115 @@ int vemb_dual_bound(vemb_problem* p, double* lb) {
     if (n > 128)
       return launch_eigvals_big(a.Kbuf, nullptr, a.lmin, n, P, false, p->opt.max_sweeps, a.sweeps + P + a.Ku,
                                 a.wscr_pair, a.tscr_pair, s);
-    return launch_lambda_min(a.Kbuf, a.lmin, n, P, p->opt.max_sweeps, a.sweeps + P + a.Ku, s);
+    const int cold = (!p->k_valid || p->k_uses % 16 == 0) ? 1 : 0;
+    return launch_lambda_min(a.Kbuf, a.lmin, n, P, p->opt.max_sweeps, a.sweeps + P + a.Ku, s, p->tpb_pair, p->Kv,
+                             cold);
   }));
-  VEMB_TRY(timed(p, VEMB_K_LMIN, "cluster lambda_min", [&] {
+  if (n <= 128 && p->Kv) {
+    p->k_valid = true;
+    ++p->k_uses;
+  }
+  return timed(p, VEMB_K_LMIN, "cluster lambda_min", [&] {
     return launch_lambda_min(a.Kbuf + (size_t)P * n * n, a.lmin + P, m, 1, p->opt.max_sweeps, nullptr, s);
-  }));
-  std::vector<double> lm(P + 1);
-  VEMB_TRY(hip_rc(hipMemcpyAsync(lm.data(), a.lmin, (P + 1) * 8, hipMemcpyDeviceToHost, s), "copy lambda_min"));
-  VEMB_TRY(hip_rc(hipStreamSynchronize(s), "dual bound sync"));
-  double v = lm[P];
+  });
+}
+
+double bound_from(const vemb_problem* p, const std::vector<double>& lm) {
+  const int P = p->P;
   double sum = 0.0;
   for (int d = 0; d < P; ++d) sum += lm[d];
-  v += 0.5 * sum;
-  *lb = v / p->g.L;
+  return (lm[P] + 0.5 * sum) / p->g.L;
+}
+}  // namespace
+
+int vemb_dual_bound(vemb_problem* p, double* lb) {
+  if (!p || !lb) return fail(VEMB_E_INVALID, "NULL argument");
+  VEMB_TRY(enqueue_bound(p));
+  std::vector<double> lm(p->P + 1);
+  VEMB_TRY(hip_rc(hipMemcpyAsync(lm.data(), p->a.lmin, (p->P + 1) * 8, hipMemcpyDeviceToHost, p->stream),
+                  "copy lambda_min"));
+  VEMB_TRY(hip_rc(hipStreamSynchronize(p->stream), "dual bound sync"));
+  VEMB_TRY(drain_marks(p));  // the stream is idle: recycle the timing events now
+  *lb = bound_from(p, lm);
   if (!std::isfinite(*lb)) return fail(VEMB_E_NUMERIC, "non-finite lower bound");
   return VEMB_OK;
+}
+
+int vemb_diagnostics(vemb_problem* p, double* lb, double* e_per_site, double* feas_err) {
+  if (!p || !lb) return fail(VEMB_E_INVALID, "NULL argument");
+  const int P = p->P;
+  hipStream_t s = p->stream;
+  std::vector<double> ep(P), fe(P), sc(4), lm(P + 1);
+  VEMB_TRY(hip_rc(hipMemcpyAsync(ep.data(), p->a.e_pair, P * 8, hipMemcpyDeviceToHost, s), "copy energies"));
+  VEMB_TRY(hip_rc(hipMemcpyAsync(fe.data(), p->a.feas, P * 8, hipMemcpyDeviceToHost, s), "copy feas"));
+  VEMB_TRY(hip_rc(hipMemcpyAsync(sc.data(), p->a.scal, 4 * 8, hipMemcpyDeviceToHost, s), "copy scalars"));
+  VEMB_TRY(enqueue_bound(p));
+  VEMB_TRY(hip_rc(hipMemcpyAsync(lm.data(), p->a.lmin, (P + 1) * 8, hipMemcpyDeviceToHost, s), "copy lambda_min"));
+  VEMB_TRY(hip_rc(hipStreamSynchronize(s), "diagnostics sync"));
+  VEMB_TRY(drain_marks(p));  // the stream is idle: recycle the timing events now
+  *lb = bound_from(p, lm);
+  double e = sc[0], f = sc[1];
+  for (int d = 0; d < P; ++d) {
+    e += 0.5 * ep[d];
+    f += fe[d];
+  }
+  if (e_per_site) *e_per_site = e / p->g.L;
+  if (feas_err) *feas_err = std::sqrt(f / (p->g.M - 1));
+  if (!std::isfinite(*lb) || !std::isfinite(e) || !std::isfinite(f))
+    return fail(VEMB_E_NUMERIC, "non-finite bound, energy or feasibility");
+  return VEMB_OK;
+}
+
+namespace {
+int diag_reduce(vemb_problem* p, const double* lm, const double* ep, const double* fe, const double* sc, double* lb,
+                double* e_per_site, double* feas_err) {
+  const int P = p->P;
+  double sum = 0.0, e = sc[0], f = sc[1];
+  for (int d = 0; d < P; ++d) {
+    sum += lm[d];
+    e += 0.5 * ep[d];
+    f += fe[d];
+  }
+  *lb = (lm[P] + 0.5 * sum) / p->g.L;
+  if (e_per_site) *e_per_site = e / p->g.L;
+  if (feas_err) *feas_err = std::sqrt(f / (p->g.M - 1));
+  if (!std::isfinite(*lb) || !std::isfinite(e) || !std::isfinite(f))
+    return fail(VEMB_E_NUMERIC, "non-finite bound, energy or feasibility");
+  return VEMB_OK;
+}
+}  // namespace
+
+int vemb_diagnostics_enqueue(vemb_problem* p) {
+  if (!p) return fail(VEMB_E_INVALID, "NULL problem");
+  const int P = p->P;
+  hipStream_t s = p->stream;
+  if (!p->diag_host) {
+    if (hipHostMalloc((void**)&p->diag_host, sizeof(double) * (3 * P + 5), hipHostMallocDefault) != hipSuccess) {
+      p->diag_host = nullptr;
+      return fail(VEMB_E_NOMEM, "pinned diagnostics buffer");
+    }
+    VEMB_TRY(hip_rc(hipEventCreateWithFlags(&p->diag_ev, hipEventDisableTiming), "diagnostics event"));
+  }
+  if (p->diag_pending) VEMB_TRY(hip_rc(hipEventSynchronize(p->diag_ev), "previous diagnostics"));
+  double* h = p->diag_host;
+  VEMB_TRY(hip_rc(hipMemcpyAsync(h + P + 1, p->a.e_pair, P * 8, hipMemcpyDeviceToHost, s), "copy energies"));
+  VEMB_TRY(hip_rc(hipMemcpyAsync(h + 2 * P + 1, p->a.feas, P * 8, hipMemcpyDeviceToHost, s), "copy feas"));
+  VEMB_TRY(hip_rc(hipMemcpyAsync(h + 3 * P + 1, p->a.scal, 4 * 8, hipMemcpyDeviceToHost, s), "copy scalars"));
+  VEMB_TRY(enqueue_bound(p));
+  VEMB_TRY(hip_rc(hipMemcpyAsync(h, p->a.lmin, (P + 1) * 8, hipMemcpyDeviceToHost, s), "copy lambda_min"));
+  VEMB_TRY(hip_rc(hipEventRecord(p->diag_ev, s), "diagnostics event"));
+  p->diag_pending = true;
+  return VEMB_OK;
+}
+
+int vemb_diagnostics_collect(vemb_problem* p, double* lb, double* e_per_site, double* feas_err) {
+  if (!p || !lb) return fail(VEMB_E_INVALID, "NULL argument");
+  if (!p->diag_pending) return fail(VEMB_E_INVALID, "no diagnostics enqueued");
+  VEMB_TRY(hip_rc(hipEventSynchronize(p->diag_ev), "diagnostics wait"));
+  p->diag_pending = false;
+  const int P = p->P;
+  const double* h = p->diag_host;
+  return diag_reduce(p, h, h + P + 1, h + 2 * P + 1, h + 3 * P + 1, lb, e_per_site, feas_err);
 }
 
 int vemb_marginals(vemb_problem* p, int which, double* rho0, double* rho_pairs) {
@@ -621,6 +741,7 @@ int vemb_set_state(vemb_problem* p, const vemb_state* st) {
   }
   VEMB_TRY(hip_rc(hipStreamSynchronize(s), "set_state sync"));
   p->v_valid = with_v;
+  p->k_valid = false;
   p->t = st->t;
   return VEMB_OK;
 }
@@ -659,6 +780,19 @@ int vemb_set_profiling(vemb_problem* p, int enable) {
     p->prof_n[k] = 0;
   }
   p->profiling = enable != 0;
+  p->prof_mask = enable ? 0xffffffffu : 0u;
+  // events for the timings are created here, not between launches
+  while (p->profiling && p->free_events.size() < 2048) {
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) break;
+    p->free_events.push_back(e);
+  }
+  return VEMB_OK;
+}
+
+int vemb_set_profiling_mask(vemb_problem* p, uint32_t kernels) {
+  VEMB_TRY(vemb_set_profiling(p, kernels != 0));
+  p->prof_mask = kernels;
   return VEMB_OK;
 }
 
@@ -682,6 +816,8 @@ void vemb_destroy(vemb_problem* p) {
   }
   for (hipEvent_t e : p->free_events) hipEventDestroy(e);
   for (void* ptr : p->allocations) hipFree(ptr);
+  if (p->diag_ev) hipEventDestroy(p->diag_ev);
+  if (p->diag_host) hipHostFree(p->diag_host);
   if (p->fork_ev) hipEventDestroy(p->fork_ev);
   if (p->join_ev) hipEventDestroy(p->join_ev);
   if (p->side) hipStreamDestroy(p->side);

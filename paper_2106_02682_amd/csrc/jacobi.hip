@@ -494,15 +494,17 @@ hipError_t launch_momentum_projection(double* Xh, int n_op, int K, int precision
 }
 
 hipError_t launch_psd_batched(const double* in, double* out, int n, int batch, bool is_complex, int precision,
-                              int max_sweeps, int* sweeps, double* vstore, int tpb, hipStream_t st) {
+                              int max_sweeps, int* sweeps, double* vstore, int tpb, hipStream_t st, int cold) {
+  if (!vstore) cold = 1;
   if (is_complex) {
     ArrayPolicy<true> pol{in, out, nullptr, nullptr, sweeps, n};
     ArrayPolicy<true> quiet{in, out, nullptr, nullptr, nullptr, n};
-    return by_precision<cplx<float>, cplx<double>>(pol, quiet, n, batch, precision, max_sweeps, vstore, 1, tpb, st);
+    return by_precision<cplx<float>, cplx<double>>(pol, quiet, n, batch, precision, max_sweeps, vstore, cold, tpb,
+                                                   st);
   }
   ArrayPolicy<false> pol{in, out, nullptr, nullptr, sweeps, n};
   ArrayPolicy<false> quiet{in, out, nullptr, nullptr, nullptr, n};
-  return by_precision<float, double>(pol, quiet, n, batch, precision, max_sweeps, vstore, 1, tpb, st);
+  return by_precision<float, double>(pol, quiet, n, batch, precision, max_sweeps, vstore, cold, tpb, st);
 }
 
 hipError_t launch_projection_group_lds(int kind, int n, int count, int precision, int max_sweeps, int cold, int tpb,
@@ -529,9 +531,9 @@ hipError_t launch_eigvalsh_batched(const double* in, double* w, int n, int batch
 }
 
 hipError_t launch_lambda_min(const double* K, double* lmin, int n, int count, int max_sweeps, int* sweeps,
-                             hipStream_t st) {
+                             hipStream_t st, int tpb, double* vstore, int cold) {
   ArrayPolicy<false> pol{K, nullptr, nullptr, lmin, sweeps, n};
-  return dispatch<double, kEigvals>(pol, n, count, max_sweeps, st);
+  return dispatch<double, kEigvals>(pol, n, count, max_sweeps, st, vstore, vstore ? cold : 1, tpb);
 }
 
 }  // namespace vemb

@@ -46,9 +46,10 @@ hipError_t launch_momentum_projection(double* Xh, int n_op, int K, int precision
 
 // Isolated batched projection / eigenvalues (ABI entry points).
 // vstore: eigenvector scratch (batch x n x n, complex doubles for Hermitian), needed by MIXED.
-// tpb: threads per workgroup of the LDS solver (256 / 512 / 1024), see the autotuner in api.cpp.
+// tpb: LDS solver variant (256 / 512 / 1024 threads, 64 / 128 register-resident), see the
+// autotuner in api.cpp.  cold = 0 starts from the eigenvectors in vstore (needs vstore).
 hipError_t launch_psd_batched(const double* in, double* out, int n, int batch, bool is_complex, int precision,
-                              int max_sweeps, int* sweeps, double* vstore, int tpb, hipStream_t st);
+                              int max_sweeps, int* sweeps, double* vstore, int tpb, hipStream_t st, int cold = 1);
 hipError_t launch_eigvalsh_batched(const double* in, double* w, int n, int batch, bool is_complex,
                                    int max_sweeps, int* sweeps, hipStream_t st);
 
@@ -64,9 +65,10 @@ hipError_t launch_psd_batched_big(const double* in, double* out, int n, int batc
 hipError_t launch_eigvals_big(const double* in, double* w, double* wmin, int n, int count, bool is_complex,
                               int max_sweeps, int* sweeps, void* wscr, void* tscr, hipStream_t st);
 
-// Smallest eigenvalue of `count` symmetric n x n matrices stored contiguously.
+// Smallest eigenvalue of `count` symmetric n x n matrices stored contiguously; with
+// vstore (count x n x n) the eigenvectors are kept and, unless cold, reused as the start.
 hipError_t launch_lambda_min(const double* K, double* lmin, int n, int count, int max_sweeps, int* sweeps,
-                             hipStream_t st);
+                             hipStream_t st, int tpb = 256, double* vstore = nullptr, int cold = 1);
 
 // ----- Iteration kernels (step_kernels.hip) ---------------------------------
 struct StepArgs {

@@ -30,11 +30,19 @@ struct vemb_problem {
   vemb::OpTables* ops = nullptr;
   // kernel timing (vemb_set_profiling)
   bool profiling = false;
+  uint32_t prof_mask = 0;  // kernels timed (bit per vemb_kernel_id)
+  // asynchronous diagnostics: pinned host copies [lmin (P+1) | e_pair (P) | feas (P) | scal (4)]
+  double* diag_host = nullptr;
+  hipEvent_t diag_ev = nullptr;
+  bool diag_pending = false;
   struct Mark { int id; hipEvent_t start, stop; };
   std::vector<Mark> marks;
   std::vector<hipEvent_t> free_events;
   double prof_ms[VEMB_K_COUNT] = {};
   bool v_valid = false;  // Vpair / Vmom hold eigenvectors of the previous iteration
+  double* Kv = nullptr;   // eigenvectors of the bound matrices (pair blocks up to 128), kept between bounds
+  bool k_valid = false;
+  int64_t k_uses = 0;  // bound evaluations; every 16th restarts them cold (orthogonality drift)
   int tpb_pair = 256, tpb_mom = 256;  // threads per workgroup of the LDS solver (autotuned)
   int64_t prof_n[VEMB_K_COUNT] = {};
 };

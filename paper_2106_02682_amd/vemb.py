@@ -33,7 +33,8 @@ EXPORTS = [
     "vemb_warm_size", "vemb_warm_encode", "vemb_warm_start", "vemb_mlp_create", "vemb_mlp_num_params",
     "vemb_mlp_set_params", "vemb_mlp_get_params", "vemb_mlp_fit_normalization", "vemb_mlp_get_normalization",
     "vemb_mlp_set_normalization", "vemb_mlp_forward", "vemb_mlp_gradients", "vemb_mlp_adam_step",
-    "vemb_mlp_train_step", "vemb_mlp_destroy",
+    "vemb_mlp_train_step", "vemb_mlp_destroy", "vemb_diagnostics", "vemb_diagnostics_enqueue",
+    "vemb_diagnostics_collect", "vemb_set_profiling_mask",
 ]
 KERNELS = ["pair_update", "pair_xstep", "pair_projection", "cluster_update", "dft_forward", "momentum_projection",
            "dft_inverse", "bound_build", "lambda_min"]
@@ -110,6 +111,10 @@ def lib():
     L.vemb_problem_threads.argtypes = [vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
     L.vemb_dual_bound.argtypes = [vp, _DP]
     L.vemb_primal_energy.argtypes = [vp, _DP, _DP]
+    L.vemb_diagnostics.argtypes = [vp, _DP, _DP, _DP]
+    L.vemb_diagnostics_enqueue.argtypes = [vp]
+    L.vemb_diagnostics_collect.argtypes = [vp, _DP, _DP, _DP]
+    L.vemb_set_profiling_mask.argtypes = [vp, ctypes.c_uint32]
     L.vemb_marginals.argtypes = [vp, ctypes.c_int, _DP, _DP]
     L.vemb_get_state.argtypes = [vp, ctypes.POINTER(vemb_state)]
     L.vemb_set_state.argtypes = [vp, ctypes.POINTER(vemb_state)]
@@ -243,6 +248,23 @@ def primal_energy(h):
     return e.value, f.value
 
 
+def diagnostics(h):
+    """(bound per site, energy per site, feasibility error) with one synchronisation."""
+    lb, e, f = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    _check(lib().vemb_diagnostics(h, ctypes.byref(lb), ctypes.byref(e), ctypes.byref(f)))
+    return lb.value, e.value, f.value
+
+
+def diagnostics_enqueue(h):
+    _check(lib().vemb_diagnostics_enqueue(h))
+
+
+def diagnostics_collect(h):
+    lb, e, f = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    _check(lib().vemb_diagnostics_collect(h, ctypes.byref(lb), ctypes.byref(e), ctypes.byref(f)))
+    return lb.value, e.value, f.value
+
+
 def marginals(h, which=RHO):
     info = problem_info(h)
     rho0 = np.zeros((info["m"], info["m"]))
@@ -312,8 +334,15 @@ def psd_project_batched_ex(inp, out, is_complex=False, precision="fp64", max_swe
                                              int(tpb), st))
 
 
-def set_profiling(h, enable=True):
-    _check(lib().vemb_set_profiling(h, int(bool(enable))))
+def set_profiling(h, enable=True, kernels=None):
+    """Kernel timing on / off; ``kernels`` (names from KERNELS) restricts it to those."""
+    if kernels is None:
+        _check(lib().vemb_set_profiling(h, int(bool(enable))))
+    else:
+        mask = 0
+        for k in kernels:
+            mask |= 1 << KERNELS.index(k)
+        _check(lib().vemb_set_profiling_mask(h, mask if enable else 0))
 
 
 def get_profile(h):
@@ -378,14 +407,23 @@ class Problem:
     def last_sweeps(self):
         return last_sweeps(self.h)
 
-    def set_profiling(self, enable=True):
-        set_profiling(self.h, enable)
+    def set_profiling(self, enable=True, kernels=None):
+        set_profiling(self.h, enable, kernels)
 
     def get_profile(self):
         return get_profile(self.h)
 
     def primal_energy(self):
         return primal_energy(self.h)
+
+    def diagnostics(self):
+        return diagnostics(self.h)
+
+    def diagnostics_enqueue(self):
+        diagnostics_enqueue(self.h)
+
+    def diagnostics_collect(self):
+        return diagnostics_collect(self.h)
 
     def marginals(self, which=RHO):
         return marginals(self.h, which)

@@ -265,3 +265,50 @@ def test_set_state_rejects_nonfinite(vemb):
         with pytest.raises(v.VembError) as ei:
             g.set_state(st)
         assert ei.value.code == -5
+
+
+def test_repeated_bounds_and_diagnostics(vemb):
+    """The bound's eigensolves start from the previous evaluation's eigenvectors (every 16th cold):
+    each of 20 evaluations, 3 iterations apart, against the oracle; vemb_diagnostics against the
+    separate calls."""
+    from paper_2106_02682_amd import vemb as v
+
+    w = synth.tfi_ring(12, 3, 0.7)
+    p = alg6.Problem.from_workload(w)
+    s = alg6.initial_state(p)
+    with v.Problem.from_workload(w) as g:
+        for k in range(20):
+            g.step(3)
+            for _ in range(3):
+                s = alg6.step(p, s)
+            if k % 2:
+                lb, e, feas = g.diagnostics()
+            else:
+                lb = g.dual_bound()
+                e, feas = g.primal_energy()
+            lb_o = alg6.lower_bound(p, s)
+            assert abs(lb - lb_o) <= 1e-10 * abs(lb_o), (k, lb, lb_o)
+            assert abs(e - alg6.energy_per_site(p, s)) <= 1e-10 * abs(lb_o)
+        lb2 = g.dual_bound()
+        e2, f2 = g.primal_energy()
+        lb3, e3, f3 = g.diagnostics()
+    assert lb3 == pytest.approx(lb2, rel=1e-13) and e3 == e2 and f3 == f2
+
+
+def test_async_diagnostics_match_synchronous(vemb):
+    """Diagnostics queued without draining the stream report the state at their place in the
+    stream, whatever was queued after them."""
+    from paper_2106_02682_amd import vemb as v
+
+    w = synth.tfi_ring(12, 3, 0.7)
+    with v.Problem.from_workload(w) as a, v.Problem.from_workload(w) as b:
+        a.step(7)
+        a.diagnostics_enqueue()
+        a.step(5)  # queued after the diagnostics
+        got = a.diagnostics_collect()
+        b.step(7)
+        want = b.diagnostics()
+        with pytest.raises(v.VembError):
+            a.diagnostics_collect()  # nothing pending
+    assert got[0] == pytest.approx(want[0], rel=1e-13)
+    assert got[1] == want[1] and got[2] == want[2]
