@@ -1,8 +1,9 @@
-"""Tiny dense Algorithm 5 (no translation invariance), FP64.
+"""Dense Algorithm 5 (no translation invariance), FP64.
 
-Oracle; test infrastructure only.  Used to pin the translation-invariant
-reduction of Algorithm 6: started from the same translation-invariant point,
-both must produce the same iterates.  Every unordered cluster pair i < j has
+Oracle; test infrastructure only.  It pins the translation-invariant reduction
+of Algorithm 6 (started from the same translation-invariant point, both produce
+the same iterates) and is the reference of the library's dense variant, which
+also takes one-site fields that break translation invariance (disorder).  Every unordered cluster pair i < j has
 its own rho_ij, rho~_ij, Lambda_ij, Lambda1_ij, Lambda2_ij (Section 3.2), the
 rho_i update collects A_1 terms of pairs (i, j > i) and A_2 terms of pairs
 (j < i, i) (eq. rhoiUpdate), and X is one dense (M n_op) x (M n_op) matrix
@@ -17,13 +18,20 @@ from .maps import pair_solve, psd_project, ptrace1, ptrace2
 
 
 class DenseProblem:
-    """Non-translation-invariant view of an Algorithm 6 problem (same H_0, H_0d, maps)."""
+    """Non-translation-invariant view of an Algorithm 6 problem (same H_0, H_0d, maps), with
+    optional one-site fields (letter, (x, y), coeff) added to the cluster Hamiltonians."""
 
-    def __init__(self, p):
+    def __init__(self, p, fields=()):
         self.p = p
         M = p.M
         self.pairs = [(i, j) for i in range(M) for j in range(i + 1, M)]
         g = p.geom
+        from .model import site_operator
+
+        self.Hc = {i: np.array(p.H0, dtype=float) for i in range(M)}
+        for letter, (x, y), coeff in fields:
+            c, loc = g.locate(x, y)
+            self.Hc[c] = self.Hc[c] + coeff * site_operator({loc: letter}, g.L).real
 
         def offset(i, j):
             ix, iy = divmod(i, g.My)
@@ -60,7 +68,7 @@ def dense_step(dp, st):
     def blk(i, j):
         return X[i * k:(i + 1) * k, j * k:(j + 1) * k]
 
-    Hp_i = {i: p.H0 - p.maps.C0(blk(i, i)) for i in range(M)}
+    Hp_i = {i: dp.Hc[i] - p.maps.C0(blk(i, i)) for i in range(M)}
     Hp_ij = {}
     for (i, j) in dp.pairs:
         R = p.maps.Rd(blk(i, j))
@@ -95,3 +103,55 @@ def dense_step(dp, st):
         G[j * k:(j + 1) * k, i * k:(i + 1) * k] = g.T
     Xn = psd_project(X - eps * G)
     return {"rho": rho, "rho_t": rho_t, "rho_p": rho_p, "Lam": Lam, "Lam1": Lam1, "Lam2": Lam2, "X": Xn}
+
+
+def energy_dense(dp, st):
+    """Energy per site of the latest pair update: [sum_i Tr H_i rho_i + sum_{i<j} Tr H_ij rho_ij] / N."""
+    p = dp.p
+    e = sum(np.trace(dp.Hc[i] @ st["rho"][i]) for i in range(p.M))
+    e += sum(np.trace(dp.H[pair] @ st["rho_p"][pair]) for pair in dp.pairs)
+    return float(e) / (p.M * p.L)
+
+
+def feasibility_dense(dp, st):
+    """eq. feasErr summed over all pairs: consistency and rho = rho~ residuals, per cluster."""
+    m = dp.p.m
+    tot = 0.0
+    for (i, j) in dp.pairs:
+        r = st["rho_p"][(i, j)]
+        tot += np.sum((ptrace2(r, m) - st["rho"][i]) ** 2) + np.sum((ptrace1(r, m) - st["rho"][j]) ** 2)
+        tot += np.sum((r - st["rho_t"][(i, j)]) ** 2)
+    return float(np.sqrt(tot / dp.p.M))
+
+
+def lower_bound_dense(dp, st):
+    """Lagrangian lower bound per site for the dense problem, valid for any PSD X and any
+    symmetric Lambda1, Lambda2 (Section 2.4 applied pair by pair):
+
+      E >= sum_i lmin(H'_i - sum_{(i,b)} L1_(i,b) - sum_{(a,i)} L2_(a,i))
+           + sum_{i<j} lmin(H'_ij + L1_ij x I + I x L2_ij),
+
+    with H'_i = H_i - C_0(X_ii), H'_ij = H_ij - R(X_ij) - R(X_ij)^T; divided by N.
+    Minimising the Lagrangian over trace-one PSD marginals gives the smallest eigenvalues."""
+    p = dp.p
+    M, m, k = p.M, p.m, p.n_op
+    X = st["X"]
+    Im = np.eye(m)
+
+    def sym(a):
+        return 0.5 * (a + a.T)
+
+    tot = 0.0
+    for i in range(M):
+        A = dp.Hc[i] - p.maps.C0(X[i * k:(i + 1) * k, i * k:(i + 1) * k])
+        for (a, b) in dp.pairs:
+            if a == i:
+                A = A - sym(st["Lam1"][(a, b)])
+            elif b == i:
+                A = A - sym(st["Lam2"][(a, b)])
+        tot += np.linalg.eigvalsh(sym(A))[0]
+    for (i, j) in dp.pairs:
+        R = p.maps.Rd(X[i * k:(i + 1) * k, j * k:(j + 1) * k])
+        K = dp.H[(i, j)] - R - R.T + np.kron(sym(st["Lam1"][(i, j)]), Im) + np.kron(Im, sym(st["Lam2"][(i, j)]))
+        tot += np.linalg.eigvalsh(sym(K))[0]
+    return float(tot) / (M * p.L)

@@ -13,9 +13,9 @@ import numpy as np
 from .model import full_hamiltonian_sparse
 
 
-def ground_state(terms, extent):
+def ground_state(terms, extent, fields=()):
     """(E_0, psi) of the full Hamiltonian by sparse Lanczos (dense eigh for tiny sizes)."""
-    H = full_hamiltonian_sparse(terms, extent)
+    H = full_hamiltonian_sparse(terms, extent, fields)
     dim = H.shape[0]
     if dim <= 256:
         w, V = np.linalg.eigh(H.toarray())
@@ -64,3 +64,27 @@ def cluster_marginals(psi, extent, cluster):
     rho0 = reduced(sites_of(0)).real
     rhos = np.stack([reduced(sites_of(0) + sites_of(d)).real for d in range(1, M)])
     return rho0, rhos
+
+
+def all_marginals(psi, extent, cluster):
+    """rho_i for every cluster and rho_ij for every pair i < j of |psi><psi| (dense Algorithm 5 layout)."""
+    Nx, Ny = extent
+    Lx, Ly = cluster
+    N = Nx * Ny
+    My = Ny // Ly
+    M = (Nx // Lx) * My
+
+    def sites_of(c):
+        cx, cy = divmod(c, My)
+        return [(cx * Lx + lx) * Ny + (cy * Ly + ly) for lx in range(Lx) for ly in range(Ly)]
+
+    T = psi.reshape((2,) * N)
+
+    def reduced(site_list):
+        rest = [s for s in range(N) if s not in site_list]
+        A = np.transpose(T, site_list + rest).reshape(2 ** len(site_list), -1)
+        return (A @ A.conj().T).real
+
+    rho = {i: reduced(sites_of(i)) for i in range(M)}
+    pairs = {(i, j): reduced(sites_of(i) + sites_of(j)) for i in range(M) for j in range(i + 1, M)}
+    return rho, pairs

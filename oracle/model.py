@@ -101,10 +101,12 @@ def local_hamiltonians(terms, geom: Geometry):
     return H0.real.copy(), Hd[1:].real.copy()
 
 
-def full_hamiltonian_sparse(terms, extent):
+def full_hamiltonian_sparse(terms, extent, fields=()):
     """Sparse 2^N x 2^N Hamiltonian on the whole lattice (for exact diagonalisation pins).
 
     Site ordering: flat site index ``x * Ny + y``, site 0 the most significant bit.
+    ``fields``: extra one-site terms (letter, (x, y), coeff) at single sites (not
+    translated), for Hamiltonians without translation invariance.
     """
     import scipy.sparse as sp
 
@@ -135,6 +137,18 @@ def full_hamiltonian_sparse(terms, extent):
                         phase *= 1j * (1 - 2 * b)
                 rows = idx ^ flip
                 H = H + sp.csr_matrix((coeff * phase, (rows, idx)), shape=(dim, dim))
+    for p, (x, y), coeff in fields:
+        s = (x % Nx) * Ny + (y % Ny)
+        b = bit(s)
+        flip = np.zeros(dim, dtype=np.int64)
+        phase = np.ones(dim, dtype=complex)
+        if p == "X":
+            flip ^= 1 << (N - 1 - s)
+        elif p == "Z":
+            phase = phase * (1 - 2 * b)
+        else:
+            raise ValueError("one-site fields are X or Z (real)")
+        H = H + sp.csr_matrix((coeff * phase, (idx ^ flip, idx)), shape=(dim, dim))
     if abs(H.imag).max() > 1e-12:
         raise ValueError("complex Hamiltonian")
     return H.real.tocsr()
