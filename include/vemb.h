@@ -283,6 +283,85 @@ int vemb_batch_info(const vemb_batch* b, int* classes, int* launches_per_iterati
 int vemb_batch_sync(vemb_batch* b);
 void vemb_batch_destroy(vemb_batch* b);
 
+/* ---- Dense Algorithm 5: no translation invariance (Section 3.2) --------------
+ * One marginal rho_i per cluster and rho_ij, rho~_ij, Lambda_ij, Lambda1_ij,
+ * Lambda2_ij per unordered cluster pair i < j (Q = M(M-1)/2 pairs, ordered
+ * (0,1), (0,2), ..., (1,2), ...), and one dense dual X of size K = M n_op
+ * (block (i, j) couples the operators of clusters i and j).  One iteration:
+ *   1. pair update of every rho_ij with H'_ij = H_ij - R(X_ij) - R(X_ij)^T   (eq. rhoijUpdate)
+ *   2. rho~_ij = Pi(rho_ij - Lambda_ij / mu), Lambda_ij update            (eq. rhoijTildeUpdate)
+ *   3. rho_i from the pairs that contain i: A_1 terms of pairs (i, j > i),
+ *      A_2 terms of pairs (j < i, i), divided by nu (M-1), unit trace      (eq. rhoiUpdate)
+ *   4. Lambda1_ij, Lambda2_ij updates with the new rho_i, rho_j
+ *   5. X <- Pi(X - eps G) for the dense G of Section 2.2 (diagonal blocks
+ *      G_00(rho_i), off-diagonal blocks G_0d(rho_ij) and their transposes),
+ *      one eigensolve of the whole K x K matrix.
+ * The bonds are those of the translation-invariant term list on the torus
+ * (H_ij = H_0d with d the offset from i to j); one-site fields may differ from
+ * site to site (disorder), which translation invariance cannot represent.
+ * Limits: K <= 256 (K > 64 is solved by the streamed eigensolver on storage
+ * padded with zeros to a multiple of 32), pair matrices n <= 256.  Same option
+ * struct, precision modes and warm starts as vemb_problem. */
+typedef struct vemb_dense vemb_dense;
+
+/* One-site term coeff * pauli at lattice site (x, y) (wrapped onto the torus),
+ * added to the Hamiltonian of the cluster holding the site.  pauli: VEMB_X or
+ * VEMB_Z (real operators). */
+typedef struct {
+  int32_t x, y;
+  int32_t pauli;
+  double coeff;
+} vemb_site_field;
+
+typedef struct {
+  int32_t M, Q, L, m, n, n_op, K;
+  int64_t t; /* iterations done */
+} vemb_dense_info;
+
+/* Host buffers (each may be NULL): X (K x K), rho0 (M x m x m), rho, rho_t, Lam
+ * (Q x n x n), Lam1, Lam2 (Q x m x m); rho is the latest pair update. */
+typedef struct {
+  int64_t t;
+  double* X;
+  double* rho0;
+  double* rho;
+  double* rho_t;
+  double* Lam;
+  double* Lam1;
+  double* Lam2;
+} vemb_dense_state;
+
+/* Builds the cluster Hamiltonians (translation-invariant terms plus `nfields`
+ * site fields, copied), allocates device state and initialises it as in
+ * Section 4 (multipliers 0, marginals identity / trace, X = I).
+ * Errors: VEMB_E_INVALID, VEMB_E_UNSUPPORTED (K or n above 256, a field other
+ * than X or Z), VEMB_E_NOMEM, VEMB_E_HIP. */
+int vemb_dense_create(const vemb_hamiltonian* H, const vemb_lattice* lattice, const vemb_clusters* clusters,
+                      const vemb_site_field* fields, int nfields, const vemb_options* opts, void* hip_stream,
+                      vemb_dense** out);
+int vemb_dense_get_info(const vemb_dense* d, vemb_dense_info* info);
+/* Enqueues `iters` iterations.  Asynchronous. */
+int vemb_dense_step(vemb_dense* d, int iters);
+/* Lagrangian lower bound per site at the current X, Lambda1, Lambda2 (Section 2.4
+ * pair by pair): [sum_i lmin(H'_i - sum_{(i,b)} sym Lambda1 - sum_{(a,i)} sym Lambda2)
+ * + sum_{i<j} lmin(H'_ij + sym Lambda1_ij x I + I x sym Lambda2_ij)] / N, with
+ * H'_i = H_i - C_0(X_ii).  Synchronises.  VEMB_E_NUMERIC if not finite. */
+int vemb_dense_dual_bound(vemb_dense* d, double* lb_per_site);
+/* Energy per site of the latest pair update, [sum_i Tr H_i rho_i + sum_{i<j}
+ * Tr H_ij rho_ij] / N, and the feasibility error sqrt(sum over pairs of the
+ * consistency and rho = rho~ residuals / M) (eq. feasErr).  Either may be NULL.
+ * Synchronises. */
+int vemb_dense_primal_energy(vemb_dense* d, double* e_per_site, double* feas_err);
+/* Copies the state to the host buffers of *st (NULL members skipped).  Synchronises. */
+int vemb_dense_get_state(vemb_dense* d, vemb_dense_state* st);
+/* Replaces the members of the state that are not NULL (X should be symmetric: the
+ * projection reads its symmetric part); the next eigensolves start cold.
+ * VEMB_E_NUMERIC for a non-finite value (nothing is changed then). */
+int vemb_dense_set_state(vemb_dense* d, const vemb_dense_state* st);
+/* Sweeps of the last pair projections (maximum) and of the last X projection. */
+int vemb_dense_last_sweeps(vemb_dense* d, int* pair_max, int* x_sweeps);
+void vemb_dense_destroy(vemb_dense* d);
+
 /* ---- Learned warm start ------------------------------------------------------
  * A multilayer perceptron maps Hamiltonian parameters to a fixed-size encoding
  * of a converged state, and the encoding becomes the starting point of a new

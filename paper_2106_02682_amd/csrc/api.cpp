@@ -307,33 +307,11 @@ int vemb_create_problem(const vemb_hamiltonian* H, const vemb_lattice* lat, cons
   if (!H || !lat || !cl || !out || (H->nterms > 0 && !H->terms)) return fail(VEMB_E_INVALID, "NULL argument");
   *out = nullptr;
   vemb_options o;
-  vemb_default_options(&o);
-  if (opts) o = *opts;
-  if (o.max_sweeps <= 0) o.max_sweeps = 40;
-  if (o.sign == 0) o.sign = -1;
-  if (o.warm_refresh == 0) o.warm_refresh = 64;
-  if (!(o.mu > 0 && o.nu > 0 && o.eps > 0)) return fail(VEMB_E_INVALID, "mu, nu, eps must be positive");
-  if (o.opset != VEMB_OPSET_COMPLETE && o.opset != VEMB_OPSET_PAULI1) return fail(VEMB_E_INVALID, "unknown opset");
-  if (o.precision < VEMB_FP64 || o.precision > VEMB_FP32) return fail(VEMB_E_INVALID, "unknown precision");
-  if (lat->ndim != 1 && lat->ndim != 2) return fail(VEMB_E_INVALID, "ndim must be 1 or 2");
   Geometry g{};
-  g.Nx = lat->extent[0];
-  g.Ny = lat->ndim == 2 ? lat->extent[1] : 1;
-  g.Lx = cl->shape[0];
-  g.Ly = lat->ndim == 2 ? cl->shape[1] : 1;
-  if (lat->ndim == 1 && cl->shape[1] > 1) return fail(VEMB_E_INVALID, "2D cluster on a 1D lattice");
-  if (g.Nx <= 0 || g.Ny <= 0 || g.Lx <= 0 || g.Ly <= 0) return fail(VEMB_E_INVALID, "extents must be positive");
-  if (!lat->periodic[0] || (lat->ndim == 2 && !lat->periodic[1]))
-    return fail(VEMB_E_UNSUPPORTED, "translation invariance needs periodic boundaries");
-  if (g.Nx % g.Lx || g.Ny % g.Ly) return fail(VEMB_E_INVALID, "clusters do not tile the lattice");
-  g.Mx = g.Nx / g.Lx;
-  g.My = g.Ny / g.Ly;
-  g.M = g.Mx * g.My;
-  g.L = g.Lx * g.Ly;
-  if (g.M < 2) return fail(VEMB_E_UNSUPPORTED, "at least two clusters are needed (M >= 2)");
-  if (g.L > 4) return fail(VEMB_E_UNSUPPORTED, "clusters of more than 4 sites are not supported");
-  g.m = 1 << g.L;
-  g.n = g.m * g.m;
+  std::string perr;
+  int prc = normalize_options(opts, o, perr);
+  if (prc == VEMB_OK) prc = parse_geometry(*lat, *cl, g, perr);
+  if (prc != VEMB_OK) return fail(prc, perr);
   const int n_op = o.opset == VEMB_OPSET_COMPLETE ? g.n : 3 * g.L;
   // eigensolver capacity: pair blocks n x n (real), momentum blocks n_op x n_op (complex), n <= 256
   if (g.n > 256 || n_op > 256) return fail(VEMB_E_UNSUPPORTED, "matrices above 256 x 256 are not supported");

@@ -59,6 +59,41 @@ std::vector<cd> kron(const std::vector<cd>& A, const std::vector<cd>& B, int m) 
 
 }  // namespace
 
+int normalize_options(const vemb_options* in, vemb_options& o, std::string& err) {
+  vemb_default_options(&o);
+  if (in) o = *in;
+  if (o.max_sweeps <= 0) o.max_sweeps = 40;
+  if (o.sign == 0) o.sign = -1;
+  if (o.warm_refresh == 0) o.warm_refresh = 64;
+  if (!(o.mu > 0 && o.nu > 0 && o.eps > 0)) return err = "mu, nu, eps must be positive", VEMB_E_INVALID;
+  if (o.opset != VEMB_OPSET_COMPLETE && o.opset != VEMB_OPSET_PAULI1) return err = "unknown opset", VEMB_E_INVALID;
+  if (o.precision < VEMB_FP64 || o.precision > VEMB_FP32) return err = "unknown precision", VEMB_E_INVALID;
+  return VEMB_OK;
+}
+
+int parse_geometry(const vemb_lattice& lat, const vemb_clusters& cl, Geometry& g, std::string& err) {
+  if (lat.ndim != 1 && lat.ndim != 2) return err = "ndim must be 1 or 2", VEMB_E_INVALID;
+  g = Geometry{};
+  g.Nx = lat.extent[0];
+  g.Ny = lat.ndim == 2 ? lat.extent[1] : 1;
+  g.Lx = cl.shape[0];
+  g.Ly = lat.ndim == 2 ? cl.shape[1] : 1;
+  if (lat.ndim == 1 && cl.shape[1] > 1) return err = "2D cluster on a 1D lattice", VEMB_E_INVALID;
+  if (g.Nx <= 0 || g.Ny <= 0 || g.Lx <= 0 || g.Ly <= 0) return err = "extents must be positive", VEMB_E_INVALID;
+  if (!lat.periodic[0] || (lat.ndim == 2 && !lat.periodic[1]))
+    return err = "translation invariance needs periodic boundaries", VEMB_E_UNSUPPORTED;
+  if (g.Nx % g.Lx || g.Ny % g.Ly) return err = "clusters do not tile the lattice", VEMB_E_INVALID;
+  g.Mx = g.Nx / g.Lx;
+  g.My = g.Ny / g.Ly;
+  g.M = g.Mx * g.My;
+  g.L = g.Lx * g.Ly;
+  if (g.M < 2) return err = "at least two clusters are needed (M >= 2)", VEMB_E_UNSUPPORTED;
+  if (g.L > 4) return err = "clusters of more than 4 sites are not supported", VEMB_E_UNSUPPORTED;
+  g.m = 1 << g.L;
+  g.n = g.m * g.m;
+  return VEMB_OK;
+}
+
 int build_model(const vemb_hamiltonian& H, const Geometry& g, HostModel& out, std::string& err) {
   const int L = g.L, m = g.m, n = g.n, M = g.M;
   std::vector<cd> H0((size_t)m * m, cd(0, 0));
@@ -195,6 +230,27 @@ void build_momenta(const Geometry& g, std::vector<double>& tw, std::vector<doubl
       tw[2 * ((size_t)ki * M + d) + 1] = -norm * std::sin(ang);
     }
   }
+}
+
+int add_site_field(const Geometry& g, int x, int y, int pauli, double coeff, std::vector<double>& Hc,
+                   std::string& err) {
+  if (pauli != VEMB_X && pauli != VEMB_Z) {
+    err = "one-site fields must be X or Z (real)";
+    return VEMB_E_UNSUPPORTED;
+  }
+  if (!std::isfinite(coeff)) {
+    err = "non-finite field";
+    return VEMB_E_INVALID;
+  }
+  const int xs = ((x % g.Nx) + g.Nx) % g.Nx, ys = ((y % g.Ny) + g.Ny) % g.Ny;
+  const int c = (xs / g.Lx) * g.My + (ys / g.Ly);
+  const int loc = (xs % g.Lx) * g.Ly + (ys % g.Ly);
+  std::vector<int> letters(g.L, VEMB_I);
+  letters[loc] = pauli;
+  const std::vector<cd> op = cluster_operator(letters, g.L);
+  const size_t mm = (size_t)g.m * g.m;
+  for (size_t e = 0; e < mm; ++e) Hc[(size_t)c * mm + e] += coeff * op[e].real();
+  return VEMB_OK;
 }
 
 }  // namespace vemb

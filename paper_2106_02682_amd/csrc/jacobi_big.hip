@@ -391,16 +391,18 @@ hipError_t launch_momentum_projection_big(double* Xh, int n_op, int K, int preci
 }
 
 hipError_t launch_psd_batched_big(const double* in, double* out, int n, int batch, bool is_complex, int precision,
-                                  int max_sweeps, int* sweeps, double* vstore, void* wscr, void* tscr, hipStream_t st) {
+                                  int max_sweeps, int* sweeps, double* vstore, void* wscr, void* tscr, hipStream_t st,
+                                  int cold) {
+  if (!vstore) cold = 1;
   if (is_complex) {
     ArrayPolicy<true> pol{in, out, nullptr, nullptr, sweeps, n};
     ArrayPolicy<true> quiet{in, out, nullptr, nullptr, nullptr, n};
-    return big_by_precision<cplx<float>, cplx<double>>(pol, quiet, n, batch, precision, max_sweeps, vstore, 1, wscr,
-                                                       tscr, st);
+    return big_by_precision<cplx<float>, cplx<double>>(pol, quiet, n, batch, precision, max_sweeps, vstore, cold,
+                                                       wscr, tscr, st);
   }
   ArrayPolicy<false> pol{in, out, nullptr, nullptr, sweeps, n};
   ArrayPolicy<false> quiet{in, out, nullptr, nullptr, nullptr, n};
-  return big_by_precision<float, double>(pol, quiet, n, batch, precision, max_sweeps, vstore, 1, wscr, tscr, st);
+  return big_by_precision<float, double>(pol, quiet, n, batch, precision, max_sweeps, vstore, cold, wscr, tscr, st);
 }
 
 hipError_t launch_projection_group_lds(int kind, int n, int count, int precision, int max_sweeps, int cold, int tpb,

@@ -60,8 +60,10 @@ hipError_t launch_pair_projection_big(const double* rho, double* Lam, double* rh
                                       void* wscr, void* tscr, hipStream_t st);
 hipError_t launch_momentum_projection_big(double* Xh, int n_op, int K, int precision, int max_sweeps, int* sweeps,
                                           double* vstore, int cold, void* wscr, void* tscr, hipStream_t st);
+// cold = 0 starts from the eigenvectors in vstore (needs vstore).
 hipError_t launch_psd_batched_big(const double* in, double* out, int n, int batch, bool is_complex, int precision,
-                                  int max_sweeps, int* sweeps, double* vstore, void* wscr, void* tscr, hipStream_t st);
+                                  int max_sweeps, int* sweeps, double* vstore, void* wscr, void* tscr, hipStream_t st,
+                                  int cold = 1);
 hipError_t launch_eigvals_big(const double* in, double* w, double* wmin, int n, int count, bool is_complex,
                               int max_sweeps, int* sweeps, void* wscr, void* tscr, hipStream_t st);
 

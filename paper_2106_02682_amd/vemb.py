@@ -34,7 +34,9 @@ EXPORTS = [
     "vemb_mlp_set_params", "vemb_mlp_get_params", "vemb_mlp_fit_normalization", "vemb_mlp_get_normalization",
     "vemb_mlp_set_normalization", "vemb_mlp_forward", "vemb_mlp_gradients", "vemb_mlp_adam_step",
     "vemb_mlp_train_step", "vemb_mlp_destroy", "vemb_diagnostics", "vemb_diagnostics_enqueue",
-    "vemb_diagnostics_collect", "vemb_set_profiling_mask",
+    "vemb_diagnostics_collect", "vemb_set_profiling_mask", "vemb_dense_create", "vemb_dense_get_info",
+    "vemb_dense_step", "vemb_dense_dual_bound", "vemb_dense_primal_energy", "vemb_dense_get_state",
+    "vemb_dense_set_state", "vemb_dense_last_sweeps", "vemb_dense_destroy",
 ]
 KERNELS = ["pair_update", "pair_xstep", "pair_projection", "cluster_update", "dft_forward", "momentum_projection",
            "dft_inverse", "bound_build", "lambda_min"]
@@ -85,6 +87,20 @@ class vemb_profile(ctypes.Structure):
 class vemb_state(ctypes.Structure):
     _fields_ = [("t", ctypes.c_int64), ("X", _DP), ("rho0", _DP), ("rho", _DP), ("rho_t", _DP), ("Lam", _DP),
                 ("Lam1", _DP), ("Lam2", _DP), ("Vpair", _DP), ("Vmom", _DP)]
+
+
+class vemb_site_field(ctypes.Structure):
+    _fields_ = [("x", ctypes.c_int32), ("y", ctypes.c_int32), ("pauli", ctypes.c_int32), ("coeff", ctypes.c_double)]
+
+
+class vemb_dense_info(ctypes.Structure):
+    _fields_ = [("M", ctypes.c_int32), ("Q", ctypes.c_int32), ("L", ctypes.c_int32), ("m", ctypes.c_int32),
+                ("n", ctypes.c_int32), ("n_op", ctypes.c_int32), ("K", ctypes.c_int32), ("t", ctypes.c_int64)]
+
+
+class vemb_dense_state(ctypes.Structure):
+    _fields_ = [("t", ctypes.c_int64), ("X", _DP), ("rho0", _DP), ("rho", _DP), ("rho_t", _DP), ("Lam", _DP),
+                ("Lam1", _DP), ("Lam2", _DP)]
 
 
 _lib = None
@@ -156,9 +172,21 @@ def lib():
     L.vemb_mlp_train_step.argtypes = [vp, vp, vp, ctypes.c_int, vp, ctypes.c_int, ctypes.c_float, _DP]
     L.vemb_mlp_destroy.argtypes = [vp]
     L.vemb_mlp_destroy.restype = None
+    L.vemb_dense_create.argtypes = [ctypes.POINTER(vemb_hamiltonian), ctypes.POINTER(vemb_lattice),
+                                    ctypes.POINTER(vemb_clusters), ctypes.POINTER(vemb_site_field), ctypes.c_int,
+                                    ctypes.POINTER(vemb_options), vp, ctypes.POINTER(vp)]
+    L.vemb_dense_get_info.argtypes = [vp, ctypes.POINTER(vemb_dense_info)]
+    L.vemb_dense_step.argtypes = [vp, ctypes.c_int]
+    L.vemb_dense_dual_bound.argtypes = [vp, _DP]
+    L.vemb_dense_primal_energy.argtypes = [vp, _DP, _DP]
+    L.vemb_dense_get_state.argtypes = [vp, ctypes.POINTER(vemb_dense_state)]
+    L.vemb_dense_set_state.argtypes = [vp, ctypes.POINTER(vemb_dense_state)]
+    L.vemb_dense_last_sweeps.argtypes = [vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
+    L.vemb_dense_destroy.argtypes = [vp]
+    L.vemb_dense_destroy.restype = None
     for name in EXPORTS:
         if name not in ("vemb_default_options", "vemb_destroy", "vemb_last_error", "vemb_batch_destroy",
-                        "vemb_mlp_destroy"):
+                        "vemb_mlp_destroy", "vemb_dense_destroy"):
             getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -192,9 +220,9 @@ def default_options():
     return o
 
 
-def create_problem(terms, extent, cluster, opset="complete", precision="fp64", mu=10.0, nu=10.0, eps=2.0,
-                   max_sweeps=40, sign=-1, warm_refresh=64, tpb=0, stream=None):
-    """Terms in the ``synth`` format: (coeff, ((pauli, (ox, oy)), ...))."""
+def _marshal(terms, extent, cluster, opset, precision, mu, nu, eps, max_sweeps, sign, warm_refresh, tpb):
+    """ctypes structs of a term list (``synth`` format: (coeff, ((pauli, (ox, oy)), ...))), lattice,
+    clusters and options; the term array is returned too, to stay alive with the Hamiltonian."""
     arr = (vemb_term * max(1, len(terms)))()
     for t, (coeff, factors) in enumerate(terms):
         arr[t].coeff = float(coeff)
@@ -215,6 +243,14 @@ def create_problem(terms, extent, cluster, opset="complete", precision="fp64", m
     o.sign = sign
     o.warm_refresh = warm_refresh
     o.tpb = tpb
+    return H, lat, cl, o, arr
+
+
+def create_problem(terms, extent, cluster, opset="complete", precision="fp64", mu=10.0, nu=10.0, eps=2.0,
+                   max_sweeps=40, sign=-1, warm_refresh=64, tpb=0, stream=None):
+    """Terms in the ``synth`` format: (coeff, ((pauli, (ox, oy)), ...))."""
+    H, lat, cl, o, _keep = _marshal(terms, extent, cluster, opset, precision, mu, nu, eps, max_sweeps, sign,
+                                    warm_refresh, tpb)
     h = ctypes.c_void_p()
     st = stream if stream is not None else current_stream()
     _check(lib().vemb_create_problem(ctypes.byref(H), ctypes.byref(lat), ctypes.byref(cl), ctypes.byref(o), st,
@@ -603,6 +639,109 @@ class MLP:
     def close(self):
         if self.h:
             lib().vemb_mlp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+# ---------------------------------------------------------------------------
+# Dense Algorithm 5 (no translation invariance): one marginal per cluster and per
+# cluster pair, one dense X; site fields make the clusters differ.
+# ---------------------------------------------------------------------------
+_DENSE_KEYS = ("X", "rho0", "rho", "rho_t", "Lam", "Lam1", "Lam2")
+
+
+class Dense:
+    """Owning wrapper of one dense problem.  fields: iterable of (letter, (x, y), coeff), letter X or Z.
+    Pairs (i, j), i < j, in lexicographic order; state arrays are stacked in that order."""
+
+    def __init__(self, terms, extent, cluster, fields=(), opset="complete", precision="fp64", mu=10.0, nu=10.0,
+                 eps=2.0, max_sweeps=40, sign=-1, warm_refresh=64, tpb=0, stream=None):
+        H, lat, cl, o, keep = _marshal(terms, extent, cluster, opset, precision, mu, nu, eps, max_sweeps, sign,
+                                       warm_refresh, tpb)
+        fields = list(fields)
+        farr = (vemb_site_field * max(1, len(fields)))()
+        for f, (letter, (x, y), coeff) in enumerate(fields):
+            farr[f].x, farr[f].y = int(x), int(y)
+            farr[f].pauli = PAULI[letter]
+            farr[f].coeff = float(coeff)
+        self.h = ctypes.c_void_p()
+        st = stream if stream is not None else current_stream()
+        _check(lib().vemb_dense_create(ctypes.byref(H), ctypes.byref(lat), ctypes.byref(cl), farr, len(fields),
+                                       ctypes.byref(o), st, ctypes.byref(self.h)))
+        info = vemb_dense_info()
+        _check(lib().vemb_dense_get_info(self.h, ctypes.byref(info)))
+        self.info = {f: getattr(info, f) for f, _ in vemb_dense_info._fields_}
+
+    @classmethod
+    def from_workload(cls, w, fields=(), **kw):
+        kw.setdefault("opset", w.opset)
+        kw.setdefault("mu", w.mu)
+        kw.setdefault("nu", w.nu)
+        kw.setdefault("eps", w.eps)
+        return cls(w.terms, w.extent, w.cluster, fields=fields, **kw)
+
+    def t(self):
+        info = vemb_dense_info()
+        _check(lib().vemb_dense_get_info(self.h, ctypes.byref(info)))
+        return info.t
+
+    def step(self, iters=1):
+        _check(lib().vemb_dense_step(self.h, int(iters)))
+
+    def dual_bound(self):
+        v = ctypes.c_double()
+        _check(lib().vemb_dense_dual_bound(self.h, ctypes.byref(v)))
+        return v.value
+
+    def primal_energy(self):
+        e, f = ctypes.c_double(), ctypes.c_double()
+        _check(lib().vemb_dense_primal_energy(self.h, ctypes.byref(e), ctypes.byref(f)))
+        return e.value, f.value
+
+    def last_sweeps(self):
+        a, b = ctypes.c_int(), ctypes.c_int()
+        _check(lib().vemb_dense_last_sweeps(self.h, ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
+
+    def _arrays(self):
+        i = self.info
+        M, Q, m, n, K = i["M"], i["Q"], i["m"], i["n"], i["K"]
+        return {"X": np.zeros((K, K)), "rho0": np.zeros((M, m, m)), "rho": np.zeros((Q, n, n)),
+                "rho_t": np.zeros((Q, n, n)), "Lam": np.zeros((Q, n, n)), "Lam1": np.zeros((Q, m, m)),
+                "Lam2": np.zeros((Q, m, m))}
+
+    def get_state(self):
+        arrs = self._arrays()
+        st = vemb_dense_state(0, *[_ptr(arrs[k]) for k in _DENSE_KEYS])
+        _check(lib().vemb_dense_get_state(self.h, ctypes.byref(st)))
+        arrs["t"] = st.t
+        return arrs
+
+    def set_state(self, state):
+        shapes = self._arrays()
+        arrs = {}
+        for k in _DENSE_KEYS:
+            if state.get(k) is not None:
+                arrs[k] = np.ascontiguousarray(state[k], dtype=np.float64)
+                if arrs[k].shape != shapes[k].shape:
+                    raise ValueError(f"{k}: shape {arrs[k].shape}, expected {shapes[k].shape}")
+        st = vemb_dense_state(int(state.get("t", 0)), *[_ptr(arrs.get(k)) for k in _DENSE_KEYS])
+        _check(lib().vemb_dense_set_state(self.h, ctypes.byref(st)))
+
+    def close(self):
+        if self.h:
+            lib().vemb_dense_destroy(self.h)
             self.h = None
 
     def __del__(self):

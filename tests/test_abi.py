@@ -66,3 +66,23 @@ def test_null_arguments():
     assert lib.vemb_batch_step(None, 1) == -1
     assert lib.vemb_batch_dual_bounds(None, None, None) == -1
     lib.vemb_batch_destroy(None)  # no-op
+
+
+def test_dense_specs_are_rejected_before_device_work():
+    null = vemb.ctypes.c_void_p(None)
+    assert _err(lambda: vemb.Dense(TFI, (8, 1), (3, 1), stream=null)) == -1  # does not tile
+    assert _err(lambda: vemb.Dense(TFI, (4, 1), (4, 1), stream=null)) == -2  # one cluster
+    # K = M n_op = 8 * 64 above the largest dense eigensolve
+    assert _err(lambda: vemb.Dense(TFI, (24, 1), (3, 1), stream=null)) == -2
+    # fields: Y is not real, coefficients must be finite
+    assert _err(lambda: vemb.Dense(TFI, (8, 1), (2, 1), fields=[("Y", (0, 0), 1.0)], stream=null)) == -2
+    assert _err(lambda: vemb.Dense(TFI, (8, 1), (2, 1), fields=[("X", (0, 0), float("nan"))], stream=null)) == -1
+    lib = vemb.lib()
+    assert lib.vemb_dense_create(None, None, None, None, 0, None, None, None) == -1
+    assert lib.vemb_dense_step(None, 1) == -1
+    assert lib.vemb_dense_dual_bound(None, None) == -1
+    assert lib.vemb_dense_primal_energy(None, None, None) == -1
+    assert lib.vemb_dense_get_state(None, None) == -1
+    assert lib.vemb_dense_set_state(None, None) == -1
+    assert lib.vemb_dense_last_sweeps(None, None, None) == -1
+    lib.vemb_dense_destroy(None)  # no-op
