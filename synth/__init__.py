@@ -231,3 +231,19 @@ N_FEATURES = 7
 def mlp_batch(n_in: int, batch: int, tag: int = 0) -> np.ndarray:
     """Seeded FP32 inputs for network parity tests."""
     return np.random.default_rng([BASE_SEED, 14, tag]).standard_normal((batch, n_in)).astype(np.float32)
+
+
+def disorder_fields(w: Workload, scale: float, letters=("X",), tag: int = 0) -> list:
+    """Random one-site fields (letter, (x, y), coeff) with coeff ~ U[-scale, scale] on every site
+    of the workload's lattice, one per letter: the disordered instances of the dense solver."""
+    rng = np.random.default_rng([BASE_SEED, 29, tag])
+    return [(letter, (x, y), float(scale * rng.uniform(-1.0, 1.0)))
+            for x in range(w.extent[0]) for y in range(w.extent[1]) for letter in letters]
+
+
+def dense_bench() -> tuple:
+    """Dense (non-invariant) benchmark instance: TFI ring N = 32, J = 1, h = 1, 2-site clusters
+    (M = 16, 120 pair marginals 16 x 16, dense X 256 x 256), random transverse fields
+    U[-0.5, 0.5] added site by site."""
+    w = tfi_ring(32, 2, 1.0, "complete", 2000, "dense_ring32_L2")
+    return w, disorder_fields(w, 0.5, ("X",), tag=1)
