@@ -45,20 +45,26 @@ from .model import Geometry, local_hamiltonians
 class Problem:
     """Fixed data of one instance: geometry, local Hamiltonians, operator maps, parameters."""
 
-    def __init__(self, terms, extent, cluster, opset="complete", mu=10.0, nu=10.0, eps=2.0):
+    def __init__(self, terms, extent, cluster, opset="complete", mu=10.0, nu=10.0, eps=2.0, fermionic=False):
         self.geom = Geometry(tuple(extent), tuple(cluster))
         g = self.geom
         self.M, self.L, self.m, self.n = g.M, g.L, g.m, g.n
         self.Mx, self.My = g.Mx, g.My
         self.P = self.M - 1
-        self.H0, self.Hd = local_hamiltonians(terms, g)
-        self.maps = OperatorMaps(opset, g.L)
+        self.fermionic = bool(fermionic)
+        if self.fermionic:
+            from .fermion import local_hamiltonians as fermion_hamiltonians
+
+            self.H0, self.Hd = fermion_hamiltonians(terms, g)
+        else:
+            self.H0, self.Hd = local_hamiltonians(terms, g)
+        self.maps = OperatorMaps(opset, g.L, self.fermionic)
         self.n_op = self.maps.n_op
         self.mu, self.nu, self.eps = float(mu), float(nu), float(eps)
 
     @classmethod
     def from_workload(cls, w):
-        return cls(w.terms, w.extent, w.cluster, w.opset, w.mu, w.nu, w.eps)
+        return cls(w.terms, w.extent, w.cluster, w.opset, w.mu, w.nu, w.eps, getattr(w, "fermionic", False))
 
 
 @dataclass

@@ -131,19 +131,28 @@ def Rd_complete(Xd, m):
 
 
 class OperatorMaps:
-    """G blocks and effective-Hamiltonian corrections for one operator collection."""
+    """G blocks and effective-Hamiltonian corrections for one operator collection.  fermionic:
+    the off-diagonal blocks carry the Jordan-Wigner parity signs of the appendix on fermions
+    (complete collection only; see ``oracle.fermion``)."""
 
-    def __init__(self, opset: str, L: int):
+    def __init__(self, opset: str, L: int, fermionic: bool = False):
         self.opset = opset
         self.L = L
         self.m = 2 ** L
         self.ops = operator_collection(opset, L)
         self.n_op = self.ops.shape[0]
+        self.fermionic = bool(fermionic)
+        if self.fermionic and opset != "complete":
+            raise ValueError("fermionic problems use the complete operator collection")
 
     def G0(self, rho0):
         return G0_complete(rho0, self.m) if self.opset == "complete" else G0_generic(rho0, self.ops)
 
     def Gd(self, rho):
+        if self.fermionic:
+            from .fermion import Gd_complete as fermion_gd
+
+            return fermion_gd(rho, self.m)
         if self.opset == "complete":
             return Gd_complete(rho, self.m)
         if rho.ndim == 2:
@@ -154,6 +163,10 @@ class OperatorMaps:
         return C0_complete(X0, self.m) if self.opset == "complete" else C0_generic(X0, self.ops)
 
     def Rd(self, Xd):
+        if self.fermionic:
+            from .fermion import Rd_complete as fermion_rd
+
+            return fermion_rd(Xd, self.m)
         if self.opset == "complete":
             return Rd_complete(Xd, self.m)
         if Xd.ndim == 2:

@@ -13,7 +13,13 @@ A term is ``(coeff, ((pauli, (ox, oy)), ...))``: a real coefficient times a
 product of Pauli letters ``"X" | "Y" | "Z"`` placed at site offsets ``(ox, oy)``
 relative to a lattice origin.  The Hamiltonian is the sum of every term
 translated to every lattice site (periodic boundary conditions).
+
+Fermionic models (spinless fermions, appendix on fermions) use the letter
+``"F"``: a two-site term ``(t, (("F", o1), ("F", o2)))`` is the hopping
+``t (a_i^dag a_j + a_j^dag a_i)`` between the sites at o1 and o2, and
+``"Z"`` stands for 1 - 2 n (so (n_i - 1/2)(n_j - 1/2) = Z_i Z_j / 4).
 """
+
 from __future__ import annotations
 
 from dataclasses import dataclass, field
@@ -50,6 +56,32 @@ def afh_terms(ndim: int = 1) -> list:
     return xxz_terms(1.0, ndim)
 
 
+def sf_terms(U: float, ndim: int = 1) -> list:
+    """Spinless fermions (eq. spinlessFerm): sum over nearest-neighbour bonds of
+    -(a_i^dag a_j + a_j^dag a_i) + U (n_i - 1/2)(n_j - 1/2)."""
+    bonds = [(1, 0)] + ([(0, 1)] if ndim == 2 else [])
+    terms = []
+    for b in bonds:
+        terms.append((-1.0, (("F", (0, 0)), ("F", b))))
+        terms.append((0.25 * float(U), (("Z", (0, 0)), ("Z", b))))
+    return terms
+
+
+def lrsf_terms(U: float, N: int) -> list:
+    """Long-range spinless fermions on a ring of N sites (eq. spinlessFermLR): nearest-neighbour
+    hopping plus U sum over ordered pairs i != j of (n_i - 1/2)(n_j - 1/2) / d(i, j), d the
+    periodic (minimum-image) distance.  Each unordered pair at distance r carries 2U/r; the term
+    at offset r translated to every site meets each such pair once (twice for r = N/2, whose
+    coefficient is halved)."""
+    terms = [(-1.0, (("F", (0, 0)), ("F", (1, 0))))]
+    for r in range(1, N // 2 + 1):
+        c = 2.0 * float(U) / r * 0.25
+        if 2 * r == N:
+            c *= 0.5
+        terms.append((c, (("Z", (0, 0)), ("Z", (r, 0)))))
+    return terms
+
+
 @dataclass(frozen=True)
 class Workload:
     """One solver instance: model terms on an Nx x Ny torus tiled by Lx x Ly clusters."""
@@ -64,6 +96,7 @@ class Workload:
     nu: float = 10.0
     eps: float = 2.0
     meta: dict = field(default_factory=dict, compare=False, hash=False)
+    fermionic: bool = False  # "F" hopping terms; pair operators Jordan-Wigner ordered per cluster pair
 
     @property
     def ndim(self) -> int:
@@ -103,6 +136,19 @@ def xxz_ring(N: int, L: int, Jz: float, opset: str = "complete", iters: int = 20
 def tfi_torus(Nx: int, Ny: int, Lx: int, Ly: int, h: float, iters: int = 2000, name=None) -> Workload:
     return Workload(name or f"tfi_torus_{Nx}x{Ny}_{Lx}x{Ly}_h{h}", tuple(tfi_terms(h, 1.0, 2)),
                     (Nx, Ny), (Lx, Ly), "complete", iters, meta={"model": "tfi", "h": h, "Jz": 0.0})
+
+
+def sf_ring(N: int, L: int, U: float, iters: int = 2000, name=None, long_range: bool = False) -> Workload:
+    """Spinless fermions (short- or long-range density interaction) on a ring of N sites."""
+    terms = lrsf_terms(U, N) if long_range else sf_terms(U, 1)
+    tag = "lrsf" if long_range else "sf"
+    return Workload(name or f"{tag}_ring_N{N}_L{L}_U{U}", tuple(terms), (N, 1), (L, 1), "complete", iters,
+                    meta={"model": tag, "U": U}, fermionic=True)
+
+
+def sf_torus(Nx: int, Ny: int, Lx: int, Ly: int, U: float, iters: int = 2000, name=None) -> Workload:
+    return Workload(name or f"sf_torus_{Nx}x{Ny}_{Lx}x{Ly}_U{U}", tuple(sf_terms(U, 2)), (Nx, Ny), (Lx, Ly),
+                    "complete", iters, meta={"model": "sf", "U": U}, fermionic=True)
 
 
 def afh_torus(Nx: int, Ny: int, Lx: int, Ly: int, iters: int = 2000, name=None) -> Workload:
