@@ -50,11 +50,19 @@ enum vemb_status {
   VEMB_E_NOCONV = -7        /* an eigensolver reached its sweep cap (result still written) */
 };
 
-enum vemb_pauli { VEMB_I = 0, VEMB_X = 1, VEMB_Y = 2, VEMB_Z = 3 };
+/* VEMB_FHOP marks the two ends of a fermionic hopping (fermionic problems only). */
+enum vemb_pauli { VEMB_I = 0, VEMB_X = 1, VEMB_Y = 2, VEMB_Z = 3, VEMB_FHOP = 4 };
 
 /* One translation-invariant term: coeff * prod_s pauli[s] at site origin + offset[s].
  * nsites is 1 or 2 (pairwise Hamiltonians, Section 2.1).  The product must be
- * real (an even number of Y factors), as the paper treats the real case. */
+ * real (an even number of Y factors), as the paper treats the real case.
+ * Fermionic problems (vemb_options.fermionic = 1; spinless fermions of the
+ * appendix on fermions): a two-site term with pauli = {VEMB_FHOP, VEMB_FHOP} is
+ * coeff (a_i^dag a_j + a_j^dag a_i) between its two sites, and VEMB_Z stands for
+ * 1 - 2 n (so (n_i - 1/2)(n_j - 1/2) = Z_i Z_j / 4); X and Y are rejected.  Each
+ * cluster uses the Jordan-Wigner order of its local sites, each cluster pair the
+ * order (first cluster's sites, then the second's), cluster 0 first for the
+ * offsets d; occupied = |1>. */
 typedef struct {
   double coeff;
   int32_t nsites;
@@ -98,6 +106,11 @@ typedef struct {
                            wavefronts, 128 = 4-column blocks on 8 wavefronts (blocks move
                            through LDS once per block round); other sizes then use 256.
                            0 = chosen by the autotuner (vemb_tuned_threads). */
+  int32_t fermionic;    /* 1: spinless fermions (appendix on fermions): VEMB_FHOP terms, and the
+                           off-diagonal G blocks and pair corrections of eq. effHam take the
+                           Jordan-Wigner parity sign of the pair order (an odd operator of the
+                           second cluster carries the first cluster's parity).  Needs
+                           VEMB_OPSET_COMPLETE.  0 (default): spins. */
 } vemb_options;
 
 typedef struct vemb_problem vemb_problem;

@@ -323,7 +323,7 @@ int vemb_create_problem(const vemb_hamiltonian* H, const vemb_lattice* lat, cons
   p->opt = o;
   p->stream = static_cast<hipStream_t>(hip_stream);
   std::string err;
-  int rc = build_model(*H, g, p->host, err);
+  int rc = build_model(*H, g, p->host, err, o.fermionic != 0);
   if (rc != VEMB_OK) {
     delete p;  // nothing on the device yet
     return fail(rc, err);
@@ -341,6 +341,7 @@ int vemb_create_problem(const vemb_hamiltonian* H, const vemb_lattice* lat, cons
   a.n_op = k;
   a.Ku = Ku;
   a.opset = o.opset;
+  a.fermionic = o.fermionic;
   a.mu = o.mu;
   a.nu = o.nu;
   a.eps = o.eps;

@@ -91,6 +91,14 @@ template <> struct convert<cplx<double>, cplx<float>> {
 // Operator-collection tables for PAULI1 (signed permutations, Section 2.2):
 // O_alpha[u][v] = sign[alpha][u] / sqrt(m) when v = perm[alpha][u], else 0.
 // ---------------------------------------------------------------------------
+// Jordan-Wigner parity sign of fermionic pair blocks (complete collection): an odd matrix
+// unit E_ce of the second cluster (popcount(c) + popcount(e) odd), taken to the pair's
+// order, carries the first cluster's parity string, which multiplies the unit E_ba of the
+// first cluster by (-1)^popcount(a).
+__device__ inline double jw_sign(int a, int c, int e) {
+  return (((__popc(c) + __popc(e)) & __popc(a)) & 1) ? -1.0 : 1.0;
+}
+
 constexpr int kMaxOps = 12;  // 3 L for L <= 4
 constexpr int kMaxM = 16;
 

@@ -11,6 +11,7 @@ struct DenseArgs {
   int ld;                // row stride of X and X' (K, or K rounded up for the streamed eigensolver;
                          // rows and columns K..ld-1 stay zero, which the projection preserves)
   int opset;
+  int fermionic;             // 1: Jordan-Wigner parity signs on the pair blocks (complete collection)
   double mu, nu, eps, sign;  // sign = -1 for X - eps G
   double a, b, c;            // closed-form inverse coefficients of the pair system
   const int2* pairs;         // Q cluster pairs (i, j), i < j

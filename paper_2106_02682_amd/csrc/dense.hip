@@ -17,7 +17,10 @@ constexpr int kBlock = 256;
 __device__ double rx_dense(const DenseArgs& A, const double* Xd, int x, int y, int xp, int yp) {
   const int m = A.m;
   const long ld = A.ld;
-  if (A.opset == VEMB_OPSET_COMPLETE) return Xd[(long)(xp * m + x) * ld + (y * m + yp)];
+  if (A.opset == VEMB_OPSET_COMPLETE) {
+    const double v = Xd[(long)(xp * m + x) * ld + (y * m + yp)];
+    return A.fermionic ? jw_sign(xp, y, yp) * v : v;
+  }
   // (1/m) sum_ab X_ab [x = perm_a(x')] sgn_a(x') [y' = perm_b(y)] sgn_b(y)
   const OpTables& T = *A.ops;
   double acc = 0.0;
@@ -230,6 +233,7 @@ __global__ void __launch_bounds__(kBlock) dense_xstep_kernel(DenseArgs A) {
   if (A.opset == VEMB_OPSET_COMPLETE) {
     const int aa = al / m, bb = al % m, cc = be / m, ee = be % m;
     g = rho[(long)(aa * m + ee) * n + (bb * m + cc)];
+    if (A.fermionic) g *= jw_sign(aa, cc, ee);
   } else {
     const OpTables& T = *A.ops;
     double acc = 0.0;

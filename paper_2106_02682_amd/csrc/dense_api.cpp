@@ -116,12 +116,14 @@ int vemb_dense_create(const vemb_hamiltonian* H, const vemb_lattice* lat, const 
   if (n > 256) return fail(VEMB_E_UNSUPPORTED, "pair matrices above 256 x 256 are not supported");
   const int ld = K <= 64 ? K : (K + 31) / 32 * 32;
   HostModel host;
-  rc = build_model(*H, g, host, err);
+  rc = build_model(*H, g, host, err, o.fermionic != 0);
   if (rc != VEMB_OK) return fail(rc, err);
   std::vector<double> Hc((size_t)M * m * m);
   for (int c = 0; c < M; ++c)
     for (size_t e = 0; e < (size_t)m * m; ++e) Hc[(size_t)c * m * m + e] = host.H0[e];
   for (int f = 0; f < nfields; ++f) {
+    if (o.fermionic && fields[f].pauli != VEMB_Z)
+      return fail(VEMB_E_UNSUPPORTED, "field " + std::to_string(f) + ": fermionic fields are Z (1 - 2n)");
     rc = add_site_field(g, fields[f].x, fields[f].y, fields[f].pauli, fields[f].coeff, Hc, err);
     if (rc != VEMB_OK) return fail(rc, "field " + std::to_string(f) + ": " + err);
   }
@@ -154,6 +156,7 @@ int vemb_dense_create(const vemb_hamiltonian* H, const vemb_lattice* lat, const 
   a.K = K;
   a.ld = ld;
   a.opset = o.opset;
+  a.fermionic = o.fermionic;
   a.mu = o.mu;
   a.nu = o.nu;
   a.eps = o.eps;

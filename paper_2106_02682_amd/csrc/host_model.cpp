@@ -57,6 +57,26 @@ std::vector<cd> kron(const std::vector<cd>& A, const std::vector<cd>& B, int m) 
   return out;
 }
 
+// coeff (a_p^dag a_q + a_q^dag a_p) on `nsites` sites in Jordan-Wigner order (site 0 the most
+// significant bit, occupied = 1), added to the dim x dim matrix H: the hopping moves a particle
+// between q and p with the sign (-1)^(number of occupied sites strictly between them).
+void add_hopping(std::vector<cd>& H, int nsites, int p, int q, double coeff) {
+  const int dim = 1 << nsites;
+  const int bp = 1 << (nsites - 1 - p), bq = 1 << (nsites - 1 - q);
+  const int lo = p < q ? p : q, hi = p < q ? q : p;
+  int between = 0;
+  for (int k = lo + 1; k < hi; ++k) between |= 1 << (nsites - 1 - k);
+  for (int u = 0; u < dim; ++u) {
+    for (int dir = 0; dir < 2; ++dir) {  // a_p^dag a_q, then a_q^dag a_p
+      const int from = dir == 0 ? bq : bp, to = dir == 0 ? bp : bq;
+      if (!(u & from) || (u & to)) continue;
+      const double sign = (__builtin_popcount(u & between) & 1) ? -1.0 : 1.0;
+      const int r = u ^ from ^ to;
+      H[(size_t)r * dim + u] += coeff * sign;
+    }
+  }
+}
+
 }  // namespace
 
 int normalize_options(const vemb_options* in, vemb_options& o, std::string& err) {
@@ -68,6 +88,9 @@ int normalize_options(const vemb_options* in, vemb_options& o, std::string& err)
   if (!(o.mu > 0 && o.nu > 0 && o.eps > 0)) return err = "mu, nu, eps must be positive", VEMB_E_INVALID;
   if (o.opset != VEMB_OPSET_COMPLETE && o.opset != VEMB_OPSET_PAULI1) return err = "unknown opset", VEMB_E_INVALID;
   if (o.precision < VEMB_FP64 || o.precision > VEMB_FP32) return err = "unknown precision", VEMB_E_INVALID;
+  if (o.fermionic != 0 && o.fermionic != 1) return err = "fermionic must be 0 or 1", VEMB_E_INVALID;
+  if (o.fermionic && o.opset != VEMB_OPSET_COMPLETE)
+    return err = "fermionic problems use the complete operator collection", VEMB_E_UNSUPPORTED;
   return VEMB_OK;
 }
 
@@ -94,7 +117,7 @@ int parse_geometry(const vemb_lattice& lat, const vemb_clusters& cl, Geometry& g
   return VEMB_OK;
 }
 
-int build_model(const vemb_hamiltonian& H, const Geometry& g, HostModel& out, std::string& err) {
+int build_model(const vemb_hamiltonian& H, const Geometry& g, HostModel& out, std::string& err, bool fermionic) {
   const int L = g.L, m = g.m, n = g.n, M = g.M;
   std::vector<cd> H0((size_t)m * m, cd(0, 0));
   std::vector<std::vector<cd>> Hd(M);
@@ -105,10 +128,25 @@ int build_model(const vemb_hamiltonian& H, const Geometry& g, HostModel& out, st
       return VEMB_E_UNSUPPORTED;
     }
     for (int s = 0; s < term.nsites; ++s)
-      if (term.pauli[s] < 0 || term.pauli[s] > 3) {
+      if (term.pauli[s] < 0 || term.pauli[s] > VEMB_FHOP) {
         err = "Pauli letter out of range";
         return VEMB_E_INVALID;
       }
+    const bool hop = term.nsites == 2 && term.pauli[0] == VEMB_FHOP && term.pauli[1] == VEMB_FHOP;
+    if (!hop && (term.pauli[0] == VEMB_FHOP || (term.nsites == 2 && term.pauli[1] == VEMB_FHOP))) {
+      err = "a hopping term has two VEMB_FHOP ends";
+      return VEMB_E_INVALID;
+    }
+    if (hop && !fermionic) {
+      err = "hopping terms need a fermionic problem (vemb_options.fermionic = 1)";
+      return VEMB_E_INVALID;
+    }
+    if (fermionic && !hop)
+      for (int s = 0; s < term.nsites; ++s)
+        if (term.pauli[s] == VEMB_X || term.pauli[s] == VEMB_Y) {
+          err = "fermionic problems take hoppings and Z (1 - 2n) letters only";
+          return VEMB_E_UNSUPPORTED;
+        }
     for (int x = 0; x < g.Nx; ++x)
       for (int y = 0; y < g.Ny; ++y) {
         int cl[2], loc[2], site[2];
@@ -125,7 +163,16 @@ int build_model(const vemb_hamiltonian& H, const Geometry& g, HostModel& out, st
         }
         const bool touches0 = cl[0] == 0 || (term.nsites == 2 && cl[1] == 0);
         if (!touches0) continue;
-        if (term.nsites == 1 || cl[0] == cl[1]) {
+        if (hop && cl[0] == cl[1]) {
+          // hopping inside cluster 0, in the cluster's Jordan-Wigner order
+          add_hopping(H0, L, loc[0], loc[1], term.coeff);
+        } else if (hop) {
+          // hopping between cluster 0 and cluster d, in the pair's order (cluster 0 first)
+          const int s0 = cl[0] == 0 ? 0 : 1;
+          const int d = cl[1 - s0];
+          if (Hd[d].empty()) Hd[d].assign((size_t)n * n, cd(0, 0));
+          add_hopping(Hd[d], 2 * L, loc[s0], L + loc[1 - s0], term.coeff);
+        } else if (term.nsites == 1 || cl[0] == cl[1]) {
           // both factors inside cluster 0: product of single-site operators
           std::vector<int> letters(L, VEMB_I);
           std::vector<cd> op;

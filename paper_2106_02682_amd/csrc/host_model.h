@@ -23,7 +23,8 @@ struct HostModel {
 int normalize_options(const vemb_options* in, vemb_options& o, std::string& err);
 // Periodic lattice tiled by clusters of at most 4 sites, at least two clusters.
 int parse_geometry(const vemb_lattice& lat, const vemb_clusters& cl, Geometry& g, std::string& err);
-int build_model(const vemb_hamiltonian& H, const Geometry& g, HostModel& out, std::string& err);
+// fermionic: VEMB_FHOP hoppings allowed (Jordan-Wigner order per cluster and per pair), X / Y rejected.
+int build_model(const vemb_hamiltonian& H, const Geometry& g, HostModel& out, std::string& err, bool fermionic = false);
 void build_pauli1_tables(int L, OpTables& T);
 // Adds coeff * (Pauli `pauli` at lattice site (x, y)) to the Hamiltonian of the cluster
 // holding that site: Hc is M x m x m.  Real one-site operators only (X, Z).

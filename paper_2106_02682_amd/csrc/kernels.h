@@ -77,6 +77,7 @@ struct StepArgs {
   // sizes
   int M, P, m, n, n_op, Ku;
   int opset;
+  int fermionic;             // 1: Jordan-Wigner parity signs on the pair blocks (complete collection)
   double mu, nu, eps, sign;  // sign = -1 for X - eps G
   double a, b, c;            // closed-form inverse coefficients
   // fixed data

@@ -10,7 +10,8 @@
 //   R(X)_(x,y),(x',y') = X_(x',x),(y,y')   (pair correction of eq. effHam)
 //   G_0d(rho)_(a,b),(c,e) = rho_(a,e),(b,c) (realignment)
 //   C_0(X)_(b,e) = sum_a X_(a,b),(a,e);  G_00(rho0)_(a,b),(c,e) = delta_ac rho0_(e,b).
-// The single-site Pauli collection uses signed-permutation tables instead.
+// The single-site Pauli collection uses signed-permutation tables instead.  Fermionic problems
+// (appendix on fermions) multiply the pair entries by the Jordan-Wigner parity sign jw_sign.
 #include "kernels.h"
 
 namespace vemb {
@@ -35,7 +36,10 @@ __device__ double rx_generic(const double* X, const OpTables& T, int m, int x, i
 
 __device__ inline double rx_value(const StepArgs& A, const double* Xd, int x, int y, int xp, int yp) {
   const int m = A.m;
-  if (A.opset == VEMB_OPSET_COMPLETE) return Xd[(size_t)(xp * m + x) * A.n_op + (y * m + yp)];
+  if (A.opset == VEMB_OPSET_COMPLETE) {
+    const double v = Xd[(size_t)(xp * m + x) * A.n_op + (y * m + yp)];
+    return A.fermionic ? jw_sign(xp, y, yp) * v : v;
+  }
   return rx_generic(Xd, *A.ops, m, x, y, xp, yp);
 }
 
@@ -137,6 +141,7 @@ __device__ void pair_xstep_body(const StepArgs& A, int bx, int by) {
     const int al = e / k, be = e % k;
     const int aa = al / m, bb = al % m, cc = be / m, ee = be % m;
     g = rho[(size_t)(aa * m + ee) * n + (bb * m + cc)];
+    if (A.fermionic) g *= jw_sign(aa, cc, ee);
   } else {
     // G_ab = (1/m) sum_{x', y} sgn_a(x') sgn_b(y) rho_(x', perm_b(y)),(perm_a(x'), y)
     const OpTables& T = *A.ops;

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libvemb.so")
 VEMB_OK = 0
 STATUS = {0: "VEMB_OK", -1: "VEMB_E_INVALID", -2: "VEMB_E_UNSUPPORTED", -3: "VEMB_E_NOMEM", -4: "VEMB_E_HIP",
           -5: "VEMB_E_NUMERIC", -6: "VEMB_E_DIVERGED", -7: "VEMB_E_NOCONV"}
-PAULI = {"I": 0, "X": 1, "Y": 2, "Z": 3}
+PAULI = {"I": 0, "X": 1, "Y": 2, "Z": 3, "F": 4}  # "F": an end of a fermionic hopping
 OPSET = {"complete": 0, "pauli1": 1}
 PRECISION = {"fp64": 0, "mixed": 1, "fp32": 2}
 RHO, RHO_TILDE = 0, 1
@@ -68,7 +68,8 @@ class vemb_clusters(ctypes.Structure):
 class vemb_options(ctypes.Structure):
     _fields_ = [("mu", ctypes.c_double), ("nu", ctypes.c_double), ("eps", ctypes.c_double),
                 ("opset", ctypes.c_int32), ("precision", ctypes.c_int32), ("max_sweeps", ctypes.c_int32),
-                ("sign", ctypes.c_int32), ("warm_refresh", ctypes.c_int32), ("tpb", ctypes.c_int32)]
+                ("sign", ctypes.c_int32), ("warm_refresh", ctypes.c_int32), ("tpb", ctypes.c_int32),
+                ("fermionic", ctypes.c_int32)]
 
 
 class vemb_info(ctypes.Structure):
@@ -220,7 +221,8 @@ def default_options():
     return o
 
 
-def _marshal(terms, extent, cluster, opset, precision, mu, nu, eps, max_sweeps, sign, warm_refresh, tpb):
+def _marshal(terms, extent, cluster, opset, precision, mu, nu, eps, max_sweeps, sign, warm_refresh, tpb,
+             fermionic=False):
     """ctypes structs of a term list (``synth`` format: (coeff, ((pauli, (ox, oy)), ...))), lattice,
     clusters and options; the term array is returned too, to stay alive with the Hamiltonian."""
     arr = (vemb_term * max(1, len(terms)))()
@@ -243,14 +245,16 @@ def _marshal(terms, extent, cluster, opset, precision, mu, nu, eps, max_sweeps, 
     o.sign = sign
     o.warm_refresh = warm_refresh
     o.tpb = tpb
+    o.fermionic = 1 if fermionic else 0
     return H, lat, cl, o, arr
 
 
 def create_problem(terms, extent, cluster, opset="complete", precision="fp64", mu=10.0, nu=10.0, eps=2.0,
-                   max_sweeps=40, sign=-1, warm_refresh=64, tpb=0, stream=None):
-    """Terms in the ``synth`` format: (coeff, ((pauli, (ox, oy)), ...))."""
+                   max_sweeps=40, sign=-1, warm_refresh=64, tpb=0, stream=None, fermionic=False):
+    """Terms in the ``synth`` format: (coeff, ((pauli, (ox, oy)), ...)); "F" letters are the ends of a
+    fermionic hopping (fermionic problems)."""
     H, lat, cl, o, _keep = _marshal(terms, extent, cluster, opset, precision, mu, nu, eps, max_sweeps, sign,
-                                    warm_refresh, tpb)
+                                    warm_refresh, tpb, fermionic)
     h = ctypes.c_void_p()
     st = stream if stream is not None else current_stream()
     _check(lib().vemb_create_problem(ctypes.byref(H), ctypes.byref(lat), ctypes.byref(cl), ctypes.byref(o), st,
@@ -425,6 +429,7 @@ class Problem:
 
     @classmethod
     def from_workload(cls, w, **kw):
+        kw.setdefault("fermionic", getattr(w, "fermionic", False))
         kw.setdefault("opset", w.opset)
         kw.setdefault("mu", w.mu)
         kw.setdefault("nu", w.nu)
@@ -666,9 +671,9 @@ class Dense:
     Pairs (i, j), i < j, in lexicographic order; state arrays are stacked in that order."""
 
     def __init__(self, terms, extent, cluster, fields=(), opset="complete", precision="fp64", mu=10.0, nu=10.0,
-                 eps=2.0, max_sweeps=40, sign=-1, warm_refresh=64, tpb=0, stream=None):
+                 eps=2.0, max_sweeps=40, sign=-1, warm_refresh=64, tpb=0, stream=None, fermionic=False):
         H, lat, cl, o, keep = _marshal(terms, extent, cluster, opset, precision, mu, nu, eps, max_sweeps, sign,
-                                       warm_refresh, tpb)
+                                       warm_refresh, tpb, fermionic)
         fields = list(fields)
         farr = (vemb_site_field * max(1, len(fields)))()
         for f, (letter, (x, y), coeff) in enumerate(fields):
@@ -685,6 +690,7 @@ class Dense:
 
     @classmethod
     def from_workload(cls, w, fields=(), **kw):
+        kw.setdefault("fermionic", getattr(w, "fermionic", False))
         kw.setdefault("opset", w.opset)
         kw.setdefault("mu", w.mu)
         kw.setdefault("nu", w.nu)

@@ -86,3 +86,18 @@ def test_dense_specs_are_rejected_before_device_work():
     assert lib.vemb_dense_set_state(None, None) == -1
     assert lib.vemb_dense_last_sweeps(None, None, None) == -1
     lib.vemb_dense_destroy(None)  # no-op
+
+
+def test_fermionic_specs_are_rejected_before_device_work():
+    null = vemb.ctypes.c_void_p(None)
+    hop = [(-1.0, (("F", (0, 0)), ("F", (1, 0))))]
+    # hopping terms need a fermionic problem; fermionic problems need the complete collection
+    assert _err(lambda: vemb.create_problem(hop, (8, 1), (2, 1), stream=null)) == -1
+    assert _err(lambda: vemb.create_problem(hop, (8, 1), (2, 1), opset="pauli1", fermionic=True, stream=null)) == -2
+    # X / Y letters have no fermionic meaning here; a lone hopping end is malformed
+    assert _err(lambda: vemb.create_problem(hop + TFI[:1], (8, 1), (2, 1), fermionic=True, stream=null)) == -2
+    assert _err(lambda: vemb.create_problem([(1.0, (("F", (0, 0)),))], (8, 1), (2, 1), fermionic=True,
+                                            stream=null)) == -1
+    # dense: fermionic fields are Z only
+    assert _err(lambda: vemb.Dense(hop, (8, 1), (2, 1), fields=[("X", (0, 0), 0.3)], fermionic=True,
+                                   stream=null)) == -2

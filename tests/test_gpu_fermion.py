@@ -1,0 +1,123 @@
+"""Spinless fermions (appendix on fermions) on the GPU against the FP64 fermionic oracle, through
+the C ABI: Jordan-Wigner pair Hamiltonians built by the library, parity-signed G blocks and pair
+corrections in the iteration, the bound and the energy.
+
+* iterates element by element after a few iterations: short-range rings (2- and 3-site clusters,
+  the latter with 64 x 64 pair blocks), the long-range model (every pair Hamiltonian nonzero), a
+  2-D torus, and the dense Algorithm 5 with a random potential (Z fields);
+* fermionic and spin problems stepped together in one batch give their single-problem iterates;
+* at U = 0 on the 20 x 1 ring of the paper's fermion benchmark the energy reaches the
+  free-fermion ground-state energy (the relaxation is exact there), and at U = 1 every bound lies
+  below the exact energy of a 12-site ring.
+FP64 tolerances: 1e-9 relative on state arrays, 1e-10 on the bound and the energy.
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import alg5, alg6, fermion as F
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def vemb():
+    if not torch.cuda.is_available():
+        pytest.fail("gpu tests need a GPU")
+    from paper_2106_02682_amd import vemb as v
+
+    v.lib()
+    return v
+
+
+def _compare(got, want, tol):
+    for k, ref in want.items():
+        err = np.abs(got[k] - ref).max()
+        scale = max(1.0, np.abs(ref).max())
+        assert err <= tol * scale, f"{k}: max error {err:.3e}"
+
+
+CASES = [synth.sf_ring(8, 2, 1.0), synth.sf_ring(12, 3, 2.0), synth.sf_ring(12, 2, 1.5, long_range=True),
+         synth.sf_torus(4, 4, 2, 1, 1.0), synth.sf_ring(10, 2, 0.0)]
+
+
+@pytest.mark.parametrize("w", CASES, ids=lambda w: w.name)
+def test_iterates_match_oracle(vemb, w):
+    p = alg6.Problem.from_workload(w)
+    s, _ = alg6.solve(p, 5)
+    print(f"{w.name}: M {p.M}, pairs {p.P} of {p.n}", flush=True)
+    with vemb.Problem.from_workload(w) as g:
+        g.step(5)
+        st = g.get_state()
+        lb = g.dual_bound()
+        e, feas = g.primal_energy()
+    _compare(st, {"X": s.X, "rho0": s.rho0, "rho": s.rho, "rho_t": s.rho_t, "Lam": s.Lam, "Lam1": s.Lam1,
+                  "Lam2": s.Lam2}, 1e-9)
+    lb_o = alg6.lower_bound(p, s)
+    assert abs(lb - lb_o) <= 1e-10 * max(1.0, abs(lb_o))
+    assert abs(e - alg6.energy_per_site(p, s)) <= 1e-10 * max(1.0, abs(e))
+    assert abs(feas - alg6.feasibility_error(p, s)) <= 1e-9 * max(1.0, feas)
+
+
+def test_dense_with_potential_matches_oracle(vemb):
+    w = synth.sf_ring(10, 2, 1.0)
+    f = synth.disorder_fields(w, 0.6, ("Z",), tag=7)
+    dp = alg5.DenseProblem(alg6.Problem.from_workload(w), f)
+    st = alg5.initial_dense(dp)
+    for _ in range(4):
+        st = alg5.dense_step(dp, st)
+    with vemb.Dense.from_workload(w, fields=f) as g:
+        g.step(4)
+        got = g.get_state()
+        lb = g.dual_bound()
+        e, _ = g.primal_energy()
+    M = dp.p.M
+    want = {"X": st["X"], "rho0": np.stack([st["rho"][i] for i in range(M)]),
+            "rho": np.stack([st["rho_p"][q] for q in dp.pairs]), "Lam1": np.stack([st["Lam1"][q] for q in dp.pairs]),
+            "Lam": np.stack([st["Lam"][q] for q in dp.pairs])}
+    _compare(got, want, 1e-9)
+    assert abs(lb - alg5.lower_bound_dense(dp, st)) <= 1e-10 * abs(lb)
+    assert abs(e - alg5.energy_dense(dp, st)) <= 1e-10 * max(1.0, abs(e))
+
+
+def test_batch_mixes_fermions_and_spins(vemb):
+    ws = [synth.sf_ring(12, 3, 1.0), synth.tfi_ring(12, 3, 1.0), synth.sf_ring(8, 2, 0.5, long_range=True)]
+    singles = []
+    for w in ws:
+        with vemb.Problem.from_workload(w) as g:
+            g.step(12)
+            singles.append(g.get_state())
+    probs = [vemb.Problem.from_workload(w) for w in ws]
+    with vemb.Batch(probs) as b:
+        b.step(12)
+        b.sync()
+        got = [p.get_state() for p in probs]
+    for p in probs:
+        p.close()
+    for a, s in zip(got, singles):
+        _compare(a, {k: s[k] for k in ("X", "rho0", "rho_t", "Lam", "Lam1", "Lam2")}, 1e-11)
+
+
+def test_free_fermions_exact_on_paper_lattice(vemb):
+    """20 x 1 ring, 2-site clusters, U = 0: the energy reaches the free-fermion value."""
+    w = synth.sf_ring(20, 2, 0.0)
+    e0 = F.free_fermion_energy(w.terms, w.extent) / 20
+    with vemb.Problem.from_workload(w) as g:
+        g.step(3000)
+        e, feas = g.primal_energy()
+        lb = g.dual_bound()
+    print(f"U = 0: energy - E0 {e - e0:.3e}, feas {feas:.2e}, bound - E0 {lb - e0:.3e}")
+    assert abs(e - e0) < 1e-7 and feas < 1e-7
+    assert lb <= e0 + 1e-12
+
+
+def test_bound_below_exact_energy(vemb):
+    w = synth.sf_ring(12, 2, 1.0)
+    E0 = F.ground_state(w.terms, w.extent)[0] / 12
+    with vemb.Problem.from_workload(w) as g:
+        for _ in range(5):
+            g.step(200)
+            assert g.dual_bound() <= E0 + 1e-12
+        assert g.dual_bound() > E0 - 0.05
