@@ -263,6 +263,12 @@ int vemb_psd_project_batched_ex(const double* in, double* out, int n, int batch,
 
 /* Eigenvalues of a batch of symmetric / Hermitian matrices (device pointers;
  * w receives batch*n doubles in ascending order), by the same Jacobi solver. */
+/* Pi(sym(in)) of ONE n x n matrix (n a positive multiple of 16, at most 4096; DEVICE row-major
+ * FP64, in may alias out) by the matrix-sign route of the dense solver: (A + A sign(A)) / 2 with
+ * sign(A) from 38 scaled Newton-Schulz steps on matrix cores, every eigenvalue above
+ * 1e-14 ||A||_F resolved.  Allocates 4 n^2 + 1 doubles of scratch for the call and synchronises
+ * hip_stream.  Errors: VEMB_E_INVALID, VEMB_E_NOMEM, VEMB_E_HIP. */
+int vemb_psd_project_sign(const double* in, double* out, int n, void* hip_stream);
 int vemb_eigvalsh_batched(const double* in, double* w, int n, int batch, int is_complex, void* hip_stream);
 
 /* ---- Batches: many independent problems stepped together --------------------
@@ -312,9 +318,12 @@ void vemb_batch_destroy(vemb_batch* b);
  * The bonds are those of the translation-invariant term list on the torus
  * (H_ij = H_0d with d the offset from i to j); one-site fields may differ from
  * site to site (disorder), which translation invariance cannot represent.
- * Limits: K <= 256 (K > 64 is solved by the streamed eigensolver on storage
- * padded with zeros to a multiple of 32), pair matrices n <= 256.  Same option
- * struct, precision modes and warm starts as vemb_problem. */
+ * Limits: K <= 1024, pair matrices n <= 256.  K <= 64: the X projection is a
+ * one-sided Jacobi eigensolve (precision modes and warm starts as vemb_problem).
+ * K > 64: Pi(A) = (A + A sign(A)) / 2 with sign(A) from a fixed schedule of 38
+ * scaled Newton-Schulz steps on matrix cores (FP64 in every precision mode; X
+ * stored padded with zeros to a multiple of 32), resolving every eigenvalue
+ * above 1e-14 ||A||_F.  Same option struct as vemb_problem. */
 typedef struct vemb_dense vemb_dense;
 
 /* One-site term coeff * pauli at lattice site (x, y) (wrapped onto the torus),
@@ -371,7 +380,8 @@ int vemb_dense_get_state(vemb_dense* d, vemb_dense_state* st);
  * projection reads its symmetric part); the next eigensolves start cold.
  * VEMB_E_NUMERIC for a non-finite value (nothing is changed then). */
 int vemb_dense_set_state(vemb_dense* d, const vemb_dense_state* st);
-/* Sweeps of the last pair projections (maximum) and of the last X projection. */
+/* Sweeps of the last pair projections (maximum) and of the last X projection
+ * (for K > 64: the number of Newton-Schulz steps). */
 int vemb_dense_last_sweeps(vemb_dense* d, int* pair_max, int* x_sweeps);
 void vemb_dense_destroy(vemb_dense* d);
 

@@ -12,6 +12,7 @@
 #include <string>
 #include <vector>
 
+#include "polar.h"
 #include "problem.h"
 
 namespace vemb {
@@ -849,6 +850,19 @@ int vemb_psd_project_batched_ex(const double* in, double* out, int n, int batch,
                                          sc.w, sc.t, st),
                   "batched projection"));
   return hip_rc(hipStreamSynchronize(st), "batched projection sync");
+}
+
+int vemb_psd_project_sign(const double* in, double* out, int n, void* hip_stream) {
+  if (!in || !out) return fail(VEMB_E_INVALID, "NULL argument");
+  if (n <= 0 || n % 16 || n > 4096) return fail(VEMB_E_INVALID, "n must be a positive multiple of 16, at most 4096");
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  double* work = nullptr;
+  const size_t words = 4 * (size_t)n * n + 1;
+  if (hipMalloc(&work, words * sizeof(double)) != hipSuccess) return fail(VEMB_E_NOMEM, "sign-projection scratch");
+  int rc = hip_rc(launch_psd_project_ns(in, out, n, work, ns_schedule(kNsResolved), st), "sign projection");
+  if (rc == VEMB_OK) rc = hip_rc(hipStreamSynchronize(st), "sign projection sync");
+  hipFree(work);
+  return rc;
 }
 
 int vemb_eigvalsh_batched(const double* in, double* w, int n, int batch, int is_complex, void* hip_stream) {

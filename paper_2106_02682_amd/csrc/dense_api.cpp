@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "dense.h"
+#include "polar.h"
 #include "problem.h"
 
 using namespace vemb;
@@ -30,8 +31,10 @@ struct vemb_dense {
   double* feas = nullptr;   // Q: ||rho_ij - rho~_ij||^2 from the pair projection
   int* sweeps = nullptr;    // Q pair projections, then the X projection
   double* Vpair = nullptr;  // Q x n x n eigenvectors kept for the warm start
-  double* Vx = nullptr;     // ld x ld
-  void *wscr_pair = nullptr, *tscr_pair = nullptr, *wscr_x = nullptr, *tscr_x = nullptr;
+  double* Vx = nullptr;     // ld x ld (K <= 64: kept eigenvectors of the X projection)
+  double* ns_work = nullptr;  // K > 64: scratch of the matrix-sign projection (4 ld^2 + 1)
+  std::vector<double> ns_sched;
+  void *wscr_pair = nullptr, *tscr_pair = nullptr;
 };
 
 namespace {
@@ -111,8 +114,9 @@ int vemb_dense_create(const vemb_hamiltonian* H, const vemb_lattice* lat, const 
   const int m = g.m, n = g.n, M = g.M;
   const int k = o.opset == VEMB_OPSET_COMPLETE ? n : 3 * g.L;
   const int K = M * k;
-  // the dense projection is one K x K eigensolve: LDS solver up to 64, streamed solver up to 256
-  if (K > 256) return fail(VEMB_E_UNSUPPORTED, "dense X above 256 x 256 (M n_op = " + std::to_string(K) + ")");
+  // the dense projection is one K x K problem: LDS Jacobi up to 64, matrix-sign iteration on
+  // matrix cores above (storage padded with zeros to a multiple of 32)
+  if (K > 1024) return fail(VEMB_E_UNSUPPORTED, "dense X above 1024 x 1024 (M n_op = " + std::to_string(K) + ")");
   if (n > 256) return fail(VEMB_E_UNSUPPORTED, "pair matrices above 256 x 256 are not supported");
   const int ld = K <= 64 ? K : (K + 31) / 32 * 32;
   HostModel host;
@@ -186,9 +190,9 @@ int vemb_dense_create(const vemb_hamiltonian* H, const vemb_lattice* lat, const 
       (rc = dalloc(d, &a.e_pair, Q)) || (rc = dalloc(d, &a.e_clu, M)) || (rc = dalloc(d, &a.cons, Q)) ||
       (rc = dalloc(d, &a.Kbuf, Q * nn + M * mm)) || (rc = dalloc(d, &d->lmin, (size_t)Q + M)) ||
       (rc = dalloc(d, &d->feas, Q)) || (rc = dalloc(d, &d->sweeps, (size_t)Q + 1)) ||
-      (rc = dalloc(d, &d->Vpair, Q * nn)) || (rc = dalloc(d, &d->Vx, xx)) ||
+      (rc = dalloc(d, &d->Vpair, Q * nn)) || (ld <= 64 && (rc = dalloc(d, &d->Vx, xx))) ||
       (n > 64 && ((rc = dalloc(d, (double**)&d->wscr_pair, Q * nn)) || (rc = dalloc(d, (double**)&d->tscr_pair, Q * nn)))) ||
-      (ld > 64 && ((rc = dalloc(d, (double**)&d->wscr_x, xx)) || (rc = dalloc(d, (double**)&d->tscr_x, xx)))))
+      (ld > 64 && (rc = dalloc(d, &d->ns_work, 4 * xx + 1))))
     return cleanup(rc);
   hipStream_t s = d->stream;
   if ((rc = hip_rc(hipMemcpyAsync(pairs_dev, d->pairs_host.data(), Q * sizeof(int2), hipMemcpyHostToDevice, s), "upload pairs")) ||
@@ -203,6 +207,7 @@ int vemb_dense_create(const vemb_hamiltonian* H, const vemb_lattice* lat, const 
   a.hp_index = hpi_dev;
   a.ops = ops_dev;
   if ((rc = upload_initial(d))) return cleanup(rc);
+  if (ld > 64) d->ns_sched = ns_schedule(kNsResolved);
   if (valid_tpb(o.tpb)) {
     d->tpb_pair = d->tpb_x = o.tpb;
   } else {
@@ -246,8 +251,7 @@ int vemb_dense_step(vemb_dense* d, int iters) {
     VEMB_TRY(hip_rc(hipEventRecord(d->join_ev, s2), "join"));
     VEMB_TRY(hip_rc(launch_dense_cluster(a, s), "dense cluster update"));
     VEMB_TRY(hip_rc(launch_dense_xstep(a, s), "dense X step"));
-    VEMB_TRY(hip_rc(a.ld > 64 ? launch_psd_batched_big(a.Xp, a.X, a.ld, 1, false, prec, ms, d->sweeps + a.Q, d->Vx,
-                                                       d->wscr_x, d->tscr_x, s, cold)
+    VEMB_TRY(hip_rc(a.ld > 64 ? launch_psd_project_ns(a.Xp, a.X, a.ld, d->ns_work, d->ns_sched, s)
                               : launch_psd_batched(a.Xp, a.X, a.ld, 1, false, prec, ms, d->sweeps + a.Q, d->Vx,
                                                    d->tpb_x, s, cold),
                     "dense X projection"));
@@ -348,7 +352,7 @@ int vemb_dense_last_sweeps(vemb_dense* d, int* pair_max, int* x_sweeps) {
   int mx = 0;
   for (int e = 0; e < d->Q; ++e) mx = sw[e] > mx ? sw[e] : mx;
   if (pair_max) *pair_max = mx;
-  if (x_sweeps) *x_sweeps = sw[d->Q];
+  if (x_sweeps) *x_sweeps = d->ld > 64 ? (int)d->ns_sched.size() : sw[d->Q];
   return VEMB_OK;
 }
 

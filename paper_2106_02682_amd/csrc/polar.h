@@ -1,0 +1,22 @@
+// PSD projection of one large symmetric matrix by the scaled Newton-Schulz sign iteration on
+// matrix cores (polar.hip).
+#pragma once
+
+#include <vector>
+
+#include "common.h"
+
+namespace vemb {
+
+// Scaling factors a_k of the iteration for a resolved fraction l0 of ||A||_F (host).
+std::vector<double> ns_schedule(double l0);
+
+// out = Pi((in + in^T) / 2) for one ld x ld matrix, ld a multiple of 16 (row-major, FP64).
+// work: 4 ld^2 + 1 doubles of device scratch.  `in` may alias `out`.  Enqueued on st.
+hipError_t launch_psd_project_ns(const double* in, double* out, int ld, double* work, const std::vector<double>& sched,
+                                 hipStream_t st);
+
+// Resolved fraction used by the library: eigenvalues below 1e-14 ||A||_F may stay partly unresolved.
+constexpr double kNsResolved = 1e-14;
+
+}  // namespace vemb

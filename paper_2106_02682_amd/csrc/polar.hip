@@ -1,0 +1,135 @@
+// PSD projection of one large symmetric matrix through the matrix sign function, on matrix cores.
+//
+// Pi(A) = (A + |A|) / 2 = (A + A sign(A)) / 2.  sign(A) is the limit of the scaled Newton-Schulz
+// iteration X_0 = A / s (s = 1.01 ||A||_F > ||A||_2),
+//     X_{k+1} = (a_k / 2) X_k (3 I - a_k^2 X_k^2),  a_k = sqrt(3 / (1 + l_k + l_k^2)),
+//     l_{k+1} = (a_k l_k / 2) (3 - a_k^2 l_k^2),
+// where l_k is a lower bound of |eigenvalue| / s still resolved: a_k balances the images of l_k and 1
+// under y (3 - y^2) / 2, so the spectrum stays in [-1, -l] U [l, 1] and l grows by about
+// 3 sqrt(3) / 2 per step while small, quadratically near 1 (Chen and Chow, SIAM J. Sci. Comput. 2014,
+// derive the same scaling).  The schedule depends on l_0 only and is fixed on the host: eigenvalues
+// with |lambda| < l_0 s are left partly unresolved, which moves Pi(A) by at most l_0 s per such
+// eigenvalue.  Every step is two products of symmetric ld x ld matrices; a product is one launch
+// over the upper-triangle 16 x 16 output tiles, one workgroup of four wavefronts per tile splitting
+// the reduction, v_mfma_f64_16x16x4_f64 on operands read row-wise from L2 (symmetric operands:
+// A(i, k) = A(k, i)), every result written exactly symmetric.
+#include "polar.h"
+
+#include <cmath>
+#include <vector>
+
+#include "mfma_tile.h"
+
+namespace vemb {
+namespace {
+
+constexpr int kNormThreads = 1024;
+
+// work[0] = ||in||_F^2 (one workgroup).
+__global__ void __launch_bounds__(kNormThreads) ns_norm_kernel(const double* in, long count, double* work) {
+  __shared__ double red[kNormThreads];
+  double acc = 0.0;
+  for (long e = threadIdx.x; e < count; e += kNormThreads) acc += in[e] * in[e];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = kNormThreads / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) work[0] = red[0];
+}
+
+// A = (in + in^T) / 2,  X = A / s with s = 1.01 ||in||_F: every |eigenvalue| of X is at most 0.99, so
+// the largest ones map under the first scaled step (a_0 ~ sqrt 3) to at least 0.05 instead of to the
+// root y = sqrt 3 of y (3 - y^2), where rounding could flip their sign (a rank-one input attains
+// ||A||_2 = ||A||_F).
+__global__ void __launch_bounds__(256) ns_init_kernel(const double* in, double* A, double* X, int ld,
+                                                      const double* norm2) {
+  const long e = (long)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (long)ld * ld) return;
+  const int i = (int)(e / ld), j = (int)(e % ld);
+  const double s2 = norm2[0];
+  const double inv = s2 > 0.0 ? 1.0 / (1.01 * sqrt(s2)) : 1.0;
+  const double a = 0.5 * (in[e] + in[(long)j * ld + i]);
+  A[e] = a;
+  X[e] = a * inv;
+}
+
+// out = c0 E + c1 P Q for symmetric P, Q, E whose product is symmetric (polynomials in one
+// matrix), written exactly symmetric: one workgroup per upper-triangle tile (ti <= tj) stores the
+// tile and its mirror, a diagonal tile stores its symmetric part.  Reading P(i, k) as P(k, i) is
+// exact only for exactly symmetric P, and an asymmetric rounding residue would grow from step to
+// step of the sign iteration, so every iterate is kept exactly symmetric.  E may be null.
+__global__ void __launch_bounds__(256) ns_gemm_kernel(const double* P, const double* Q, const double* E,
+                                                      double* out, int ld, double c0, double c1) {
+  const int tiles = ld / 16;
+  if ((int)blockIdx.x >= tiles * (tiles + 1) / 2) return;  // the grid holds the upper-triangle tiles only
+  int ti = 0, rem = blockIdx.x;
+  while (rem >= tiles - ti) {
+    rem -= tiles - ti;
+    ++ti;
+  }
+  const int tj = ti + rem;
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int r16 = l & 15, kk = l >> 4;
+  const int chunk = ld / 4;  // reduction range of one wavefront (a multiple of 4)
+  const double* pa = P + (long)(w * chunk + kk) * ld + ti * 16 + r16;  // P(i, k) read as P(k, i)
+  const double* pb = Q + (long)(w * chunk + kk) * ld + tj * 16 + r16;  // Q(k, j)
+  mf_d4 acc = {0.0, 0.0, 0.0, 0.0};
+  for (int k0 = 0; k0 < chunk; k0 += 4) {
+    acc = mfma_k4(pa[(long)k0 * ld], pb[(long)k0 * ld], acc);
+  }
+  __shared__ double red[4][256];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) red[w][mfma_row<double>(l, r) * 16 + r16] = acc[r];
+  __syncthreads();
+  const int t = threadIdx.x, row = t >> 4, col = t & 15;
+  double v = red[0][t] + red[1][t] + red[2][t] + red[3][t];
+  if (ti == tj) {
+    const int tt = col * 16 + row;
+    v = 0.5 * (v + (red[0][tt] + red[1][tt] + red[2][tt] + red[3][tt]));
+  }
+  const long o = (long)(ti * 16 + row) * ld + tj * 16 + col;
+  const double val = E ? c0 * E[o] + c1 * v : c1 * v;
+  out[o] = val;
+  if (ti != tj) out[(long)(tj * 16 + col) * ld + ti * 16 + row] = val;
+}
+
+}  // namespace
+
+std::vector<double> ns_schedule(double l0) {
+  std::vector<double> a;
+  double l = l0;
+  while (1.0 - l > 1e-15 && a.size() < 64) {
+    const double al = std::sqrt(3.0 / (1.0 + l + l * l));
+    a.push_back(al);
+    l = 0.5 * al * l * (3.0 - al * al * l * l);
+  }
+  return a;
+}
+
+hipError_t launch_psd_project_ns(const double* in, double* out, int ld, double* work, const std::vector<double>& sched,
+                                 hipStream_t st) {
+  if (ld <= 0 || ld % 16) return hipErrorInvalidValue;
+  const long nn = (long)ld * ld;
+  double* A = work;
+  double* X = A + nn;
+  double* Y = X + nn;
+  double* T = Y + nn;
+  double* norm2 = T + nn;
+  const int eblocks = (int)((nn + 255) / 256);
+  const int tiles = (ld / 16) * (ld / 16 + 1) / 2;  // upper-triangle tiles
+  hipLaunchKernelGGL(ns_norm_kernel, dim3(1), dim3(kNormThreads), 0, st, in, nn, norm2);
+  hipLaunchKernelGGL(ns_init_kernel, dim3(eblocks), dim3(256), 0, st, in, A, X, ld, norm2);
+  for (double a : sched) {
+    hipLaunchKernelGGL(ns_gemm_kernel, dim3(tiles), dim3(256), 0, st, X, X, nullptr, Y, ld, 0.0, 1.0);
+    hipLaunchKernelGGL(ns_gemm_kernel, dim3(tiles), dim3(256), 0, st, X, Y, X, T, ld, 1.5 * a, -0.5 * a * a * a);
+    std::swap(X, T);
+  }
+  // Pi(A) = (A + A S) / 2 (A and S commute: the product is symmetric up to rounding, written
+  // exactly symmetric)
+  hipLaunchKernelGGL(ns_gemm_kernel, dim3(tiles), dim3(256), 0, st, A, X, A, out, ld, 0.5, 0.5);
+  return hipGetLastError();
+}
+
+}  // namespace vemb

@@ -72,8 +72,8 @@ def test_dense_specs_are_rejected_before_device_work():
     null = vemb.ctypes.c_void_p(None)
     assert _err(lambda: vemb.Dense(TFI, (8, 1), (3, 1), stream=null)) == -1  # does not tile
     assert _err(lambda: vemb.Dense(TFI, (4, 1), (4, 1), stream=null)) == -2  # one cluster
-    # K = M n_op = 8 * 64 above the largest dense eigensolve
-    assert _err(lambda: vemb.Dense(TFI, (24, 1), (3, 1), stream=null)) == -2
+    # K = M n_op = 10 * 256 above the largest dense projection (1024)
+    assert _err(lambda: vemb.Dense(TFI, (40, 1), (4, 1), stream=null)) == -2
     # fields: Y is not real, coefficients must be finite
     assert _err(lambda: vemb.Dense(TFI, (8, 1), (2, 1), fields=[("Y", (0, 0), 1.0)], stream=null)) == -2
     assert _err(lambda: vemb.Dense(TFI, (8, 1), (2, 1), fields=[("X", (0, 0), float("nan"))], stream=null)) == -1
@@ -101,3 +101,12 @@ def test_fermionic_specs_are_rejected_before_device_work():
     # dense: fermionic fields are Z only
     assert _err(lambda: vemb.Dense(hop, (8, 1), (2, 1), fields=[("X", (0, 0), 0.3)], fermionic=True,
                                    stream=null)) == -2
+
+
+def test_sign_projection_rejects_bad_sizes():
+    lib = vemb.lib()
+    assert lib.vemb_psd_project_sign(None, None, 16, None) == -1
+    buf = ctypes.c_void_p(1)
+    assert lib.vemb_psd_project_sign(buf, buf, 24, None) == -1
+    assert lib.vemb_psd_project_sign(buf, buf, 0, None) == -1
+    assert lib.vemb_psd_project_sign(buf, buf, 8192, None) == -1

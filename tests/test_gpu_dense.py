@@ -107,16 +107,18 @@ def test_iterates_match_oracle(vemb, name):
     assert sw[0] < 40 and sw[1] < 40
 
 
-def test_largest_dense_x(vemb):
-    """K = 256 (16 clusters of 2 sites, complete collection), 120 pairs."""
-    w = synth.tfi_ring(32, 2, 1.0)
+@pytest.mark.parametrize("N", [32, 128])
+def test_large_dense_x(vemb, N):
+    """K = 256 (16 clusters of 2 sites, complete collection, 120 pairs) and the largest dense
+    X, K = 1024 (64 clusters, 2016 pairs)."""
+    w = synth.tfi_ring(N, 2, 1.0)
     f = _fields(w, 99)
     dp = _oracle(w, f)
     st = alg5.initial_dense(dp)
     for _ in range(2):
         st = alg5.dense_step(dp, st)
     with vemb.Dense.from_workload(w, fields=f) as g:
-        assert g.info["K"] == 256
+        assert g.info["K"] == 8 * N
         g.step(2)
         got = g.get_state()
         lb = g.dual_bound()
