@@ -266,7 +266,7 @@ int vemb_psd_project_batched_ex(const double* in, double* out, int n, int batch,
 /* Pi(sym(in)) of ONE n x n matrix (n a positive multiple of 16, at most 4096; DEVICE row-major
  * FP64, in may alias out) by the matrix-sign route of the dense solver: (A + A sign(A)) / 2 with
  * sign(A) from 38 scaled Newton-Schulz steps on matrix cores, every eigenvalue above
- * 1e-14 ||A||_F resolved.  Allocates 4 n^2 + 1 doubles of scratch for the call and synchronises
+ * 1e-14 ||A||_F resolved.  Allocates 4 n^2 + 64 doubles of scratch for the call and synchronises
  * hip_stream.  Errors: VEMB_E_INVALID, VEMB_E_NOMEM, VEMB_E_HIP. */
 int vemb_psd_project_sign(const double* in, double* out, int n, void* hip_stream);
 int vemb_eigvalsh_batched(const double* in, double* w, int n, int batch, int is_complex, void* hip_stream);

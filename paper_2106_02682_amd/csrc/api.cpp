@@ -857,7 +857,7 @@ int vemb_psd_project_sign(const double* in, double* out, int n, void* hip_stream
   if (n <= 0 || n % 16 || n > 4096) return fail(VEMB_E_INVALID, "n must be a positive multiple of 16, at most 4096");
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
   double* work = nullptr;
-  const size_t words = 4 * (size_t)n * n + 1;
+  const size_t words = 4 * (size_t)n * n + 64;
   if (hipMalloc(&work, words * sizeof(double)) != hipSuccess) return fail(VEMB_E_NOMEM, "sign-projection scratch");
   int rc = hip_rc(launch_psd_project_ns(in, out, n, work, ns_schedule(kNsResolved), st), "sign projection");
   if (rc == VEMB_OK) rc = hip_rc(hipStreamSynchronize(st), "sign projection sync");

@@ -32,7 +32,7 @@ struct vemb_dense {
   int* sweeps = nullptr;    // Q pair projections, then the X projection
   double* Vpair = nullptr;  // Q x n x n eigenvectors kept for the warm start
   double* Vx = nullptr;     // ld x ld (K <= 64: kept eigenvectors of the X projection)
-  double* ns_work = nullptr;  // K > 64: scratch of the matrix-sign projection (4 ld^2 + 1)
+  double* ns_work = nullptr;  // K > 64: scratch of the matrix-sign projection (4 ld^2 + 64)
   std::vector<double> ns_sched;
   void *wscr_pair = nullptr, *tscr_pair = nullptr;
 };
@@ -192,7 +192,7 @@ int vemb_dense_create(const vemb_hamiltonian* H, const vemb_lattice* lat, const 
       (rc = dalloc(d, &d->feas, Q)) || (rc = dalloc(d, &d->sweeps, (size_t)Q + 1)) ||
       (rc = dalloc(d, &d->Vpair, Q * nn)) || (ld <= 64 && (rc = dalloc(d, &d->Vx, xx))) ||
       (n > 64 && ((rc = dalloc(d, (double**)&d->wscr_pair, Q * nn)) || (rc = dalloc(d, (double**)&d->tscr_pair, Q * nn)))) ||
-      (ld > 64 && (rc = dalloc(d, &d->ns_work, 4 * xx + 1))))
+      (ld > 64 && (rc = dalloc(d, &d->ns_work, 4 * xx + 64))))
     return cleanup(rc);
   hipStream_t s = d->stream;
   if ((rc = hip_rc(hipMemcpyAsync(pairs_dev, d->pairs_host.data(), Q * sizeof(int2), hipMemcpyHostToDevice, s), "upload pairs")) ||

@@ -12,7 +12,7 @@ namespace vemb {
 std::vector<double> ns_schedule(double l0);
 
 // out = Pi((in + in^T) / 2) for one ld x ld matrix, ld a multiple of 16 (row-major, FP64).
-// work: 4 ld^2 + 1 doubles of device scratch.  `in` may alias `out`.  Enqueued on st.
+// work: 4 ld^2 + 64 doubles of device scratch.  `in` may alias `out`.  Enqueued on st.
 hipError_t launch_psd_project_ns(const double* in, double* out, int ld, double* work, const std::vector<double>& sched,
                                  hipStream_t st);
 

@@ -23,20 +23,20 @@
 namespace vemb {
 namespace {
 
-constexpr int kNormThreads = 1024;
+constexpr int kNormBlocks = 64;
 
-// work[0] = ||in||_F^2 (one workgroup).
-__global__ void __launch_bounds__(kNormThreads) ns_norm_kernel(const double* in, long count, double* work) {
-  __shared__ double red[kNormThreads];
+// partial[b] = sum of squares of the b-th slice of `in` (kNormBlocks workgroups of 256).
+__global__ void __launch_bounds__(256) ns_norm_kernel(const double* in, long count, double* partial) {
+  __shared__ double red[256];
   double acc = 0.0;
-  for (long e = threadIdx.x; e < count; e += kNormThreads) acc += in[e] * in[e];
+  for (long e = (long)blockIdx.x * 256 + threadIdx.x; e < count; e += (long)kNormBlocks * 256) acc += in[e] * in[e];
   red[threadIdx.x] = acc;
   __syncthreads();
-  for (int s = kNormThreads / 2; s > 0; s >>= 1) {
+  for (int s = 128; s > 0; s >>= 1) {
     if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
     __syncthreads();
   }
-  if (threadIdx.x == 0) work[0] = red[0];
+  if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
 }
 
 // A = (in + in^T) / 2,  X = A / s with s = 1.01 ||in||_F: every |eigenvalue| of X is at most 0.99, so
@@ -44,11 +44,12 @@ __global__ void __launch_bounds__(kNormThreads) ns_norm_kernel(const double* in,
 // root y = sqrt 3 of y (3 - y^2), where rounding could flip their sign (a rank-one input attains
 // ||A||_2 = ||A||_F).
 __global__ void __launch_bounds__(256) ns_init_kernel(const double* in, double* A, double* X, int ld,
-                                                      const double* norm2) {
+                                                      const double* partial) {
   const long e = (long)blockIdx.x * 256 + threadIdx.x;
   if (e >= (long)ld * ld) return;
   const int i = (int)(e / ld), j = (int)(e % ld);
-  const double s2 = norm2[0];
+  double s2 = 0.0;
+  for (int b = 0; b < kNormBlocks; ++b) s2 += partial[b];
   const double inv = s2 > 0.0 ? 1.0 / (1.01 * sqrt(s2)) : 1.0;
   const double a = 0.5 * (in[e] + in[(long)j * ld + i]);
   A[e] = a;
@@ -60,8 +61,11 @@ __global__ void __launch_bounds__(256) ns_init_kernel(const double* in, double* 
 // tile and its mirror, a diagonal tile stores its symmetric part.  Reading P(i, k) as P(k, i) is
 // exact only for exactly symmetric P, and an asymmetric rounding residue would grow from step to
 // step of the sign iteration, so every iterate is kept exactly symmetric.  E may be null.
-__global__ void __launch_bounds__(256) ns_gemm_kernel(const double* P, const double* Q, const double* E,
-                                                      double* out, int ld, double c0, double c1) {
+// KW wavefronts split the reduction of a tile; each issues all its operand loads before its
+// products (batches of 8), so a product waits on L2 latency about once.
+template <int KW>
+__global__ void __launch_bounds__(64 * KW) ns_gemm_kernel(const double* P, const double* Q, const double* E,
+                                                          double* out, int ld, double c0, double c1) {
   const int tiles = ld / 16;
   if ((int)blockIdx.x >= tiles * (tiles + 1) / 2) return;  // the grid holds the upper-triangle tiles only
   int ti = 0, rem = blockIdx.x;
@@ -72,27 +76,52 @@ __global__ void __launch_bounds__(256) ns_gemm_kernel(const double* P, const dou
   const int tj = ti + rem;
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
   const int r16 = l & 15, kk = l >> 4;
-  const int chunk = ld / 4;  // reduction range of one wavefront (a multiple of 4)
+  const int chunk = ld / KW;  // reduction range of one wavefront (a multiple of 4)
   const double* pa = P + (long)(w * chunk + kk) * ld + ti * 16 + r16;  // P(i, k) read as P(k, i)
   const double* pb = Q + (long)(w * chunk + kk) * ld + tj * 16 + r16;  // Q(k, j)
   mf_d4 acc = {0.0, 0.0, 0.0, 0.0};
-  for (int k0 = 0; k0 < chunk; k0 += 4) {
-    acc = mfma_k4(pa[(long)k0 * ld], pb[(long)k0 * ld], acc);
+  for (int k0 = 0; k0 < chunk; k0 += 32) {
+    double av[8], bv[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const bool in = k0 + 4 * u < chunk;
+      av[u] = in ? pa[(long)(k0 + 4 * u) * ld] : 0.0;
+      bv[u] = in ? pb[(long)(k0 + 4 * u) * ld] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc = mfma_k4(av[u], bv[u], acc);
   }
-  __shared__ double red[4][256];
+  __shared__ double red[KW][256];
 #pragma unroll
   for (int r = 0; r < 4; ++r) red[w][mfma_row<double>(l, r) * 16 + r16] = acc[r];
   __syncthreads();
+  if (threadIdx.x >= 256) return;
   const int t = threadIdx.x, row = t >> 4, col = t & 15;
-  double v = red[0][t] + red[1][t] + red[2][t] + red[3][t];
+  double v = 0.0;
+#pragma unroll
+  for (int q = 0; q < KW; ++q) v += red[q][t];
   if (ti == tj) {
     const int tt = col * 16 + row;
-    v = 0.5 * (v + (red[0][tt] + red[1][tt] + red[2][tt] + red[3][tt]));
+    double vt = 0.0;
+#pragma unroll
+    for (int q = 0; q < KW; ++q) vt += red[q][tt];
+    v = 0.5 * (v + vt);
   }
   const long o = (long)(ti * 16 + row) * ld + tj * 16 + col;
   const double val = E ? c0 * E[o] + c1 * v : c1 * v;
   out[o] = val;
   if (ti != tj) out[(long)(tj * 16 + col) * ld + ti * 16 + row] = val;
+}
+
+// One product with the widest split whose per-wavefront range is a multiple of 4.
+void gemm(const double* P, const double* Q, const double* E, double* out, int ld, double c0, double c1, int blocks,
+          hipStream_t st) {
+  if (ld % 64 == 0)
+    hipLaunchKernelGGL(ns_gemm_kernel<16>, dim3(blocks), dim3(1024), 0, st, P, Q, E, out, ld, c0, c1);
+  else if (ld % 32 == 0)
+    hipLaunchKernelGGL(ns_gemm_kernel<8>, dim3(blocks), dim3(512), 0, st, P, Q, E, out, ld, c0, c1);
+  else
+    hipLaunchKernelGGL(ns_gemm_kernel<4>, dim3(blocks), dim3(256), 0, st, P, Q, E, out, ld, c0, c1);
 }
 
 }  // namespace
@@ -116,19 +145,19 @@ hipError_t launch_psd_project_ns(const double* in, double* out, int ld, double* 
   double* X = A + nn;
   double* Y = X + nn;
   double* T = Y + nn;
-  double* norm2 = T + nn;
+  double* partial = T + nn;
   const int eblocks = (int)((nn + 255) / 256);
   const int tiles = (ld / 16) * (ld / 16 + 1) / 2;  // upper-triangle tiles
-  hipLaunchKernelGGL(ns_norm_kernel, dim3(1), dim3(kNormThreads), 0, st, in, nn, norm2);
-  hipLaunchKernelGGL(ns_init_kernel, dim3(eblocks), dim3(256), 0, st, in, A, X, ld, norm2);
+  hipLaunchKernelGGL(ns_norm_kernel, dim3(kNormBlocks), dim3(256), 0, st, in, nn, partial);
+  hipLaunchKernelGGL(ns_init_kernel, dim3(eblocks), dim3(256), 0, st, in, A, X, ld, partial);
   for (double a : sched) {
-    hipLaunchKernelGGL(ns_gemm_kernel, dim3(tiles), dim3(256), 0, st, X, X, nullptr, Y, ld, 0.0, 1.0);
-    hipLaunchKernelGGL(ns_gemm_kernel, dim3(tiles), dim3(256), 0, st, X, Y, X, T, ld, 1.5 * a, -0.5 * a * a * a);
+    gemm(X, X, nullptr, Y, ld, 0.0, 1.0, tiles, st);
+    gemm(X, Y, X, T, ld, 1.5 * a, -0.5 * a * a * a, tiles, st);
     std::swap(X, T);
   }
   // Pi(A) = (A + A S) / 2 (A and S commute: the product is symmetric up to rounding, written
   // exactly symmetric)
-  hipLaunchKernelGGL(ns_gemm_kernel, dim3(tiles), dim3(256), 0, st, A, X, A, out, ld, 0.5, 0.5);
+  gemm(A, X, A, out, ld, 0.5, 0.5, tiles, st);
   return hipGetLastError();
 }
 
