@@ -18,7 +18,8 @@
 // Work split: 256 threads; each column pair of a round is owned by a group of G
 // lanes of one wavefront (G = 256 / (n/2), at most 64), each lane holding n/G
 // rows; the three dot products are reduced with wavefront shuffles.  One
-// barrier per round.  Sweeps stop when no pair rotated (|gamma| <= tol
+// barrier per round.  Sweeps stop when no pair rotated, or after a sweep whose rotations were all
+// small enough that the next one would rotate nothing (|gamma| <= tol
 // sqrt(alpha beta), tol = max(n, 16) * machine epsilon of the compute type);
 // columns of negligible norm (rounding noise left by an exactly singular B) are
 // not rotated, see below.
@@ -245,10 +246,17 @@ __global__ void __launch_bounds__(NT) jacobi_kernel(Policy pol, int n, int max_s
     const int npair = np / 2;
     const int g = tid / G;   // pair slot
     const int l = tid % G;   // lane within the group
+    // A sweep whose largest rotated |gamma| / sqrt(alpha beta) stays below sqrt(tol) / 16 ends the
+    // solve: cyclic Jacobi converges quadratically, so the next sweep's inner products would be
+    // about tol / 256 and rotate nothing (it would only confirm convergence).  Within clusters of
+    // nearly equal eigenvalues the convergence is slower; what is left there mixes eigenvectors of
+    // nearly equal eigenvalues, which moves Pi only for clusters at the cut (eigenvalues near 0).
+    const R early = dev_sqrt(tol) * R(0.0625);
     for (; sweep < max_sweeps; ++sweep) {
       // squared column norms, recomputed exactly once per sweep and carried through the
       // rotations in between (|w_p'|^2 = |w_p|^2 - t|gamma|, |w_q'|^2 = |w_q|^2 + t|gamma|),
       // so a round reduces only the inner products
+      R relmax = R(0);
       if (tid == 0) rotated = 0;
       for (int j = tid; j < n; j += NT) {
         R s2 = R(0);
@@ -282,7 +290,9 @@ __global__ void __launch_bounds__(NT) jacobi_kernel(Policy pol, int n, int max_s
         const R alpha = live ? cn[p] : R(0), beta = live ? cn[q] : R(0);
         const R ag = modulus(gam);
         const R small = alpha < beta ? alpha : beta;
-        if (live && small > floor2 && ag > tol * dev_sqrt(alpha * beta) && ag > R(0)) {
+        const R gab = dev_sqrt(alpha * beta);
+        if (live && small > floor2 && ag > tol * gab && ag > R(0)) {
+          relmax = ag > relmax * gab ? ag / gab : relmax;
           const R zeta = (beta - alpha) / (R(2) * ag);
           const R az = dev_abs(zeta);
           R t = R(1) / (az + dev_sqrt(R(1) + zeta * zeta));
@@ -317,6 +327,10 @@ __global__ void __launch_bounds__(NT) jacobi_kernel(Policy pol, int n, int max_s
       const int any = rotated;
       __syncthreads();
       if (!any) break;
+      if (block_max(relmax, red) < early) {
+        ++sweep;
+        break;
+      }
     }
   }
   if (tid == 0) pol.record_sweeps(mat, sweep);

