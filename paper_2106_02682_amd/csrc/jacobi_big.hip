@@ -23,9 +23,9 @@ template <> struct big_block<float> { static constexpr int v = 32; };
 template <> struct big_block<cplx<float>> { static constexpr int v = 16; };
 
 // Rotates the column pair (Wp, Wq) (and Vp, Vq) held in LDS, G lanes per pair,
-// rows l, l+G, ... < n.  Returns true when this group rotated.
+// rows l, l+G, ... < n.  Returns |gamma| / sqrt(alpha beta) when this group rotated, else 0.
 template <typename S, int G, bool TRACKV>
-__device__ bool rotate_pair(S* Wp, S* Wq, S* Vp, S* Vq, int n, int l, bool live,
+__device__ typename scalar_traits<S>::real rotate_pair(S* Wp, S* Wq, S* Vp, S* Vq, int n, int l, bool live,
                             typename scalar_traits<S>::real tol, typename scalar_traits<S>::real floor2) {
   using R = typename scalar_traits<S>::real;
   constexpr int RPL = (kBigMax + G - 1) / G;
@@ -54,7 +54,8 @@ __device__ bool rotate_pair(S* Wp, S* Wq, S* Vp, S* Vq, int n, int l, bool live,
   }
   const R ag = modulus(gam);
   const R small = alpha < beta ? alpha : beta;
-  if (!(live && small > floor2 && ag > tol * dev_sqrt(alpha * beta) && ag > R(0))) return false;
+  const R gab = dev_sqrt(alpha * beta);
+  if (!(live && small > floor2 && ag > tol * gab && ag > R(0))) return R(0);
   const R zeta = (beta - alpha) / (R(2) * ag);
   R t = R(1) / (dev_abs(zeta) + dev_sqrt(R(1) + zeta * zeta));
   if (zeta < R(0)) t = -t;
@@ -76,7 +77,7 @@ __device__ bool rotate_pair(S* Wp, S* Wq, S* Vp, S* Vq, int n, int l, bool live,
       }
     }
   }
-  return true;
+  return ag / gab;
 }
 
 // C (n x n, column-major) = A (n x K) * op(B) where A(i, k) = a(i, k) and the
@@ -243,9 +244,12 @@ __global__ void __launch_bounds__(kThreads) jacobi_big_kernel(Policy pol, int n,
     }
   };
 
-  // 4. sweeps
+  // 4. sweeps (ended early as in the LDS solver: once the largest rotation of a sweep is below
+  // sqrt(tol) / 16, the next sweep would rotate nothing)
+  const R early = dev_sqrt(tol) * R(0.0625);
   int sweep = 0;
   for (; sweep < max_sweeps; ++sweep) {
+    R relmax = R(0);
     if (tid == 0) rotated = 0;
     __syncthreads();
     // 4a. pairs inside each block: round-robin on BLK columns, BLK/2 pairs per round
@@ -261,9 +265,10 @@ __global__ void __launch_bounds__(kThreads) jacobi_big_kernel(Policy pol, int n,
           int p = 0, q = 0;
           const bool live = g < NP;
           if (live) rr_pair(round, g, BLK, p, q);
-          const bool rot = rotate_pair<S, G, TRACKV>(&L[p * LDC], &L[q * LDC], &L[(2 * BLK + p) * LDC],
-                                                     &L[(2 * BLK + q) * LDC], n, l, live, tol, floor2);
-          if (rot && l == 0) rotated = 1;
+          const R rel = rotate_pair<S, G, TRACKV>(&L[p * LDC], &L[q * LDC], &L[(2 * BLK + p) * LDC],
+                                                  &L[(2 * BLK + q) * LDC], n, l, live, tol, floor2);
+          relmax = rel > relmax ? rel : relmax;
+          if (rel > R(0) && l == 0) rotated = 1;
           __syncthreads();
         }
         store_block(blk, 0);
@@ -283,9 +288,10 @@ __global__ void __launch_bounds__(kThreads) jacobi_big_kernel(Policy pol, int n,
           for (int r = 0; r < BLK; ++r) {
             const bool live = g < BLK;
             const int p = g, q = BLK + (g + r) % BLK;
-            const bool rot = rotate_pair<S, G, TRACKV>(&L[p * LDC], &L[q * LDC], &L[(2 * BLK + p) * LDC],
-                                                       &L[(2 * BLK + q) * LDC], n, l, live, tol, floor2);
-            if (rot && l == 0) rotated = 1;
+            const R rel = rotate_pair<S, G, TRACKV>(&L[p * LDC], &L[q * LDC], &L[(2 * BLK + p) * LDC],
+                                                    &L[(2 * BLK + q) * LDC], n, l, live, tol, floor2);
+            relmax = rel > relmax ? rel : relmax;
+            if (rel > R(0) && l == 0) rotated = 1;
             __syncthreads();
           }
           store_block(bi, 0);
@@ -296,6 +302,10 @@ __global__ void __launch_bounds__(kThreads) jacobi_big_kernel(Policy pol, int n,
     const int any = rotated;
     __syncthreads();
     if (!any) break;
+    if (block_max(relmax, red) < early) {
+      ++sweep;
+      break;
+    }
   }
   if (tid == 0) pol.record_sweeps(mat, sweep);
   if constexpr (MODE == kVectors) return;
