@@ -3,8 +3,9 @@ the C ABI: Jordan-Wigner pair Hamiltonians built by the library, parity-signed G
 corrections in the iteration, the bound and the energy.
 
 * iterates element by element after a few iterations: short-range rings (2- and 3-site clusters,
-  the latter with 64 x 64 pair blocks), the long-range model (every pair Hamiltonian nonzero), a
-  2-D torus, and the dense Algorithm 5 with a random potential (Z fields);
+  the latter with 64 x 64 pair blocks), the long-range model (every pair Hamiltonian nonzero), 2-D
+  tori with 2 x 1 and 2 x 2 clusters (256 x 256 blocks, streamed solver), and the dense Algorithm 5
+  with a random potential (Z fields), also with a dual above 64 x 64 (sign-iteration projection);
 * fermionic and spin problems stepped together in one batch give their single-problem iterates;
 * at U = 0 on the 20 x 1 ring of the paper's fermion benchmark the energy reaches the
   free-fermion ground-state energy (the relaxation is exact there), and at U = 1 every bound lies
@@ -40,7 +41,8 @@ def _compare(got, want, tol):
 
 
 CASES = [synth.sf_ring(8, 2, 1.0), synth.sf_ring(12, 3, 2.0), synth.sf_ring(12, 2, 1.5, long_range=True),
-         synth.sf_torus(4, 4, 2, 1, 1.0), synth.sf_ring(10, 2, 0.0)]
+         synth.sf_torus(4, 4, 2, 1, 1.0), synth.sf_ring(10, 2, 0.0),
+         synth.sf_torus(4, 4, 2, 2, 1.0)]  # 2 x 2 clusters: 16-state clusters, 256 x 256 pair and momentum blocks
 
 
 @pytest.mark.parametrize("w", CASES, ids=lambda w: w.name)
@@ -61,8 +63,10 @@ def test_iterates_match_oracle(vemb, w):
     assert abs(feas - alg6.feasibility_error(p, s)) <= 1e-9 * max(1.0, feas)
 
 
-def test_dense_with_potential_matches_oracle(vemb):
-    w = synth.sf_ring(10, 2, 1.0)
+@pytest.mark.parametrize("N", [10, 12])
+def test_dense_with_potential_matches_oracle(vemb, N):
+    """K = 80 and 96: both above 64, so the dual goes through the sign-iteration projection."""
+    w = synth.sf_ring(N, 2, 1.0)
     f = synth.disorder_fields(w, 0.6, ("Z",), tag=7)
     dp = alg5.DenseProblem(alg6.Problem.from_workload(w), f)
     st = alg5.initial_dense(dp)
