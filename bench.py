@@ -230,6 +230,36 @@ def dense_leg(args):
     }
 
 
+def tune_leg(args):
+    """Per-family parameter race (tuning.py) on the warm-start ring family (TFI / XXZ, N = 64, 2-site
+    clusters): tune (mu = nu, eps) on 4 training draws, then compare the winner with the paper's
+    choice on 8 held-out draws (iterations until the certified-bound gap stays below 1e-5 / 1e-6)."""
+    import numpy as np
+
+    from paper_2106_02682_amd import tuning
+
+    iters = 30000
+    best, table, secs = tuning.tune(tuning.family(4, split=0), iters=iters, every=100, tol=1e-5, log=log)
+    log(f"tuning: winner {best} in {secs:.1f} s")
+    t0 = time.perf_counter()
+    its, lbs = tuning.run(tuning.family(8, split=1), [tuning.PAPER, best], iters, 100, log=log)
+    secs_eval = time.perf_counter() - t0
+
+    def summary(sc):
+        v = [math.inf if x is None else x for x in sc]
+        return {"reached": sum(x is not None for x in sc), "median_iters": float(np.median(v)), "iters": sc}
+
+    out = {"family": "TFI/XXZ ring N=64, 2-site clusters, seeded draws", "candidates": [list(c) for c in tuning.CANDIDATES],
+           "winner": list(best), "tuning_table_1e-5": {str(list(k)): v for k, v in table.items()},
+           "tuning_seconds": secs, "heldout": 8, "horizon_iters": iters, "heldout_seconds": secs_eval}
+    for tol in (1e-5, 1e-6):
+        sc = tuning.scores_of(its, lbs, tol)
+        out[f"heldout_{tol:.0e}"] = {"paper": summary(sc[0]), "tuned": summary(sc[1])}
+    return {"metric": "iterations to the certified-bound gap, tuned vs the paper's (mu, nu, eps)", "value": None,
+            "unit": "iterations", "n_gpus": 1, "data": "synthetic", "dtype": "f64",
+            "config": {"workload": "parameter race on a ring family"}, "tuning": out}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -237,9 +267,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--h", type=float, default=1.0)
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
-    ap.add_argument("--workload", choices=["c2b", "c4", "dense"], default="c2b",
+    ap.add_argument("--workload", choices=["c2b", "c4", "dense", "tune"], default="c2b",
                     help="c2b: the N=384 ring (default); c4: the 64-instance batched sweep; dense: Algorithm 5 "
-                         "on a disordered ring")
+                         "on a disordered ring; tune: the per-family parameter race")
     ap.add_argument("--lb-every", type=int, default=10)
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="oracle sample length (0 disables)")
     ap.add_argument("--warm", type=int, default=1, help="run the learned warm-start leg (0 skips it)")
@@ -267,6 +297,9 @@ def main():
         return
     if args.workload == "dense":
         print(json.dumps(dense_leg(args)), flush=True)
+        return
+    if args.workload == "tune":
+        print(json.dumps(tune_leg(args)), flush=True)
         return
     w = synth.config_c2(args.h)[1]
     g = vemb.Problem.from_workload(w, precision=args.precision)

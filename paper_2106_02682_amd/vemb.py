@@ -522,10 +522,13 @@ class Batch:
     def sync(self):
         _check(lib().vemb_batch_sync(self.h))
 
-    def dual_bounds(self):
+    def dual_bounds(self, check=True):
+        """Per-problem bounds; check=False returns (bounds, status codes) instead of raising."""
         lb = np.zeros(len(self.problems))
         st = (ctypes.c_int * len(self.problems))()
         lib().vemb_batch_dual_bounds(self.h, _ptr(lb), st)
+        if not check:
+            return lb, list(st)
         for rc in st:
             _check(rc)
         return lb
