@@ -1,8 +1,8 @@
 // Per-iteration kernels of Algorithm 6 other than the eigensolves:
 //   pair_update     steps 1-2 (+ the G_0d part of step 6) for every offset d
 //   cluster_update  steps 4-5 (rho_0 and the consistency multipliers) + G_00 of step 6
-//   dft_forward     step 7  (momentum blocks of X')
-//   dft_inverse     step 9  (first block row of X from the projected blocks)
+//   dft_mfma<true>  step 7  (momentum blocks of X', a product with the twiddle matrix on matrix cores)
+//   dft_mfma<false> step 9  (first block row of X from the projected blocks, likewise)
 //   bound_build     matrices whose smallest eigenvalues give the Lagrangian bound
 //
 // Index conventions: a pair index is (x, y) -> x*m + y (cluster 0 first).
@@ -13,6 +13,7 @@
 // The single-site Pauli collection uses signed-permutation tables instead.  Fermionic problems
 // (appendix on fermions) multiply the pair entries by the Jordan-Wigner parity sign jw_sign.
 #include "kernels.h"
+#include "mfma_tile.h"
 
 namespace vemb {
 namespace {
@@ -266,68 +267,61 @@ __device__ void cluster_update_body(const StepArgs& A) {
   }
 }
 
-// ---------------------------------------------------------------------------
-// Step 7: Xh_k = sum_d tw[k][d] X'_d over the unique momenta (tw includes M^{-1/2}).
-// Thread per entry e of the n_op x n_op block, KC momenta per thread (few, so that
-// many workgroups keep the loads of X' in flight; X' is re-read from L2).
-// ---------------------------------------------------------------------------
-constexpr int KC = 2;
-
-__device__ void dft_forward_body(const StepArgs& A, int bx, int by) {
+// Steps 7 and 9 as real products on matrix cores.  Forward: C = T X' with rows r = 2k + p of T(r, d) = part p of tw[k][d]
+// (p = 0 real, 1 imaginary), C(r, e) -> part p of Xh_k(e).  Inverse: X(d, e) = sum_r U(d, r) Y(r, e)
+// with U(d, 2k + p) = w_k (part p of tw[k][d]) and Y(2k + p, e) = part p of Y_k(e), which is
+// w_k Re(conj(tw[k][d]) Y_k(e)) summed over k.  One wavefront per 16 x 16 output tile (four per
+// workgroup along e), v_mfma_f64_16x16x4_f64; rows, columns and the reduction are padded with zeros;
+// each wavefront issues eight reduction steps of loads before their products.
+template <bool FWD>
+__device__ void dft_mfma_body(const StepArgs& A, int bx, int by) {
   const int E = A.n_op * A.n_op;
-  const int e = bx * kBlock + threadIdx.x;
-  const int k0 = by * KC;
-  if (e >= E) return;
-  const int kc = min(KC, A.Ku - k0);
-  double re[KC], im[KC];
+  const int R = FWD ? 2 * A.Ku : A.M;   // output rows
+  const int Kr = FWD ? A.M : 2 * A.Ku;  // reduction length
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int i16 = l & 15, kk = l >> 4;
+  const int row0 = by * 16, col0 = (bx * 4 + w) * 16;
+  if (col0 >= E) return;  // the whole wavefront (no barrier in this kernel)
+  const int r = row0 + i16;  // operand row supplied by this lane
+  const int e = col0 + i16;  // operand column supplied by this lane
+  mf_d4 acc = {0.0, 0.0, 0.0, 0.0};
+  for (int k0 = 0; k0 < Kr; k0 += 32) {
+    double av[8], bv[8];
 #pragma unroll
-  for (int c = 0; c < KC; ++c) re[c] = im[c] = 0.0;
-#pragma unroll 8
-  for (int d = 0; d < A.M; ++d) {
-    const double v = A.Xp[(size_t)d * E + e];
-#pragma unroll
-    for (int c = 0; c < KC; ++c) {
-      if (c < kc) {
-        const double* t = A.tw + 2 * ((size_t)(k0 + c) * A.M + d);
-        re[c] += t[0] * v;
-        im[c] += t[1] * v;
+    for (int u = 0; u < 8; ++u) {
+      const int q = k0 + 4 * u + kk;  // reduction index supplied by this lane
+      double a = 0.0, b = 0.0;
+      if (q < Kr) {
+        if constexpr (FWD) {
+          if (r < R) a = A.tw[2 * ((size_t)(r >> 1) * A.M + q) + (r & 1)];
+          if (e < E) b = A.Xp[(size_t)q * E + e];
+        } else {
+          const int k = q >> 1, p = q & 1;
+          if (r < R) a = A.wk[k] * A.tw[2 * ((size_t)k * A.M + r) + p];
+          if (e < E) b = A.Xh[2 * ((size_t)k * E + e) + p];
+        }
       }
+      av[u] = a;
+      bv[u] = b;
     }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc = mfma_k4(av[u], bv[u], acc);
   }
-  for (int c = 0; c < kc; ++c) {
-    double* o = A.Xh + 2 * ((size_t)(k0 + c) * E + e);
-    o[0] = re[c];
-    o[1] = im[c];
+#pragma unroll
+  for (int g = 0; g < 4; ++g) {
+    const int orow = row0 + mfma_row<double>(l, g), ocol = col0 + i16;
+    if (orow < R && ocol < E) {
+      if constexpr (FWD)
+        A.Xh[2 * ((size_t)(orow >> 1) * E + ocol) + (orow & 1)] = acc[g];
+      else
+        A.X[(size_t)orow * E + ocol] = acc[g];
+    }
   }
 }
 
-// Step 9: X_d = sum_k w_k Re(conj(tw[k][d]) Y_k), thread per entry, DC offsets per thread.
-constexpr int DC = 4;
-
-__device__ void dft_inverse_body(const StepArgs& A, int bx, int by) {
-  const int E = A.n_op * A.n_op;
-  const int e = bx * kBlock + threadIdx.x;
-  const int d0 = by * DC;
-  if (e >= E) return;
-  const int dc = min(DC, A.M - d0);
-  double acc[DC];
-#pragma unroll
-  for (int c = 0; c < DC; ++c) acc[c] = 0.0;
-#pragma unroll 8
-  for (int k = 0; k < A.Ku; ++k) {
-    const double* y = A.Xh + 2 * ((size_t)k * E + e);
-    const double yr = y[0], yi = y[1];
-    const double wk = A.wk[k];
-#pragma unroll
-    for (int c = 0; c < DC; ++c) {
-      if (c < dc) {
-        const double* t = A.tw + 2 * ((size_t)k * A.M + d0 + c);
-        // conj(t) * y = (tr yr + ti yi) + i(...)
-        acc[c] += wk * (t[0] * yr + t[1] * yi);
-      }
-    }
-  }
-  for (int c = 0; c < dc; ++c) A.X[(size_t)(d0 + c) * E + e] = acc[c];
+template <bool FWD>
+__global__ void __launch_bounds__(kBlock) dft_mfma_kernel(StepArgs A) {
+  dft_mfma_body<FWD>(A, blockIdx.x, blockIdx.y);
 }
 
 // Single-instance kernels and batched kernels.  A batched launch covers every
@@ -335,8 +329,6 @@ __device__ void dft_inverse_body(const StepArgs& A, int bx, int by) {
 __global__ void __launch_bounds__(kBlock) pair_update_kernel(StepArgs A) { pair_update_body(A, blockIdx.x); }
 __global__ void __launch_bounds__(kBlock) pair_xstep_kernel(StepArgs A) { pair_xstep_body(A, blockIdx.x, blockIdx.y); }
 __global__ void __launch_bounds__(kClusterBlock) cluster_update_kernel(StepArgs A) { cluster_update_body(A); }
-__global__ void __launch_bounds__(kBlock) dft_forward_kernel(StepArgs A) { dft_forward_body(A, blockIdx.x, blockIdx.y); }
-__global__ void __launch_bounds__(kBlock) dft_inverse_kernel(StepArgs A) { dft_inverse_body(A, blockIdx.x, blockIdx.y); }
 
 __global__ void __launch_bounds__(kBlock) pair_update_batched(const StepArgs* args, const WorkItem* work) {
   const WorkItem w = work[blockIdx.x];
@@ -351,11 +343,11 @@ __global__ void __launch_bounds__(kClusterBlock) cluster_update_batched(const St
 }
 __global__ void __launch_bounds__(kBlock) dft_forward_batched(const StepArgs* args, const WorkItem* work) {
   const WorkItem w = work[blockIdx.x];
-  dft_forward_body(args[w.inst], w.bx, w.by);
+  dft_mfma_body<true>(args[w.inst], w.bx, w.by);
 }
 __global__ void __launch_bounds__(kBlock) dft_inverse_batched(const StepArgs* args, const WorkItem* work) {
   const WorkItem w = work[blockIdx.x];
-  dft_inverse_body(args[w.inst], w.bx, w.by);
+  dft_mfma_body<false>(args[w.inst], w.bx, w.by);
 }
 
 // ---------------------------------------------------------------------------
@@ -413,15 +405,13 @@ hipError_t launch_cluster_update(const StepArgs& a, hipStream_t st) {
 
 hipError_t launch_dft_forward(const StepArgs& a, hipStream_t st) {
   const int E = a.n_op * a.n_op;
-  hipLaunchKernelGGL(dft_forward_kernel, dim3((E + kBlock - 1) / kBlock, (a.Ku + KC - 1) / KC), dim3(kBlock), 0,
-                     st, a);
+  hipLaunchKernelGGL(dft_mfma_kernel<true>, dim3((E + 63) / 64, (2 * a.Ku + 15) / 16), dim3(kBlock), 0, st, a);
   return hipGetLastError();
 }
 
 hipError_t launch_dft_inverse(const StepArgs& a, hipStream_t st) {
   const int E = a.n_op * a.n_op;
-  hipLaunchKernelGGL(dft_inverse_kernel, dim3((E + kBlock - 1) / kBlock, (a.M + DC - 1) / DC), dim3(kBlock), 0,
-                     st, a);
+  hipLaunchKernelGGL(dft_mfma_kernel<false>, dim3((E + 63) / 64, (a.M + 15) / 16), dim3(kBlock), 0, st, a);
   return hipGetLastError();
 }
 
@@ -434,10 +424,10 @@ void local_grids(const StepArgs& a, int grid[5][2]) {
   grid[1][1] = a.P;
   grid[2][0] = 1;  // cluster update
   grid[2][1] = 1;
-  grid[3][0] = ebx;  // forward DFT
-  grid[3][1] = (a.Ku + KC - 1) / KC;
-  grid[4][0] = ebx;  // inverse DFT
-  grid[4][1] = (a.M + DC - 1) / DC;
+  grid[3][0] = (E + 63) / 64;  // forward DFT: 16 x 64 output tiles of (2 K_u) x E
+  grid[3][1] = (2 * a.Ku + 15) / 16;
+  grid[4][0] = (E + 63) / 64;  // inverse DFT: 16 x 64 output tiles of M x E
+  grid[4][1] = (a.M + 15) / 16;
 }
 
 hipError_t launch_step_batched(int which, const StepArgs* args, const WorkItem* work, int nwork, hipStream_t st) {
