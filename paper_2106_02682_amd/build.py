@@ -12,7 +12,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(PKG, "csrc")
 OBJ = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libvemb.so")
-SOURCES = ["jacobi.hip", "jacobi_big.hip", "step_kernels.hip", "host_model.cpp", "api.cpp", "batch.cpp", "mlp.hip", "mlp_api.cpp", "warm.hip", "dense.hip", "dense_api.cpp", "polar.hip"]
+SOURCES = ["jacobi.hip", "jacobi_big.hip", "step_kernels.hip", "host_model.cpp", "api.cpp", "batch.cpp", "mlp.hip", "mlp_api.cpp", "warm.hip", "dense.hip", "dense_api.cpp", "polar.hip", "sign_batched.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -14,6 +14,7 @@
 
 #include "polar.h"
 #include "problem.h"
+#include "sign_batched.h"
 
 namespace vemb {
 
@@ -375,6 +376,8 @@ int vemb_create_problem(const vemb_hamiltonian* H, const vemb_lattice* lat, cons
       (rc = dalloc(p, &a.Vpair, (size_t)P * n * n)) || (rc = dalloc(p, &a.Vmom, (size_t)2 * Ku * k * k)) ||
       (n > 64 && ((rc = dalloc(p, (double**)&a.wscr_pair, (size_t)P * n * n)) ||
                   (rc = dalloc(p, (double**)&a.tscr_pair, (size_t)P * n * n)))) ||
+      (n > 64 && o.precision == VEMB_FP64 && (rc = dalloc(p, (char**)&p->sign_pair, sign_work_bytes(n, P, false)))) ||
+      (k > 64 && o.precision == VEMB_FP64 && (rc = dalloc(p, (char**)&p->sign_mom, sign_work_bytes(k, Ku, true)))) ||
       (k > 64 && ((rc = dalloc(p, (double**)&a.wscr_mom, (size_t)2 * Ku * k * k)) ||
                   (rc = dalloc(p, (double**)&a.tscr_mom, (size_t)2 * Ku * k * k)))))
     return cleanup(rc);
@@ -438,6 +441,9 @@ int run_iterations(vemb_problem* p, int iters, int prec) {
     VEMB_TRY(hip_rc(hipEventRecord(p->fork_ev, s), "fork"));
     VEMB_TRY(hip_rc(hipStreamWaitEvent(s2, p->fork_ev, 0), "fork"));
     VEMB_TRY(timed(p, VEMB_K_PAIR_PROJ, "pair projection", [&] {
+      if (a.n > 64 && prec == VEMB_FP64 && p->sign_pair)
+        return launch_pair_projection_sign(a.rho, a.Lam, a.rho_t, a.feas, a.n, a.P, a.mu, a.sweeps, p->sign_pair,
+                                           s2);
       if (a.n > 64)
         return launch_pair_projection_big(a.rho, a.Lam, a.rho_t, a.feas, a.n, a.P, a.mu, prec, ms, a.sweeps, a.Vpair,
                                           cold, a.wscr_pair, a.tscr_pair, s2);
@@ -448,6 +454,8 @@ int run_iterations(vemb_problem* p, int iters, int prec) {
     VEMB_TRY(timed(p, VEMB_K_CLUSTER, "cluster update", [&] { return launch_cluster_update(a, s); }));
     VEMB_TRY(timed(p, VEMB_K_DFT_FWD, "forward DFT", [&] { return launch_dft_forward(a, s); }));
     VEMB_TRY(timed(p, VEMB_K_MOM_PROJ, "momentum projection", [&] {
+      if (a.n_op > 64 && prec == VEMB_FP64 && p->sign_mom)
+        return launch_momentum_projection_sign(a.Xh, a.n_op, a.Ku, a.sweeps + a.P, p->sign_mom, s);
       if (a.n_op > 64)
         return launch_momentum_projection_big(a.Xh, a.n_op, a.Ku, prec, ms, a.sweeps + a.P, a.Vmom, cold, a.wscr_mom,
                                               a.tscr_mom, s);

@@ -16,6 +16,7 @@
 #include <vector>
 
 #include "problem.h"
+#include "sign_batched.h"
 
 using namespace vemb;
 
@@ -36,6 +37,7 @@ struct vemb_batch {
     void* vstore_any;
     void* wscr;
     void* tscr;
+    void* nscr;  // FP64 blocks above 64: scratch of the sign-function projection (else null)
   };
   std::vector<Group> groups;
   bool use_graph = true;
@@ -67,16 +69,18 @@ int enqueue_iteration(vemb_batch* b, int cold) {
   VEMB_TRY(hip_rc(hipStreamWaitEvent(b->side, b->fork_ev, 0), "fork"));
   for (const auto& g : b->groups)
     if (g.kind == 0)
-      VEMB_TRY(hip_rc(launch_projection_group(0, g.n, g.count, g.precision, max_sweeps, cold, g.tpb, g.d_item,
-                                              b->d_pair, g.vstore_any, g.wscr, g.tscr, b->side),
+      VEMB_TRY(hip_rc(g.nscr ? launch_projection_group_sign(0, g.n, g.count, g.d_item, b->d_pair, g.nscr, b->side)
+                             : launch_projection_group(0, g.n, g.count, g.precision, max_sweeps, cold, g.tpb,
+                                                       g.d_item, b->d_pair, g.vstore_any, g.wscr, g.tscr, b->side),
                       "batched pair projection"));
   VEMB_TRY(hip_rc(hipEventRecord(b->join_ev, b->side), "join"));
   VEMB_TRY(hip_rc(launch_step_batched(2, b->d_args, nullptr, n_inst, s), "batched cluster update"));
   VEMB_TRY(hip_rc(launch_step_batched(3, b->d_args, b->d_work[3], b->nwork[3], s), "batched forward DFT"));
   for (const auto& g : b->groups)
     if (g.kind == 1)
-      VEMB_TRY(hip_rc(launch_projection_group(1, g.n, g.count, g.precision, max_sweeps, cold, g.tpb, g.d_item,
-                                              b->d_mom, g.vstore_any, g.wscr, g.tscr, s),
+      VEMB_TRY(hip_rc(g.nscr ? launch_projection_group_sign(1, g.n, g.count, g.d_item, b->d_mom, g.nscr, s)
+                             : launch_projection_group(1, g.n, g.count, g.precision, max_sweeps, cold, g.tpb,
+                                                       g.d_item, b->d_mom, g.vstore_any, g.wscr, g.tscr, s),
                       "batched momentum projection"));
   VEMB_TRY(hip_rc(launch_step_batched(4, b->d_args, b->d_work[4], b->nwork[4], s), "batched inverse DFT"));
   VEMB_TRY(hip_rc(hipStreamWaitEvent(s, b->join_ev, 0), "join"));
@@ -177,7 +181,12 @@ int vemb_batch_create(vemb_problem* const* problems, int count, int use_graph, v
         (rc = hip_rc(hipMemcpyAsync(g.d_item, items.data(), sizeof(int2) * items.size(), hipMemcpyHostToDevice, s),
                      "class table")))
       return cleanup(rc);
-    if (g.n > 64) {  // streamed solver scratch, complex-double sized
+    if (g.n > 64 && g.precision == VEMB_FP64) {  // sign-function projection on matrix cores
+      char* w = nullptr;
+      if ((rc = balloc(b, &w, sign_work_bytes(g.n, g.count, g.kind == 1)))) return cleanup(rc);
+      g.nscr = w;
+      g.tpb = 256;
+    } else if (g.n > 64) {  // streamed solver scratch, complex-double sized
       double *w = nullptr, *t = nullptr;
       if ((rc = balloc(b, &w, (size_t)2 * g.count * g.n * g.n)) || (rc = balloc(b, &t, (size_t)2 * g.count * g.n * g.n)))
         return cleanup(rc);

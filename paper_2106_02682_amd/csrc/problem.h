@@ -44,6 +44,9 @@ struct vemb_problem {
   bool k_valid = false;
   int64_t k_uses = 0;  // bound evaluations; every 16th restarts them cold (orthogonality drift)
   int tpb_pair = 256, tpb_mom = 256;  // threads per workgroup of the LDS solver (autotuned)
+  // FP64 blocks above 64 (4-site clusters): scratch of the sign-function projections (else null)
+  void* sign_pair = nullptr;
+  void* sign_mom = nullptr;
   int64_t prof_n[VEMB_K_COUNT] = {};
 };
 

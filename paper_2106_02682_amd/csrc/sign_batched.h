@@ -1,0 +1,25 @@
+// Batched PSD projections of 256 x 256 blocks by the matrix sign function on matrix cores
+// (sign_batched.hip), FP64: the pair and momentum projections of 4-site clusters.
+#pragma once
+
+#include "kernels.h"
+
+namespace vemb {
+
+constexpr int kSignMax = 256;  // block size handled (a multiple of 64, at most this)
+
+// Scratch per block: 4 n^2 scalars (doubles for pairs, complex doubles for momentum blocks).
+inline size_t sign_work_bytes(int n, int count, bool cplx) {
+  return (size_t)count * 4 * n * n * (cplx ? 16 : 8);
+}
+
+// Pair step 3 + Lambda update (as launch_pair_projection) for P blocks of size n.
+hipError_t launch_pair_projection_sign(const double* rho, double* Lam, double* rho_t, double* feas, int n, int P,
+                                       double mu, int* sweeps, void* work, hipStream_t st);
+// Step 8 in place (as launch_momentum_projection) for K complex blocks of size n_op.
+hipError_t launch_momentum_projection_sign(double* Xh, int n_op, int K, int* sweeps, void* work, hipStream_t st);
+// A batch size class (kind 0 pairs, 1 momentum blocks) through the batched policies.
+hipError_t launch_projection_group_sign(int kind, int n, int count, const int2* item, const void* ptrs, void* work,
+                                        hipStream_t st);
+
+}  // namespace vemb
