@@ -441,7 +441,7 @@ int run_iterations(vemb_problem* p, int iters, int prec) {
     VEMB_TRY(hip_rc(hipEventRecord(p->fork_ev, s), "fork"));
     VEMB_TRY(hip_rc(hipStreamWaitEvent(s2, p->fork_ev, 0), "fork"));
     VEMB_TRY(timed(p, VEMB_K_PAIR_PROJ, "pair projection", [&] {
-      if (a.n > 64 && prec == VEMB_FP64 && p->sign_pair)
+      if (prec == VEMB_FP64 && p->sign_pair)
         return launch_pair_projection_sign(a.rho, a.Lam, a.rho_t, a.feas, a.n, a.P, a.mu, a.sweeps, p->sign_pair,
                                            s2);
       if (a.n > 64)
@@ -454,7 +454,7 @@ int run_iterations(vemb_problem* p, int iters, int prec) {
     VEMB_TRY(timed(p, VEMB_K_CLUSTER, "cluster update", [&] { return launch_cluster_update(a, s); }));
     VEMB_TRY(timed(p, VEMB_K_DFT_FWD, "forward DFT", [&] { return launch_dft_forward(a, s); }));
     VEMB_TRY(timed(p, VEMB_K_MOM_PROJ, "momentum projection", [&] {
-      if (a.n_op > 64 && prec == VEMB_FP64 && p->sign_mom)
+      if (prec == VEMB_FP64 && p->sign_mom)
         return launch_momentum_projection_sign(a.Xh, a.n_op, a.Ku, a.sweeps + a.P, p->sign_mom, s);
       if (a.n_op > 64)
         return launch_momentum_projection_big(a.Xh, a.n_op, a.Ku, prec, ms, a.sweeps + a.P, a.Vmom, cold, a.wscr_mom,

@@ -154,11 +154,15 @@ __global__ void __launch_bounds__(kSignThreads) sign_store_kernel(Policy pol, in
   }
 }
 
-template <typename S, int KW>
+// 16 wavefronts split a tile's reduction for n >= 128, 4 below (each keeps a range of >= 16).
+template <typename S>
 void gemm(S* work, int n, int count, int p, int q, int e, int o, double c0, double c1, hipStream_t st) {
   const int tiles = n / 16;
-  hipLaunchKernelGGL((sign_gemm_kernel<S, KW>), dim3(tiles * (tiles + 1) / 2, count), dim3(64 * KW), 0, st, work,
-                     n, p, q, e, o, c0, c1);
+  const dim3 grid(tiles * (tiles + 1) / 2, count);
+  if (n >= 128)
+    hipLaunchKernelGGL((sign_gemm_kernel<S, 16>), grid, dim3(1024), 0, st, work, n, p, q, e, o, c0, c1);
+  else
+    hipLaunchKernelGGL((sign_gemm_kernel<S, 4>), grid, dim3(256), 0, st, work, n, p, q, e, o, c0, c1);
 }
 
 template <typename S, typename Policy>
@@ -173,12 +177,12 @@ hipError_t sign_project(const Policy& pol, int n, int count, void* work_raw, hip
   int X = nn, T = 3 * nn;
   hipLaunchKernelGGL((sign_load_kernel<S, Policy>), dim3(count), dim3(kSignThreads), 0, st, pol, n, work);
   for (double a : sched) {
-    gemm<S, 16>(work, n, count, X, X, -1, Y, 0.0, 1.0, st);
-    gemm<S, 16>(work, n, count, X, Y, X, T, 1.5 * a, -0.5 * a * a * a, st);
+    gemm<S>(work, n, count, X, X, -1, Y, 0.0, 1.0, st);
+    gemm<S>(work, n, count, X, Y, X, T, 1.5 * a, -0.5 * a * a * a, st);
     std::swap(X, T);
   }
   // Pi(A) = (A + A S) / 2 into the slot of X^2, free after the last step
-  gemm<S, 16>(work, n, count, A, X, A, Y, 0.5, 0.5, st);
+  gemm<S>(work, n, count, A, X, A, Y, 0.5, 0.5, st);
   hipLaunchKernelGGL((sign_store_kernel<S, Policy>), dim3(count), dim3(kSignThreads), 0, st, pol, n, work, Y,
                      (int)sched.size());
   return hipGetLastError();
