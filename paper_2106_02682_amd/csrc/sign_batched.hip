@@ -5,7 +5,7 @@
 // (X_0 = A / (1.01 ||A||_F), 38 steps X <- (a/2) X (3I - a^2 X^2), every eigenvalue above
 // 1e-14 ||A||_F resolved).  A one-sided Jacobi solve of one 256 x 256 block runs on one workgroup
 // with its columns streamed through L2; here every step is a batched product over all blocks, one
-// workgroup per upper-triangle 16 x 16 tile per block, so the chip is filled by tiles.  The blocks
+// workgroup per upper-triangle 64 x 64 tile per block, so the chip is filled by tiles.  The blocks
 // are read and written through the eigensolver's policies (pair: C = rho - Lambda/mu in, rho~ and the
 // Lambda update and ||rho - rho~||^2 out; momentum: in place), so single problems and batches share
 // these kernels.  Products of Hermitian polynomials in A are Hermitian; each is written exactly
@@ -49,12 +49,18 @@ __global__ void __launch_bounds__(kSignThreads) sign_load_kernel(Policy pol, int
   for (size_t e = threadIdx.x; e < nn; e += kSignThreads) X[e] = scale_s(inv, A[e]);
 }
 
-// Per block: out(i, j) = c0 E(i, j) + c1 (P Q)(i, j) over the upper-triangle tiles (blockIdx.x) of
-// block blockIdx.y; P, Q, E, out are offsets (in scalars) inside the block's 4 n^2 work area.
-template <typename S, int KW>
-__global__ void __launch_bounds__(64 * KW) sign_gemm_kernel(S* work, int n, int p_off, int q_off, int e_off,
-                                                            int o_off, double c0, double c1) {
-  const int tiles = n / 16;
+// Per block: out(i, j) = c0 E(i, j) + c1 (P Q)(i, j) over the upper-triangle 64 x 64 tiles
+// (blockIdx.x) of block blockIdx.y; P, Q, E, out are offsets (in scalars) inside the block's 4 n^2
+// work area.  Sixteen wavefronts, one 16 x 16 sub-tile each; the reduction runs in chunks of 32:
+// the 32 x 64 slices P(k0.., i-range) and Q(k0.., j-range) are staged in LDS with coalesced row
+// reads (P(i, k) = conj(P(k, i)) read as rows of P), so every operand is read from memory once per
+// 64 x 64 tile instead of once per 16 x 16 tile.  The finished tile passes through the same LDS to
+// be written (with its conjugate mirror, or its Hermitian part on the diagonal) row by row.
+template <typename S>
+__global__ void __launch_bounds__(1024) sign_gemm_kernel(S* work, int n, int p_off, int q_off, int e_off, int o_off,
+                                                         double c0, double c1) {
+  constexpr int TB = 64, KC = 32;
+  const int tiles = n / TB;
   if ((int)blockIdx.x >= tiles * (tiles + 1) / 2) return;
   int ti = 0, rem = blockIdx.x;
   while (rem >= tiles - ti) {
@@ -67,72 +73,56 @@ __global__ void __launch_bounds__(64 * KW) sign_gemm_kernel(S* work, int n, int 
   const S* Q = base + q_off;
   const S* E = e_off >= 0 ? base + e_off : nullptr;
   S* out = base + o_off;
-  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
   const int r16 = l & 15, kk = l >> 4;
-  const int chunk = n / KW;  // a multiple of 4
-  const S* pa = P + (size_t)(w * chunk + kk) * n + ti * 16 + r16;  // P(i, k) = conj(P(k, i))
-  const S* pb = Q + (size_t)(w * chunk + kk) * n + tj * 16 + r16;  // Q(k, j)
+  const int sr = w >> 2, sc = w & 3;  // sub-tile of this wavefront
+  // staging: Ps[k][i] = P(k0 + k, ti*64 + i), Qs[k][j] = Q(k0 + k, tj*64 + j); later the result tile
+  __shared__ S lds[2 * KC * TB];
+  S* Ps = lds;
+  S* Qs = lds + KC * TB;
   mf_d4 re = {0.0, 0.0, 0.0, 0.0}, im = {0.0, 0.0, 0.0, 0.0};
-  for (int k0 = 0; k0 < chunk; k0 += 32) {
-    S av[8], bv[8];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const bool in = k0 + 4 * u < chunk;
-      av[u] = in ? pa[(size_t)(k0 + 4 * u) * n] : s_zero<S>();
-      bv[u] = in ? pb[(size_t)(k0 + 4 * u) * n] : s_zero<S>();
+  for (int k0 = 0; k0 < n; k0 += KC) {
+    for (int e = tid; e < KC * TB; e += 1024) {
+      const int k = e / TB, c = e % TB;
+      Ps[e] = P[(size_t)(k0 + k) * n + ti * TB + c];
+      Qs[e] = Q[(size_t)(k0 + k) * n + tj * TB + c];
     }
+    __syncthreads();
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
+    for (int u = 0; u < KC / 4; ++u) {
+      const S av = Ps[(4 * u + kk) * TB + sr * 16 + r16];  // A(i, k) = conj(av)
+      const S bv = Qs[(4 * u + kk) * TB + sc * 16 + r16];  // B(k, j)
       if constexpr (scalar_traits<S>::is_complex) {
-        // A(i, k) = conj(stored): re = a.re, im = -a.im
-        re = mfma_k4(av[u].re, bv[u].re, re);
-        re = mfma_k4(av[u].im, bv[u].im, re);
-        im = mfma_k4(av[u].re, bv[u].im, im);
-        im = mfma_k4(-av[u].im, bv[u].re, im);
+        re = mfma_k4(av.re, bv.re, re);
+        re = mfma_k4(av.im, bv.im, re);
+        im = mfma_k4(av.re, bv.im, im);
+        im = mfma_k4(-av.im, bv.re, im);
       } else {
-        re = mfma_k4(av[u], bv[u], re);
+        re = mfma_k4(av, bv, re);
       }
     }
+    __syncthreads();
   }
-  constexpr int NP = scalar_traits<S>::is_complex ? 2 : 1;
-  __shared__ double red[NP][KW][256];
+  // the finished 64 x 64 tile into LDS: Ts[r][c]
+  S* Ts = lds;
 #pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    red[0][w][mfma_row<double>(l, r) * 16 + r16] = re[r];
-    if constexpr (NP == 2) red[NP - 1][w][mfma_row<double>(l, r) * 16 + r16] = im[r];
+  for (int g = 0; g < 4; ++g) {
+    const int r = sr * 16 + mfma_row<double>(l, g), c = sc * 16 + r16;
+    if constexpr (scalar_traits<S>::is_complex)
+      Ts[r * TB + c] = S{re[g], im[g]};
+    else
+      Ts[r * TB + c] = re[g];
   }
   __syncthreads();
-  if (threadIdx.x >= 256) return;
-  const int t = threadIdx.x, row = t >> 4, col = t & 15;
-  double vr = 0.0, vi = 0.0;
-#pragma unroll
-  for (int q = 0; q < KW; ++q) {
-    vr += red[0][q][t];
-    if constexpr (NP == 2) vi += red[NP - 1][q][t];
-  }
-  if (ti == tj) {  // symmetric / Hermitian part of a diagonal tile
-    const int tt = col * 16 + row;
-    double wr = 0.0, wi = 0.0;
-#pragma unroll
-    for (int q = 0; q < KW; ++q) {
-      wr += red[0][q][tt];
-      if constexpr (NP == 2) wi += red[NP - 1][q][tt];
-    }
-    vr = 0.5 * (vr + wr);
-    vi = 0.5 * (vi - wi);
-  }
-  const size_t o = (size_t)(ti * 16 + row) * n + tj * 16 + col;
-  const size_t om = (size_t)(tj * 16 + col) * n + ti * 16 + row;
-  if constexpr (NP == 2) {
-    cplx<double> v{c1 * vr, c1 * vi};
-    if (E) v = v + scale_s(c0, E[o]);
-    out[o] = v;
-    if (ti != tj) out[om] = conjugate(v);
-  } else {
-    double v = c1 * vr;
-    if (E) v += c0 * E[o];
-    out[o] = v;
-    if (ti != tj) out[om] = v;
+  for (int e = tid; e < TB * TB; e += 1024) {
+    const int r = e / TB, c = e % TB;
+    S v = Ts[e];
+    if (ti == tj) v = herm_part<S>(v, Ts[c * TB + r]);
+    S val = scale_s(c1, v);
+    const size_t o = (size_t)(ti * TB + r) * n + tj * TB + c;
+    if (E) val = val + scale_s(c0, E[o]);
+    out[o] = val;
+    if (ti != tj) out[(size_t)(tj * TB + c) * n + ti * TB + r] = conjugate(val);
   }
 }
 
@@ -154,15 +144,11 @@ __global__ void __launch_bounds__(kSignThreads) sign_store_kernel(Policy pol, in
   }
 }
 
-// 16 wavefronts split a tile's reduction for n >= 128, 4 below (each keeps a range of >= 16).
 template <typename S>
 void gemm(S* work, int n, int count, int p, int q, int e, int o, double c0, double c1, hipStream_t st) {
-  const int tiles = n / 16;
-  const dim3 grid(tiles * (tiles + 1) / 2, count);
-  if (n >= 128)
-    hipLaunchKernelGGL((sign_gemm_kernel<S, 16>), grid, dim3(1024), 0, st, work, n, p, q, e, o, c0, c1);
-  else
-    hipLaunchKernelGGL((sign_gemm_kernel<S, 4>), grid, dim3(256), 0, st, work, n, p, q, e, o, c0, c1);
+  const int tiles = n / 64;
+  hipLaunchKernelGGL((sign_gemm_kernel<S>), dim3(tiles * (tiles + 1) / 2, count), dim3(1024), 0, st, work, n, p, q,
+                     e, o, c0, c1);
 }
 
 template <typename S, typename Policy>
