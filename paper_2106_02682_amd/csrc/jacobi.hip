@@ -285,21 +285,21 @@ __global__ void __launch_bounds__(NT) jacobi_kernel(Policy pol, int n, int max_s
           }
           gam = gam + conj_mul(a[r], b[r]);
         }
-  #pragma unroll
-        for (int off = G / 2; off > 0; off >>= 1) gam = gam + shfl_x(gam, off);
+        gam = group_sum<G>(gam);
         const R alpha = live ? cn[p] : R(0), beta = live ? cn[q] : R(0);
-        const R ag = modulus(gam);
+        const R ag = modulus_fast(gam);
         const R small = alpha < beta ? alpha : beta;
         const R gab = dev_sqrt(alpha * beta);
         if (live && small > floor2 && ag > tol * gab && ag > R(0)) {
           relmax = ag > relmax * gab ? ag / gab : relmax;
-          const R zeta = (beta - alpha) / (R(2) * ag);
+          const R inv_ag = R(1) / ag;
+          const R zeta = (beta - alpha) * (R(0.5) * inv_ag);
           const R az = dev_abs(zeta);
           R t = R(1) / (az + dev_sqrt(R(1) + zeta * zeta));
           if (zeta < R(0)) t = -t;
           const R c = R(1) / dev_sqrt(R(1) + t * t);
           const R s = c * t;
-          const S ph = conj_phase(gam, ag);  // conj(e)
+          const S ph = conj_phase_inv(gam, inv_ag);  // conj(e)
           if (l == 0) {
             const R da = t * ag;
             cn[p] = alpha - da > R(0) ? alpha - da : R(0);

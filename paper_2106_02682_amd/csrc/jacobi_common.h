@@ -25,6 +25,35 @@ template <typename T> __device__ inline cplx<T> shfl_x(cplx<T> v, int m) {
   return {__shfl_xor(v.re, m), __shfl_xor(v.im, m)};
 }
 
+// Sum over aligned groups of G lanes, the same bits in every lane of a group.  Groups of 16 are the
+// rows of the DPP network: rotations by 8, 4, 2, 1 within the row add operand pairs that every lane
+// sees in the same two values (so the group agrees bit for bit), at register latency instead of
+// the LDS crossbar's; other group sizes use butterfly shuffles.
+template <int N> __device__ inline double row_ror(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_mov_dpp((int)b, 0x120 + N, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), 0x120 + N, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+template <int N> __device__ inline float row_ror(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x120 + N, 0xF, 0xF, false));
+}
+template <int G, typename R> __device__ inline R group_sum(R v) {
+  if constexpr (G == 16) {
+    v = v + row_ror<8>(v);
+    v = v + row_ror<4>(v);
+    v = v + row_ror<2>(v);
+    v = v + row_ror<1>(v);
+  } else {
+#pragma unroll
+    for (int off = G / 2; off > 0; off >>= 1) v = v + __shfl_xor(v, off);
+  }
+  return v;
+}
+template <int G, typename R> __device__ inline cplx<R> group_sum(cplx<R> v) {
+  return {group_sum<G>(v.re), group_sum<G>(v.im)};
+}
+
 template <typename R> __device__ inline R scale_by(R s, R a) { return s * a; }
 template <typename R> __device__ inline cplx<R> scale_by(R s, cplx<R> a) { return {s * a.re, s * a.im}; }
 
@@ -40,6 +69,23 @@ template <typename R> __device__ inline R modulus(cplx<R> a) {
   if (big == R(0)) return R(0);
   const R xs = x / big, ys = y / big;
   return big * dev_sqrt(xs * xs + ys * ys);
+}
+
+// |a| without the rescaling where the squares can neither overflow nor underflow.
+template <typename R> struct square_safe;
+template <> struct square_safe<double> { static constexpr double lo = 0x1p-500, hi = 0x1p500; };
+template <> struct square_safe<float> { static constexpr float lo = 0x1p-60f, hi = 0x1p60f; };
+template <typename R> __device__ inline R modulus_fast(R a) { return dev_abs(a); }
+template <typename R> __device__ inline R modulus_fast(cplx<R> a) {
+  const R x = dev_abs(a.re), y = dev_abs(a.im);
+  const R big = x > y ? x : y;
+  if (big > square_safe<R>::lo && big < square_safe<R>::hi) return dev_sqrt(a.re * a.re + a.im * a.im);
+  return modulus(a);
+}
+// conj(gamma)/|gamma| from 1/|gamma| (complex); the exact sign of gamma (real).
+template <typename R> __device__ inline R conj_phase_inv(R g, R) { return g < R(0) ? R(-1) : R(1); }
+template <typename R> __device__ inline cplx<R> conj_phase_inv(cplx<R> g, R inv_absg) {
+  return {g.re * inv_absg, -g.im * inv_absg};
 }
 
 // conj(gamma)/|gamma| for complex, sign(gamma) for real.
