@@ -25,28 +25,41 @@ template <typename T> __device__ inline cplx<T> shfl_x(cplx<T> v, int m) {
   return {__shfl_xor(v.re, m), __shfl_xor(v.im, m)};
 }
 
-// Sum over aligned groups of G lanes, the same bits in every lane of a group.  Groups of 16 are the
-// rows of the DPP network: rotations by 8, 4, 2, 1 within the row add operand pairs that every lane
-// sees in the same two values (so the group agrees bit for bit), at register latency instead of
-// the LDS crossbar's; other group sizes use butterfly shuffles.
-template <int N> __device__ inline double row_ror(double v) {
+// Sum over aligned groups of G lanes (G a power of two up to 64), the same bits in every lane of a
+// group.  Within a row of 16 lanes the DPP network adds operand pairs at register latency instead of
+// the LDS crossbar's: rotations by 8, 4, 2, 1 for 16 lanes; for 8 lanes the half-row mirror
+// (lane i with 7 - i) and the quad permutations swapping lanes 1 apart and 2 apart.  Every step
+// adds two values that the partner lane adds in the other order, so a group agrees bit for bit.
+// Offsets of 16 and 32 go through shuffles.
+template <int CTRL> __device__ inline double dpp_mov(double v) {
   const long long b = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_mov_dpp((int)b, 0x120 + N, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), 0x120 + N, 0xF, 0xF, false);
+  const int lo = __builtin_amdgcn_mov_dpp((int)b, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xF, 0xF, false);
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
-template <int N> __device__ inline float row_ror(float v) {
-  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x120 + N, 0xF, 0xF, false));
+template <int CTRL> __device__ inline float dpp_mov(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, false));
 }
+constexpr int kDppQuadXor1 = 0xB1;     // quad_perm [1, 0, 3, 2]
+constexpr int kDppQuadXor2 = 0x4E;     // quad_perm [2, 3, 0, 1]
+constexpr int kDppHalfMirror = 0x141;  // row_half_mirror
+constexpr int kDppRowRor = 0x120;      // row_ror:N is kDppRowRor + N
 template <int G, typename R> __device__ inline R group_sum(R v) {
-  if constexpr (G == 16) {
-    v = v + row_ror<8>(v);
-    v = v + row_ror<4>(v);
-    v = v + row_ror<2>(v);
-    v = v + row_ror<1>(v);
-  } else {
+  static_assert(G >= 1 && G <= 64 && (G & (G - 1)) == 0, "groups of a power of two lanes within a wavefront");
+  if constexpr (G == 2 || G == 4) {
+    v = v + dpp_mov<kDppQuadXor1>(v);
+    if constexpr (G == 4) v = v + dpp_mov<kDppQuadXor2>(v);
+  } else if constexpr (G == 8) {
+    v = v + dpp_mov<kDppHalfMirror>(v);
+    v = v + dpp_mov<kDppQuadXor1>(v);
+    v = v + dpp_mov<kDppQuadXor2>(v);
+  } else if constexpr (G >= 16) {
+    v = v + dpp_mov<kDppRowRor + 8>(v);
+    v = v + dpp_mov<kDppRowRor + 4>(v);
+    v = v + dpp_mov<kDppRowRor + 2>(v);
+    v = v + dpp_mov<kDppRowRor + 1>(v);
 #pragma unroll
-    for (int off = G / 2; off > 0; off >>= 1) v = v + __shfl_xor(v, off);
+    for (int off = 16; off < G; off <<= 1) v = v + __shfl_xor(v, off);
   }
   return v;
 }
