@@ -47,7 +47,7 @@ def flops_per_launch(kernel, info):
 
 def source_digest():
     h = hashlib.sha256()
-    for f in ("jacobi.hip",):
+    for f in ("jacobi.hip", "jacobi_common.h"):  # the eigensolver kernels' sources
         with open(os.path.join(ROOT, "paper_2106_02682_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

@@ -37,8 +37,12 @@ TRAFFIC_KERNELS = [
 
 
 def source_digest():
-    with open(os.path.join(ROOT, "paper_2106_02682_amd", "csrc", "jacobi.hip"), "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    """Digest of the eigensolver kernels' sources (jacobi.hip and its helpers)."""
+    h = hashlib.sha256()
+    for name in ("jacobi.hip", "jacobi_common.h"):
+        with open(os.path.join(ROOT, "paper_2106_02682_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def summarize_traffic(fetch_dir, write_dir, cmd_fetch, cmd_write):
@@ -78,7 +82,7 @@ def summarize_traffic(fetch_dir, write_dir, cmd_fetch, cmd_write):
           f"Counters: `{cmd_fetch}` and `{cmd_write}` (one counter per run).", "",
           f"Calibration: a plain 256 MiB device copy (`__amd_rocclr_copyBuffer`) reads FETCH_SIZE {calib(F):.0f} KiB "
           f"and WRITE_SIZE {calib(W):.0f} KiB against {copy_kib:.0f} KiB true: factors {fF:.3f} (fetch) and "
-          f"{fW:.3f} (write) are applied below.", ""] + lines + ["", f"jacobi.hip digest: {digest}",
+          f"{fW:.3f} (write) are applied below.", ""] + lines + ["", f"eigensolver source digest (jacobi.hip, jacobi_common.h): {digest}",
           "Summarised by `python paper_2106_02682_amd/profile_run.py --summarize-traffic <fetch out> <write out>`."]
     with open(os.path.join(ROOT, "profiles", "traffic_c2b_fp64.md"), "w") as fh:
         fh.write("\n".join(md) + "\n")
