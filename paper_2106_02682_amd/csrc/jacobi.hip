@@ -45,6 +45,13 @@ __global__ void __launch_bounds__(NT) jacobi_kernel(Policy pol, int n, int max_s
   constexpr int G0 = NT / NPAIR;
   constexpr int G = G0 > 64 ? 64 : G0;  // lanes per pair, within one wavefront
   constexpr int RPL = (NMAX + G - 1) / G;  // rows per lane
+  // Projection solves keep no rotated copy of V during the sweeps: at convergence W = B V has
+  // mutually orthogonal columns (to the relative tolerance, checked on the stored W), so w_j / ||w_j||
+  // is an orthonormal eigenbasis of B (sign(lambda_j) v_j) and is what the next warm start needs.
+  // A block with a column at the noise floor (never rotated, so not orthogonal to the rest) keeps the
+  // identity instead, which makes its next solve cold.  Half of every round's LDS traffic and
+  // arithmetic (the V columns) goes away.
+  constexpr bool VFW = WARM && MODE == kProject && !REG;
   __shared__ S W[NMAX * LD];
   __shared__ S V[WARM ? NMAX * LD : 1];
   __shared__ R red[NT];
@@ -312,7 +319,7 @@ __global__ void __launch_bounds__(NT) jacobi_kernel(Policy pol, int n, int max_s
               const S bq = mul_phase(ph, b[r]);
               W[p * LD + i] = scale_by(c, a[r]) - scale_by(s, bq);
               W[q * LD + i] = scale_by(s, a[r]) + scale_by(c, bq);
-              if constexpr (WARM) {
+              if constexpr (WARM && !VFW) {
                 const S va = V[p * LD + i];
                 const S vb = mul_phase(ph, V[q * LD + i]);
                 V[p * LD + i] = scale_by(c, va) - scale_by(s, vb);
@@ -334,7 +341,7 @@ __global__ void __launch_bounds__(NT) jacobi_kernel(Policy pol, int n, int max_s
     }
   }
   if (tid == 0) pol.record_sweeps(mat, sweep);
-  if constexpr (WARM) {
+  if constexpr (WARM && !VFW) {
     D* vout = pol.template vslot<D>(vstore_raw, mat, (size_t)nn);
     for (int idx = tid; idx < nn; idx += NT) {
       const int j = idx / n, i = idx - (idx / n) * n;
@@ -344,12 +351,22 @@ __global__ void __launch_bounds__(NT) jacobi_kernel(Policy pol, int n, int max_s
   if constexpr (MODE == kVectors) return;
 
   // 4. column norms sigma_j = lambda_j(B)
+  R noise = R(0);
   for (int j = tid; j < n; j += NT) {
     R s2 = R(0);
     for (int i = 0; i < n; ++i) s2 += abs2(W[j * LD + i]);
     colf[j] = dev_sqrt(s2);
+    if (s2 <= floor2) noise = R(1);
   }
   __syncthreads();
+  if constexpr (VFW) {
+    const bool ident = block_max(noise, red) > R(0);
+    D* vout = pol.template vslot<D>(vstore_raw, mat, (size_t)nn);
+    for (int idx = tid; idx < nn; idx += NT) {
+      const int j = idx / n, i = idx - (idx / n) * n;
+      vout[idx] = ident ? widen(i == j ? one_of<S>() : s_zero<S>()) : widen(scale_by(R(1) / colf[j], W[j * LD + i]));
+    }
+  }
 
   if constexpr (MODE == kEigvals) {
     // eigenvalues of C: sigma_j - s, sorted ascending by rank
