@@ -165,7 +165,8 @@ __global__ void __launch_bounds__(NT) jacobi_kernel(Policy pol, int n, int max_s
   __syncthreads();
   // Warm start: W = B V_prev, where V_prev holds the eigenvectors of the previous
   // solve of this matrix slot.  B V_prev is nearly column-orthogonal when the
-  // matrix moved little, so few sweeps remain.  V accumulates the rotations.
+  // matrix moved little, so few sweeps remain.  V accumulates the rotations (eigenvalue and
+  // eigenvector solves; projection solves rebuild V from W at the end instead).
   if constexpr (WARM) {
     const D* vin = pol.template vslot<D>(vstore_raw, mat, (size_t)nn);  // column-major: V(i, j) at [j*n + i]
     if (cold == 1) {

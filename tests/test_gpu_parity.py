@@ -239,6 +239,28 @@ def test_state_roundtrip_and_resume(vemb, w):
     assert sb["t"] == 50
 
 
+@pytest.mark.parametrize("w", [synth.tfi_ring(8, 2, 1.0), synth.afh_torus(4, 4, 1, 1), synth.config_c2(1.0)[1]],
+                         ids=lambda w: w.name)
+def test_kept_eigenvectors_orthonormal(vemb, w):
+    """The eigenvectors kept for the next warm start (the normalised columns of the converged W, or the
+    identity for a block with a noise-floor column) are orthonormal in every block up to the residual
+    non-orthogonality of the converged W, which also bounds the error of the projection built from that W:
+    the sweep that ends a solve rotated by less than sqrt(tol) / 16 (~7e-9 at n = 64), and after it the
+    residual is far smaller except inside clusters of nearly equal eigenvalues (measured: 3.4e-12 on the
+    N = 384 ring after 30 iterations)."""
+    from paper_2106_02682_amd import vemb as v
+
+    with v.Problem.from_workload(w) as g:
+        g.step(30)
+        st = g.get_state(with_eigvecs=True)
+    vp = st["Vpair"]
+    vm = st["Vmom"][..., 0] + 1j * st["Vmom"][..., 1]
+    for name, V in (("pair", vp), ("momentum", vm)):
+        eye = np.eye(V.shape[1])
+        dev = max(np.abs(b @ b.conj().T - eye).max() for b in V)
+        assert dev < 1e-10, (name, dev)
+
+
 @pytest.mark.parametrize("w", [synth.tfi_ring(8, 2, 1.0), synth.afh_torus(4, 4, 1, 1), synth.config_c2(1.5)[1]],
                          ids=lambda w: w.name)
 def test_warm_started_eigensolves_match_cold(vemb, w):
