@@ -149,7 +149,7 @@ __global__ void __launch_bounds__(NT) jacobi_kernel(Policy pol, int n, int max_s
     for (int i = tid; i < n; i += NT) {
       R rad = R(0);
       for (int j = 0; j < n; ++j)
-        if (j != i) rad += modulus(W[j * LD + i]);
+        if (j != i) rad += modulus_fast(W[j * LD + i]);
       R d = re_part(W[i * LD + i]);
       R e = rad - d;
       v = e > v ? e : v;
@@ -264,7 +264,9 @@ __global__ void __launch_bounds__(NT) jacobi_kernel(Policy pol, int n, int max_s
       // squared column norms, recomputed exactly once per sweep and carried through the
       // rotations in between (|w_p'|^2 = |w_p|^2 - t|gamma|, |w_q'|^2 = |w_q|^2 + t|gamma|),
       // so a round reduces only the inner products
-      R relmax = R(0);
+      // largest rotated |gamma| / sqrt(alpha beta) of the sweep, kept as a fraction (num / den) so a
+      // round needs no division for it
+      R rnum = R(0), rden = R(1);
       if (tid == 0) rotated = 0;
       for (int j = tid; j < n; j += NT) {
         R s2 = R(0);
@@ -272,13 +274,16 @@ __global__ void __launch_bounds__(NT) jacobi_kernel(Policy pol, int n, int max_s
         cn[j] = s2;
       }
       __syncthreads();
-      for (int round = 0; round < np - 1; ++round) {
-        int p = 0, q = 0;
-        bool live = g < npair;
-        if (live) {
-          rr_pair(round, g, np, p, q);
-          live = p < n && q < n;
+      // the slot's pair of round 0, advanced by one (mod np - 1) per round: the circle method
+      int p = 0, q = 0;
+      if (g < npair) rr_pair(0, g, np, p, q);
+      const int kk = np - 1;
+      for (int round = 0; round < kk; ++round) {
+        if (round > 0 && g < npair) {
+          if (g > 0) p = p + 1 == kk ? 0 : p + 1;
+          q = q + 1 == kk ? 0 : q + 1;
         }
+        const bool live = g < npair && p < n && q < n;
         S a[RPL], b[RPL];
         S gam = s_zero<S>();
   #pragma unroll
@@ -299,7 +304,10 @@ __global__ void __launch_bounds__(NT) jacobi_kernel(Policy pol, int n, int max_s
         const R small = alpha < beta ? alpha : beta;
         const R gab = dev_sqrt(alpha * beta);
         if (live && small > floor2 && ag > tol * gab && ag > R(0)) {
-          relmax = ag > relmax * gab ? ag / gab : relmax;
+          if (ag * rden > rnum * gab) {
+            rnum = ag;
+            rden = gab;
+          }
           const R inv_ag = R(1) / ag;
           const R zeta = (beta - alpha) * (R(0.5) * inv_ag);
           const R az = dev_abs(zeta);
@@ -335,7 +343,7 @@ __global__ void __launch_bounds__(NT) jacobi_kernel(Policy pol, int n, int max_s
       const int any = rotated;
       __syncthreads();
       if (!any) break;
-      if (block_max(relmax, red) < early) {
+      if (block_max(rnum / rden, red) < early) {
         ++sweep;
         break;
       }
