@@ -64,14 +64,26 @@ __device__ double rhs_value(const StepArgs& A, int pd, int i, int j) {
 // ---------------------------------------------------------------------------
 // Steps 1-2 and X'_0d.  One workgroup per offset d.
 // ---------------------------------------------------------------------------
+// Pair blocks up to this size stage R in LDS: it is formed once (coalesced reads of every input)
+// and the partial traces and the update read it from there; larger blocks form each entry of R
+// where it is needed.
+constexpr int kStageN = 64;
+
 __device__ void pair_update_body(const StepArgs& A, int bx) {
   const int pd = bx;  // offset d = pd + 1
   const int m = A.m, n = A.n, mm = m * m;
   const int tid = threadIdx.x;
   __shared__ double T2[kMaxM * kMaxM];  // Tr_2 R
   __shared__ double T1[kMaxM * kMaxM];  // Tr_1 R
+  __shared__ double Rs[kStageN * kStageN];
   __shared__ double red[kBlock];
   __shared__ double trR_s;
+  const bool staged = n <= kStageN;
+  if (staged) {
+    for (int idx = tid; idx < n * n; idx += kBlock) Rs[idx] = rhs_value(A, pd, idx / n, idx % n);
+    __syncthreads();
+  }
+  auto R = [&](int i, int j) { return staged ? Rs[i * n + j] : rhs_value(A, pd, i, j); };
 
   // partial traces of R: Tr_2 R(x,x') = sum_y R(xy, x'y); Tr_1 R(y,y') = sum_x R(xy, xy')
   for (int e = tid; e < 2 * mm; e += kBlock) {
@@ -79,9 +91,9 @@ __device__ void pair_update_body(const StepArgs& A, int bx) {
     double acc = 0.0;
     for (int k = 0; k < m; ++k) {
       if (which == 0)
-        acc += rhs_value(A, pd, u * m + k, w * m + k);
+        acc += R(u * m + k, w * m + k);
       else
-        acc += rhs_value(A, pd, k * m + u, k * m + w);
+        acc += R(k * m + u, k * m + w);
     }
     if (which == 0)
       T2[u * m + w] = acc;
@@ -104,7 +116,7 @@ __device__ void pair_update_body(const StepArgs& A, int bx) {
   for (int idx = tid; idx < n * n; idx += kBlock) {
     const int i = idx / n, j = idx % n;
     const int x = i / m, y = i % m, xp = j / m, yp = j % m;
-    double v = a * rhs_value(A, pd, i, j);
+    double v = a * R(i, j);
     double corr = 0.0;
     if (y == yp) corr += T2[x * m + xp];
     if (x == xp) corr += T1[y * m + yp];
