@@ -214,7 +214,8 @@ enum vemb_kernel_id {
   VEMB_K_DFT_INV = 6,      /* step 9 */
   VEMB_K_BOUND_BUILD = 7,  /* bound matrices */
   VEMB_K_LMIN = 8,         /* bound eigenvalues */
-  VEMB_K_COUNT = 9
+  VEMB_K_PROJ = 9,         /* steps 3 and 8 in one launch (FP64 blocks of 33..64 with matching solver variants) */
+  VEMB_K_COUNT = 10
 };
 typedef struct {
   double ms[VEMB_K_COUNT];

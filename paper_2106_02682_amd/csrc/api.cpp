@@ -426,6 +426,13 @@ int vemb_problem_info(const vemb_problem* p, vemb_info* info) {
 }
 
 namespace {
+// FP64 iterations with pair and momentum blocks of 33..64 that the autotuner gave the same LDS solver
+// variant run both projections in one launch.
+bool fused_projections(const vemb_problem* p, int prec) {
+  return prec == VEMB_FP64 && !p->sign_pair && !p->sign_mom && fused_projection_fits(p->a.n, p->a.n_op) &&
+         p->tpb_pair == kFusedThreads && p->tpb_mom == kFusedThreads;
+}
+
 int run_iterations(vemb_problem* p, int iters, int prec) {
   const StepArgs& a = p->a;
   hipStream_t s = p->stream;
@@ -435,6 +442,19 @@ int run_iterations(vemb_problem* p, int iters, int prec) {
     const int cold = (!p->v_valid || refresh < 0 || p->t % refresh == 0) ? 1 : 0;
     VEMB_TRY(timed(p, VEMB_K_PAIR_UPDATE, "pair update", [&] { return launch_pair_update(a, s); }));
     VEMB_TRY(timed(p, VEMB_K_PAIR_XSTEP, "pair X step", [&] { return launch_pair_xstep(a, s); }));
+    if (fused_projections(p, prec)) {
+      // both projections in one launch after the forward DFT: one stream, no fork and join
+      VEMB_TRY(timed(p, VEMB_K_CLUSTER, "cluster update", [&] { return launch_cluster_update(a, s); }));
+      VEMB_TRY(timed(p, VEMB_K_DFT_FWD, "forward DFT", [&] { return launch_dft_forward(a, s); }));
+      VEMB_TRY(timed(p, VEMB_K_PROJ, "projections", [&] {
+        return launch_projections_fused(a.rho, a.Lam, a.rho_t, a.feas, a.n, a.P, a.mu, a.Xh, a.n_op, a.Ku, ms,
+                                        a.sweeps, a.Vpair, a.Vmom, cold, s);
+      }));
+      VEMB_TRY(timed(p, VEMB_K_DFT_INV, "inverse DFT", [&] { return launch_dft_inverse(a, s); }));
+      p->v_valid = true;
+      ++p->t;
+      continue;
+    }
     // fork: pair projection on the side stream (reads rho, Lambda; writes rho_t,
     // Lambda, feas, Vpair -- nothing the main branch touches)
     hipStream_t s2 = p->side;

@@ -34,9 +34,27 @@ namespace {
 // Core kernel.  S: compute scalar (double, float, cplx<double>, cplx<float>);
 // NMAX: capacity (n <= NMAX, NMAX even); Policy: load / store of one matrix.
 // ---------------------------------------------------------------------------
+// LDS layout of one solve (byte offsets, 16-byte aligned): W and V (n x n, padded columns), the
+// reduction buffers, the column norms, the active-column list and a few flags.
+constexpr size_t lds_align(size_t b) { return (b + 15) & ~size_t(15); }
+template <typename S, int NMAX, bool WARM, int NT>
+struct JacobiLds {
+  using R = typename scalar_traits<S>::real;
+  static constexpr int LD = NMAX + 1;
+  static constexpr size_t oV = lds_align(sizeof(S) * NMAX * LD);
+  static constexpr size_t oRed = lds_align(oV + sizeof(S) * (WARM ? NMAX * LD : 1));
+  static constexpr size_t oRedD = lds_align(oRed + sizeof(R) * NT);
+  static constexpr size_t oColf = lds_align(oRedD + sizeof(double) * NT);
+  static constexpr size_t oCn = lds_align(oColf + sizeof(R) * NMAX);
+  static constexpr size_t oAct = lds_align(oCn + sizeof(R) * NMAX);
+  static constexpr size_t oInts = lds_align(oAct + sizeof(int) * NMAX);  // nact, rotated, 8 wavefront flags
+  static constexpr size_t bytes = lds_align(oInts + sizeof(int) * 10);
+};
+
+// One matrix (index mat of the policy) per workgroup, in the LDS area smem (JacobiLds bytes).
 template <typename S, int NMAX, int MODE, bool WARM, int NT, typename Policy, bool REG = false>
-__global__ void __launch_bounds__(NT) jacobi_kernel(Policy pol, int n, int max_sweeps, void* vstore_raw,
-                                                          int cold) {
+__device__ __attribute__((always_inline)) void jacobi_body(Policy pol, int n, int max_sweeps, void* vstore_raw,
+                                                           int cold, const int mat, unsigned char* smem) {
   static_assert(!REG || (NMAX == 64 && (NT == 256 || NT == 512)), "register-resident sweeps: n = 64, 4 or 8 waves");
   using R = typename scalar_traits<S>::real;
   using D = typename wide<S>::type;  // FP64 storage type of V
@@ -52,18 +70,19 @@ __global__ void __launch_bounds__(NT) jacobi_kernel(Policy pol, int n, int max_s
   // identity instead, which makes its next solve cold.  Half of every round's LDS traffic and
   // arithmetic (the V columns) goes away.
   constexpr bool VFW = WARM && MODE == kProject && !REG;
-  __shared__ S W[NMAX * LD];
-  __shared__ S V[WARM ? NMAX * LD : 1];
-  __shared__ R red[NT];
-  __shared__ double red_d[NT];
-  __shared__ R colf[NMAX];
-  __shared__ R cn[NMAX];  // squared column norms carried through a sweep
-  __shared__ int active[NMAX];
-  __shared__ int nact_s;
-  __shared__ int rotated;
-  __shared__ int rr_flags[8];
+  using L = JacobiLds<S, NMAX, WARM, NT>;
+  S* const W = reinterpret_cast<S*>(smem);
+  S* const V = reinterpret_cast<S*>(smem + L::oV);
+  R* const red = reinterpret_cast<R*>(smem + L::oRed);
+  double* const red_d = reinterpret_cast<double*>(smem + L::oRedD);
+  R* const colf = reinterpret_cast<R*>(smem + L::oColf);
+  R* const cn = reinterpret_cast<R*>(smem + L::oCn);  // squared column norms carried through a sweep
+  int* const active = reinterpret_cast<int*>(smem + L::oAct);
+  int* const ints = reinterpret_cast<int*>(smem + L::oInts);
+  int& nact_s = ints[0];
+  int& rotated = ints[1];
+  int* const rr_flags = ints + 2;
 
-  const int mat = blockIdx.x;
   const int tid = threadIdx.x;
   const int nn = n * n;
   constexpr int NOUT = (NMAX * NMAX + NT - 1) / NT;
@@ -450,6 +469,28 @@ __global__ void __launch_bounds__(NT) jacobi_kernel(Policy pol, int n, int max_s
   }
 }
 
+template <typename S, int NMAX, int MODE, bool WARM, int NT, typename Policy, bool REG = false>
+__global__ void __launch_bounds__(NT) jacobi_kernel(Policy pol, int n, int max_sweeps, void* vstore_raw, int cold) {
+  __shared__ __attribute__((aligned(16))) unsigned char smem[JacobiLds<S, NMAX, WARM, NT>::bytes];
+  jacobi_body<S, NMAX, MODE, WARM, NT, Policy, REG>(pol, n, max_sweeps, vstore_raw, cold, blockIdx.x, smem);
+}
+
+// The pair and momentum projections of one iteration in one launch: workgroups below P take the
+// (real) pair blocks, the rest the (complex) momentum blocks, both warm-started FP64 solves of
+// blocks of 33..64 with NT threads.  The two sets touch disjoint data, and one launch on one stream
+// needs no fork and join between streams.
+template <int NT>
+__global__ void __launch_bounds__(NT) fused_projection_kernel(PairPolicy pp, int n, int P, MomentumPolicy mp, int n_op,
+                                                              int max_sweeps, void* vpair, void* vmom, int cold) {
+  constexpr size_t bp = JacobiLds<double, 64, true, NT>::bytes, bm = JacobiLds<cplx<double>, 64, true, NT>::bytes;
+  __shared__ __attribute__((aligned(16))) unsigned char smem[bp > bm ? bp : bm];
+  if ((int)blockIdx.x < P)
+    jacobi_body<double, 64, kProject, true, NT, PairPolicy>(pp, n, max_sweeps, vpair, cold, blockIdx.x, smem);
+  else
+    jacobi_body<cplx<double>, 64, kProject, true, NT, MomentumPolicy>(mp, n_op, max_sweeps, vmom, cold,
+                                                                       (int)blockIdx.x - P, smem);
+}
+
 // vstore == nullptr: cold solve without eigenvector storage.  Otherwise the
 // eigenvectors of every matrix slot are read (unless cold) and written back.
 // tpb: threads per workgroup (256, 512 or 1024; others fall back to 256).  More
@@ -531,6 +572,17 @@ hipError_t launch_momentum_projection(double* Xh, int n_op, int K, int precision
   MomentumPolicy pol{Xh, sweeps, n_op};
   MomentumPolicy quiet{Xh, nullptr, n_op};
   return by_precision<cplx<float>, cplx<double>>(pol, quiet, n_op, K, precision, max_sweeps, vstore, cold, tpb, st);
+}
+
+hipError_t launch_projections_fused(const double* rho, double* Lam, double* rho_t, double* feas, int n, int P,
+                                   double mu, double* Xh, int n_op, int K, int max_sweeps, int* sweeps, double* vpair,
+                                   double* vmom, int cold, hipStream_t st) {
+  if (!fused_projection_fits(n, n_op) || !vpair || !vmom || P <= 0 || K <= 0) return hipErrorInvalidValue;
+  PairPolicy pp{rho, Lam, rho_t, feas, sweeps, n, mu};
+  MomentumPolicy mp{Xh, sweeps + P, n_op};
+  hipLaunchKernelGGL(fused_projection_kernel<kFusedThreads>, dim3(P + K), dim3(kFusedThreads), 0, st, pp, n, P, mp,
+                     n_op, max_sweeps, vpair, vmom, cold);
+  return hipGetLastError();
 }
 
 hipError_t launch_psd_batched(const double* in, double* out, int n, int batch, bool is_complex, int precision,

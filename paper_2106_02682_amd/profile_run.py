@@ -31,6 +31,7 @@ COPY_BYTES = 256 << 20
 TRAFFIC_KERNELS = [
     ("momentum_projection", r"jacobi_kernel<vemb::cplx<double>, 64, 0, true, \d+, vemb::\(anonymous namespace\)::MomentumPolicy"),
     ("pair_projection", r"jacobi_kernel<double, 64, 0, true, \d+, vemb::\(anonymous namespace\)::PairPolicy"),
+    ("projections", r"fused_projection_kernel<\d+>"),
     ("pair_update", r"pair_update_kernel"), ("pair_xstep", r"pair_xstep_kernel"),
     ("cluster_update", r"cluster_update_kernel"), ("dft_forward", r"dft_mfma_kernel<true>"),
     ("dft_inverse", r"dft_mfma_kernel<false>")]

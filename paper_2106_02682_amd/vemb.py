@@ -39,7 +39,7 @@ EXPORTS = [
     "vemb_dense_set_state", "vemb_dense_last_sweeps", "vemb_dense_destroy", "vemb_psd_project_sign",
 ]
 KERNELS = ["pair_update", "pair_xstep", "pair_projection", "cluster_update", "dft_forward", "momentum_projection",
-           "dft_inverse", "bound_build", "lambda_min"]
+           "dft_inverse", "bound_build", "lambda_min", "projections"]
 
 
 class VembError(RuntimeError):
@@ -82,7 +82,7 @@ _DP = ctypes.POINTER(ctypes.c_double)
 
 
 class vemb_profile(ctypes.Structure):
-    _fields_ = [("ms", ctypes.c_double * 9), ("launches", ctypes.c_int64 * 9)]
+    _fields_ = [("ms", ctypes.c_double * 10), ("launches", ctypes.c_int64 * 10)]
 
 
 class vemb_state(ctypes.Structure):

@@ -239,6 +239,28 @@ def test_state_roundtrip_and_resume(vemb, w):
     assert sb["t"] == 50
 
 
+def test_fused_projections_match_separate_launches(vemb):
+    """With both eigensolvers on 512 threads the pair and momentum projections run as one launch on one
+    stream; forced to 1024 threads they run as two launches on two streams.  The iterates agree to the
+    rounding of the different lane groupings."""
+    from paper_2106_02682_amd import vemb as v
+
+    w = synth.config_c2(1.0)[1]
+    with v.Problem.from_workload(w, tpb=512) as a, v.Problem.from_workload(w, tpb=1024) as b:
+        a.set_profiling(True)
+        b.set_profiling(True)
+        a.step(20)
+        b.step(20)
+        pa, pb = a.get_profile(), b.get_profile()
+        sa, sb = a.get_state(), b.get_state()
+        la, lb = a.dual_bound(), b.dual_bound()
+    assert pa["projections"][1] == 20 and pa["pair_projection"][1] == 0 and pa["momentum_projection"][1] == 0
+    assert pb["projections"][1] == 0 and pb["pair_projection"][1] == 20 and pb["momentum_projection"][1] == 20
+    for k in ("X", "rho0", "rho_t", "Lam", "Lam1", "Lam2"):
+        assert np.abs(sa[k] - sb[k]).max() < 1e-9, k
+    assert abs(la - lb) < 1e-10 * abs(lb)
+
+
 @pytest.mark.parametrize("w", [synth.tfi_ring(8, 2, 1.0), synth.afh_torus(4, 4, 1, 1), synth.config_c2(1.0)[1]],
                          ids=lambda w: w.name)
 def test_kept_eigenvectors_orthonormal(vemb, w):
