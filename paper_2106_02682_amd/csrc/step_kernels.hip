@@ -68,25 +68,29 @@ __device__ double rhs_value(const StepArgs& A, int pd, int i, int j) {
 // and the partial traces and the update read it from there; larger blocks form each entry of R
 // where it is needed.
 constexpr int kStageN = 64;
+// Threads of a pair-update workgroup: four entries of a 64 x 64 block per thread keep enough loads
+// in flight (the step is bound by memory latency, one workgroup per pair).
+constexpr int kPairThreads = 1024;
 
 __device__ void pair_update_body(const StepArgs& A, int bx) {
+  constexpr int NT = kPairThreads;
   const int pd = bx;  // offset d = pd + 1
   const int m = A.m, n = A.n, mm = m * m;
   const int tid = threadIdx.x;
   __shared__ double T2[kMaxM * kMaxM];  // Tr_2 R
   __shared__ double T1[kMaxM * kMaxM];  // Tr_1 R
   __shared__ double Rs[kStageN * kStageN];
-  __shared__ double red[kBlock];
+  __shared__ double red[NT];
   __shared__ double trR_s;
   const bool staged = n <= kStageN;
   if (staged) {
-    for (int idx = tid; idx < n * n; idx += kBlock) Rs[idx] = rhs_value(A, pd, idx / n, idx % n);
+    for (int idx = tid; idx < n * n; idx += NT) Rs[idx] = rhs_value(A, pd, idx / n, idx % n);
     __syncthreads();
   }
   auto R = [&](int i, int j) { return staged ? Rs[i * n + j] : rhs_value(A, pd, i, j); };
 
   // partial traces of R: Tr_2 R(x,x') = sum_y R(xy, x'y); Tr_1 R(y,y') = sum_x R(xy, xy')
-  for (int e = tid; e < 2 * mm; e += kBlock) {
+  for (int e = tid; e < 2 * mm; e += NT) {
     const int which = e / mm, u = (e % mm) / m, w = e % m;
     double acc = 0.0;
     for (int k = 0; k < m; ++k) {
@@ -113,7 +117,7 @@ __device__ void pair_update_body(const StepArgs& A, int bx) {
   // rho = a R + (b/m)(Tr_2 R x I + I x Tr_1 R) + (c/m^2) Tr R I, and Tr(H_0d rho)
   const int h = A.hd_index[pd];
   double epart = 0.0;
-  for (int idx = tid; idx < n * n; idx += kBlock) {
+  for (int idx = tid; idx < n * n; idx += NT) {
     const int i = idx / n, j = idx % n;
     const int x = i / m, y = i % m, xp = j / m, yp = j % m;
     double v = a * R(i, j);
@@ -127,14 +131,14 @@ __device__ void pair_update_body(const StepArgs& A, int bx) {
   }
   // A_1 rho = (a + b) Tr_2 R + ((b + c)/m) Tr R I ;  A_2 rho likewise with Tr_1 R
   const double ab = A.a + A.b, bc = (A.b + A.c) / m * trR;
-  for (int e = tid; e < mm; e += kBlock) {
+  for (int e = tid; e < mm; e += NT) {
     const int u = e / m, w = e % m;
     A.tr2[(size_t)pd * mm + e] = ab * T2[e] + (u == w ? bc : 0.0);
     A.tr1[(size_t)pd * mm + e] = ab * T1[e] + (u == w ? bc : 0.0);
   }
   red[tid] = epart;
   __syncthreads();
-  for (int s = kBlock / 2; s > 0; s >>= 1) {
+  for (int s = NT / 2; s > 0; s >>= 1) {
     if (tid < s) red[tid] += red[tid + s];
     __syncthreads();
   }
@@ -338,11 +342,11 @@ __global__ void __launch_bounds__(kBlock) dft_mfma_kernel(StepArgs A) {
 
 // Single-instance kernels and batched kernels.  A batched launch covers every
 // instance of a batch: work[blockIdx.x] names the instance and its local block.
-__global__ void __launch_bounds__(kBlock) pair_update_kernel(StepArgs A) { pair_update_body(A, blockIdx.x); }
+__global__ void __launch_bounds__(kPairThreads) pair_update_kernel(StepArgs A) { pair_update_body(A, blockIdx.x); }
 __global__ void __launch_bounds__(kBlock) pair_xstep_kernel(StepArgs A) { pair_xstep_body(A, blockIdx.x, blockIdx.y); }
 __global__ void __launch_bounds__(kClusterBlock) cluster_update_kernel(StepArgs A) { cluster_update_body(A); }
 
-__global__ void __launch_bounds__(kBlock) pair_update_batched(const StepArgs* args, const WorkItem* work) {
+__global__ void __launch_bounds__(kPairThreads) pair_update_batched(const StepArgs* args, const WorkItem* work) {
   const WorkItem w = work[blockIdx.x];
   pair_update_body(args[w.inst], w.bx);
 }
@@ -400,7 +404,7 @@ __global__ void __launch_bounds__(kBlock) bound_cluster_kernel(StepArgs A) {
 }  // namespace
 
 hipError_t launch_pair_update(const StepArgs& a, hipStream_t st) {
-  hipLaunchKernelGGL(pair_update_kernel, dim3(a.P), dim3(kBlock), 0, st, a);
+  hipLaunchKernelGGL(pair_update_kernel, dim3(a.P), dim3(kPairThreads), 0, st, a);
   return hipGetLastError();
 }
 
@@ -446,7 +450,7 @@ hipError_t launch_step_batched(int which, const StepArgs* args, const WorkItem* 
   if (nwork <= 0) return hipSuccess;
   switch (which) {
     case 0:
-      hipLaunchKernelGGL(pair_update_batched, dim3(nwork), dim3(kBlock), 0, st, args, work);
+      hipLaunchKernelGGL(pair_update_batched, dim3(nwork), dim3(kPairThreads), 0, st, args, work);
       break;
     case 1:
       hipLaunchKernelGGL(pair_xstep_batched, dim3(nwork), dim3(kBlock), 0, st, args, work);
