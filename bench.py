@@ -276,6 +276,7 @@ def main():
                     help="c2b: the N=384 ring (default); c4: the 64-instance batched sweep; dense: Algorithm 5 "
                          "on a disordered ring; tune: the per-family parameter race")
     ap.add_argument("--lb-every", type=int, default=10)
+    ap.add_argument("--prof-every", type=int, default=10, help="time the eigensolver launch on every N-th iteration")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="oracle sample length (0 disables)")
     ap.add_argument("--warm", type=int, default=1, help="run the learned warm-start leg (0 skips it)")
     ap.add_argument("--warm-train", type=int, default=256)
@@ -312,10 +313,12 @@ def main():
     log(f"throughput: {w.name}, {args.warmup} warm-up + {args.steps} timed steps")
     g.step(args.warmup)
     torch.cuda.synchronize()
-    # time the two eigensolver kernels (the roofline's candidates) with HIP events; the
-    # diagnostics are queued on the stream and collected one interval later, so the
-    # stream never drains inside the timed region
+    # time the eigensolver launches (the roofline's candidates) with HIP events on every
+    # prof_every-th iteration (each timed launch adds two event packets, ~8 us each on the GPU's
+    # timeline); the diagnostics are queued on the stream and collected one interval later, so
+    # the stream never drains inside the timed region
     g.set_profiling(True, kernels=list(PROJ_KERNELS))
+    g.set_profiling_every(args.prof_every)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     lb = e = feas = None
@@ -351,6 +354,8 @@ def main():
         "frac": achieved / peak,
         "traffic": measured_traffic(dom, args.precision),
         "avg_launch_ms": avg_s * 1e3,
+        "timed_launches": launches,
+        "timed_every": args.prof_every,
     }
     out = {
         "metric": METRIC,

@@ -226,6 +226,11 @@ int vemb_set_profiling(vemb_problem* p, int enable);
 /* As vemb_set_profiling with a bit mask of the kernels to time (bit vemb_kernel_id);
  * 0 turns timing off.  Fewer events per iteration disturb the timed run less. */
 int vemb_set_profiling_mask(vemb_problem* p, uint32_t kernels);
+/* Times only the iterations whose index t (iterations done so far on the problem) is a multiple of
+ * `every` (>= 1; default 1, every iteration): each timed launch adds two event packets to the
+ * stream, and sampling keeps their cost out of most iterations.  Errors: VEMB_E_INVALID for a NULL
+ * problem or every < 1. */
+int vemb_set_profiling_every(vemb_problem* p, int every);
 int vemb_get_profile(vemb_problem* p, vemb_profile* out);
 
 /* Autotuner of the LDS eigensolver variant (256 / 512 / 1024 threads, and the

@@ -90,7 +90,7 @@ template <typename F>
 int timed(vemb_problem* p, int id, const char* what, F&& launch, hipStream_t st = nullptr) {
   if (!st) st = p->stream;
   hipEvent_t a = nullptr, b = nullptr;
-  const bool on = p->profiling && ((p->prof_mask >> id) & 1u);
+  const bool on = p->profiling && ((p->prof_mask >> id) & 1u) && p->t % p->prof_every == 0;
   if (on) {
     a = take_event(p);
     b = take_event(p);
@@ -801,6 +801,12 @@ int vemb_set_profiling(vemb_problem* p, int enable) {
 int vemb_set_profiling_mask(vemb_problem* p, uint32_t kernels) {
   VEMB_TRY(vemb_set_profiling(p, kernels != 0));
   p->prof_mask = kernels;
+  return VEMB_OK;
+}
+
+int vemb_set_profiling_every(vemb_problem* p, int every) {
+  if (!p || every < 1) return fail(VEMB_E_INVALID, "bad arguments to vemb_set_profiling_every");
+  p->prof_every = every;
   return VEMB_OK;
 }
 

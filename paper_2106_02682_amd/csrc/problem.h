@@ -31,6 +31,7 @@ struct vemb_problem {
   // kernel timing (vemb_set_profiling)
   bool profiling = false;
   uint32_t prof_mask = 0;  // kernels timed (bit per vemb_kernel_id)
+  int prof_every = 1;      // timed iterations: those with t a multiple of prof_every
   // asynchronous diagnostics: pinned host copies [lmin (P+1) | e_pair (P) | feas (P) | scal (4)]
   double* diag_host = nullptr;
   hipEvent_t diag_ev = nullptr;

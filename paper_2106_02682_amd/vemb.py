@@ -37,6 +37,7 @@ EXPORTS = [
     "vemb_diagnostics_collect", "vemb_set_profiling_mask", "vemb_dense_create", "vemb_dense_get_info",
     "vemb_dense_step", "vemb_dense_dual_bound", "vemb_dense_primal_energy", "vemb_dense_get_state",
     "vemb_dense_set_state", "vemb_dense_last_sweeps", "vemb_dense_destroy", "vemb_psd_project_sign",
+    "vemb_set_profiling_every",
 ]
 KERNELS = ["pair_update", "pair_xstep", "pair_projection", "cluster_update", "dft_forward", "momentum_projection",
            "dft_inverse", "bound_build", "lambda_min", "projections"]
@@ -132,6 +133,7 @@ def lib():
     L.vemb_diagnostics_enqueue.argtypes = [vp]
     L.vemb_diagnostics_collect.argtypes = [vp, _DP, _DP, _DP]
     L.vemb_set_profiling_mask.argtypes = [vp, ctypes.c_uint32]
+    L.vemb_set_profiling_every.argtypes = [vp, ctypes.c_int]
     L.vemb_marginals.argtypes = [vp, ctypes.c_int, _DP, _DP]
     L.vemb_get_state.argtypes = [vp, ctypes.POINTER(vemb_state)]
     L.vemb_set_state.argtypes = [vp, ctypes.POINTER(vemb_state)]
@@ -462,6 +464,10 @@ class Problem:
 
     def get_profile(self):
         return get_profile(self.h)
+
+    def set_profiling_every(self, every):
+        """Time only every `every`-th iteration (see set_profiling)."""
+        _check(lib().vemb_set_profiling_every(self.h, int(every)))
 
     def primal_energy(self):
         return primal_energy(self.h)
