@@ -239,6 +239,24 @@ def test_state_roundtrip_and_resume(vemb, w):
     assert sb["t"] == 50
 
 
+def test_sampled_kernel_timing(vemb):
+    """With timing on every 5th iteration, 20 iterations time 4 launches of each timed kernel;
+    a step count below 1 is rejected."""
+    from paper_2106_02682_amd import vemb as v
+
+    with v.Problem.from_workload(synth.tfi_ring(8, 2, 1.0)) as g:
+        g.step(3)
+        g.set_profiling(True, kernels=["pair_update", "cluster_update"])
+        g.set_profiling_every(5)
+        g.step(20)  # iterations 3..22: t = 5, 10, 15, 20 are timed
+        prof = g.get_profile()
+        with pytest.raises(v.VembError):
+            g.set_profiling_every(0)
+    assert prof["pair_update"][1] == 4 and prof["cluster_update"][1] == 4
+    assert prof["pair_xstep"][1] == 0
+    assert prof["pair_update"][0] > 0
+
+
 def test_fused_projections_match_separate_launches(vemb):
     """With both eigensolvers on 512 threads the pair and momentum projections run as one launch on one
     stream; forced to 1024 threads they run as two launches on two streams.  The iterates agree to the
