@@ -327,12 +327,13 @@ __device__ __attribute__((always_inline)) void jacobi_body(Policy pol, int n, in
             rnum = ag;
             rden = gab;
           }
-          const R inv_ag = R(1) / ag;
+          const R inv_ag = rcp_nr(ag);
           const R zeta = (beta - alpha) * (R(0.5) * inv_ag);
           const R az = dev_abs(zeta);
-          R t = R(1) / (az + dev_sqrt(R(1) + zeta * zeta));
+          const R z2 = R(1) + zeta * zeta;
+          R t = rcp_nr(az + z2 * rsqrt_nr(z2));
           if (zeta < R(0)) t = -t;
-          const R c = R(1) / dev_sqrt(R(1) + t * t);
+          const R c = rsqrt_nr(R(1) + t * t);
           const R s = c * t;
           const S ph = conj_phase_inv(gam, inv_ag);  // conj(e)
           if (l == 0) {

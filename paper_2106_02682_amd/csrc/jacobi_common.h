@@ -84,6 +84,23 @@ template <typename R> __device__ inline R modulus(cplx<R> a) {
   return big * dev_sqrt(xs * xs + ys * ys);
 }
 
+// 1/x and 1/sqrt(x) for the rotation parameters: the hardware estimates (v_rcp_f64, v_rsq_f64)
+// refined by two Newton steps each (the error squares per step), instead of the correctly rounded
+// division and square root sequences.  x > 0 and normal (the callers' arguments are at least 1 or a
+// rotated |gamma| above the noise floor).  FP32 keeps the library operations.
+__device__ inline double rcp_nr(double x) {
+  double y = __builtin_amdgcn_rcp(x);
+  y = fma(y, fma(-x, y, 1.0), y);
+  return fma(y, fma(-x, y, 1.0), y);
+}
+__device__ inline float rcp_nr(float x) { return 1.0f / x; }
+__device__ inline double rsqrt_nr(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  y = fma(0.5 * y, fma(-x * y, y, 1.0), y);
+  return fma(0.5 * y, fma(-x * y, y, 1.0), y);
+}
+__device__ inline float rsqrt_nr(float x) { return 1.0f / sqrtf(x); }
+
 // |a| without the rescaling where the squares can neither overflow nor underflow.
 template <typename R> struct square_safe;
 template <> struct square_safe<double> { static constexpr double lo = 0x1p-500, hi = 0x1p500; };
