@@ -275,6 +275,17 @@ int vemb_psd_project_batched_ex(const double* in, double* out, int n, int batch,
  * 1e-14 ||A||_F resolved.  Allocates 4 n^2 + 64 doubles of scratch for the call and synchronises
  * hip_stream.  Errors: VEMB_E_INVALID, VEMB_E_NOMEM, VEMB_E_HIP. */
 int vemb_psd_project_sign(const double* in, double* out, int n, void* hip_stream);
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): vemb_psd_project_sign without any allocation.  Same arguments,
+ * result and kernels; n a positive multiple of 16, at most 512 (VEMB_E_INVALID beyond, with a
+ * message).  The scratch (4 n^2 + 64 doubles) lives in a static device array of 4 * 512^2 + 64
+ * doubles (8 MiB) that each GPU the call runs on holds until the process ends; its device address
+ * is looked up once per device on the first call.  Nothing in it needs to start at zero: each call
+ * writes every scratch word it reads.  Asynchronous on hip_stream (it does not synchronise).  Every
+ * call on one GPU shares that GPU's array, so calls that overlap on one GPU (different streams or
+ * host threads without ordering) race and give wrong results: order them, e.g. on one stream.
+ * Errors: VEMB_E_INVALID, VEMB_E_HIP. */
+int vemb_psd_project_sign_noalloc(const double* in, double* out, int n, void* hip_stream);
 int vemb_eigvalsh_batched(const double* in, double* w, int n, int batch, int is_complex, void* hip_stream);
 
 /* ---- Batches: many independent problems stepped together --------------------

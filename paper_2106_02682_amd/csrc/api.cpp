@@ -899,6 +899,18 @@ int vemb_psd_project_sign(const double* in, double* out, int n, void* hip_stream
   return rc;
 }
 
+int vemb_psd_project_sign_noalloc(const double* in, double* out, int n, void* hip_stream) {
+  if (!in || !out) return fail(VEMB_E_INVALID, "NULL argument");
+  if (n <= 0 || n % 16) return fail(VEMB_E_INVALID, "n must be a positive multiple of 16");
+  if (n > kStaticSignMaxN)
+    return fail(VEMB_E_INVALID, "n = " + std::to_string(n) + " exceeds the static scratch limit of " +
+                                    std::to_string(kStaticSignMaxN));
+  double* work = nullptr;
+  VEMB_TRY(hip_rc(static_sign_scratch(&work), "static scratch address"));
+  return hip_rc(launch_psd_project_ns(in, out, n, work, ns_schedule_resolved(), static_cast<hipStream_t>(hip_stream)),
+                "sign projection");
+}
+
 int vemb_eigvalsh_batched(const double* in, double* w, int n, int batch, int is_complex, void* hip_stream) {
   if (!in || !w || n <= 0 || batch < 0) return fail(VEMB_E_INVALID, "bad arguments to vemb_eigvalsh_batched");
   if (n > 256) return fail(VEMB_E_UNSUPPORTED, "matrices above 256 x 256 are not supported");

@@ -19,4 +19,16 @@ hipError_t launch_psd_project_ns(const double* in, double* out, int ld, double* 
 // Resolved fraction used by the library: eigenvalues below 1e-14 ||A||_F may stay partly unresolved.
 constexpr double kNsResolved = 1e-14;
 
+// The schedule for kNsResolved, computed once on the host.
+const std::vector<double>& ns_schedule_resolved();
+
+// Allocation-free projections: the largest matrix and the scratch words (4 n^2 + 64) they need.
+constexpr int kStaticSignMaxN = 512;
+constexpr size_t kStaticSignWords = 4 * (size_t)kStaticSignMaxN * kStaticSignMaxN + 64;
+constexpr int kMaxDevices = 64;
+
+// Device address of the current device's static scratch array (kStaticSignWords doubles), looked up
+// with hipGetSymbolAddress on the first call for each device and kept.
+hipError_t static_sign_scratch(double** ptr);
+
 }  // namespace vemb

@@ -16,6 +16,7 @@
 #include "polar.h"
 
 #include <cmath>
+#include <mutex>
 #include <vector>
 
 #include "mfma_tile.h"
@@ -124,7 +125,36 @@ void gemm(const double* P, const double* Q, const double* E, double* out, int ld
     hipLaunchKernelGGL(ns_gemm_kernel<4>, dim3(blocks), dim3(256), 0, st, P, Q, E, out, ld, c0, c1);
 }
 
+// Scratch of the allocation-free entry point: A, X, Y, T and the norm partials of one projection of
+// at most kStaticSignMaxN x kStaticSignMaxN, one copy per GPU, alive until the process ends.  Host
+// code never uses this name as an address (in host code it is a stand-in, not device memory): the
+// device address comes from hipGetSymbolAddress, once per device.
+static __device__ __align__(256) double scratch[kStaticSignWords];
+
 }  // namespace
+
+hipError_t static_sign_scratch(double** ptr) {
+  static std::mutex mu;
+  static double* addr[kMaxDevices] = {};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[dev]) {
+    double* p = nullptr;
+    e = hipGetSymbolAddress(reinterpret_cast<void**>(&p), HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    addr[dev] = p;
+  }
+  *ptr = addr[dev];
+  return hipSuccess;
+}
+
+const std::vector<double>& ns_schedule_resolved() {
+  static const std::vector<double> sched = ns_schedule(kNsResolved);
+  return sched;
+}
 
 std::vector<double> ns_schedule(double l0) {
   std::vector<double> a;

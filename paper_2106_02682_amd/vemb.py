@@ -37,7 +37,7 @@ EXPORTS = [
     "vemb_diagnostics_collect", "vemb_set_profiling_mask", "vemb_dense_create", "vemb_dense_get_info",
     "vemb_dense_step", "vemb_dense_dual_bound", "vemb_dense_primal_energy", "vemb_dense_get_state",
     "vemb_dense_set_state", "vemb_dense_last_sweeps", "vemb_dense_destroy", "vemb_psd_project_sign",
-    "vemb_set_profiling_every",
+    "vemb_set_profiling_every", "vemb_psd_project_sign_noalloc",
 ]
 KERNELS = ["pair_update", "pair_xstep", "pair_projection", "cluster_update", "dft_forward", "momentum_projection",
            "dft_inverse", "bound_build", "lambda_min", "projections"]
@@ -187,6 +187,7 @@ def lib():
     L.vemb_dense_last_sweeps.argtypes = [vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
     L.vemb_dense_destroy.argtypes = [vp]
     L.vemb_psd_project_sign.argtypes = [vp, vp, ctypes.c_int, vp]
+    L.vemb_psd_project_sign_noalloc.argtypes = [vp, vp, ctypes.c_int, vp]
     L.vemb_dense_destroy.restype = None
     for name in EXPORTS:
         if name not in ("vemb_default_options", "vemb_destroy", "vemb_last_error", "vemb_batch_destroy",
@@ -370,6 +371,15 @@ def psd_project_sign(inp, out, stream=None):
     n = inp.shape[-1]
     st = stream if stream is not None else current_stream()
     _check(lib().vemb_psd_project_sign(ctypes.c_void_p(inp.data_ptr()), ctypes.c_void_p(out.data_ptr()), n, st))
+
+
+def psd_project_sign_noalloc(inp, out, stream=None):
+    """As psd_project_sign, with the scratch in the library's static device array (n <= 512): no
+    allocation; asynchronous on the stream."""
+    n = inp.shape[-1]
+    st = stream if stream is not None else current_stream()
+    _check(lib().vemb_psd_project_sign_noalloc(ctypes.c_void_p(inp.data_ptr()), ctypes.c_void_p(out.data_ptr()), n,
+                                               st))
 
 
 def psd_project_batched_ex(inp, out, is_complex=False, precision="fp64", max_sweeps=0, sweeps=None, tpb=0,
