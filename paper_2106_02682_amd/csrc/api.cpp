@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <filesystem>
 #include <map>
 #include <mutex>
 #include <string>
@@ -157,14 +158,21 @@ void tune_store(const std::string& key, int v) {
   const std::string path = tune_path();
   if (path.empty()) return;
   const size_t slash = path.rfind('/');
-  if (slash != std::string::npos) {
-    const std::string dir = path.substr(0, slash);
-    std::string cmd_dir = dir;  // create the directory if missing (best effort)
-    (void)std::system(("mkdir -p '" + cmd_dir + "' 2>/dev/null").c_str());
+  if (slash != std::string::npos && slash > 0) {
+    // create the directory if missing; no shell is spawned
+    std::error_code ec;
+    std::filesystem::create_directories(path.substr(0, slash), ec);
+    if (ec) {
+      std::fprintf(stderr, "vemb: autotuner cache directory for %s: %s (result kept in memory)\n", path.c_str(),
+                   ec.message().c_str());
+      return;
+    }
   }
   if (FILE* f = std::fopen(path.c_str(), "a")) {
     std::fprintf(f, "%s %d\n", key.c_str(), v);
     std::fclose(f);
+  } else {
+    std::fprintf(stderr, "vemb: cannot append to the autotuner cache %s (result kept in memory)\n", path.c_str());
   }
 }
 

@@ -109,10 +109,18 @@ def test_pauli1_collection():
     assert np.isrealobj(ops)
 
 
-@pytest.mark.parametrize("opset,L,N", [("complete", 1, 6), ("complete", 2, 8), ("pauli1", 1, 6)])
-def test_global_matrix_of_true_marginals_is_psd(opset, L, N):
-    """For marginals of a real state, G is the Gram matrix of the O_{i,a} expectations: PSD."""
-    w = synth.tfi_ring(N, L, 0.8, opset)
+@pytest.mark.parametrize("model,opset,L,N", [
+    ("tfi", "complete", 1, 6), ("tfi", "complete", 2, 8), ("tfi", "pauli1", 1, 6),
+    ("xxz", "complete", 1, 6), ("xxz", "complete", 2, 8), ("xxz", "pauli1", 1, 6),
+    ("afh", "complete", 1, 6), ("afh", "complete", 1, 8), ("afh", "complete", 2, 6), ("afh", "complete", 2, 8),
+])
+def test_global_matrix_of_true_marginals_is_psd(model, opset, L, N):
+    """For marginals of a real state, G is the Gram matrix of the O_{i,a} expectations: PSD.
+
+    The XXZ (J_z = 0.5) and AFH (eq. AFH) ground states have off-diagonal XX + YY bonds, so their
+    marginals exercise the realignment G_0d on entries that the diagonal TFI bonds leave at zero."""
+    w = {"tfi": lambda: synth.tfi_ring(N, L, 0.8, opset), "xxz": lambda: synth.xxz_ring(N, L, 0.5, opset),
+         "afh": lambda: synth.xxz_ring(N, L, 1.0, opset)}[model]()
     p = Problem.from_workload(w)
     _, psi = exact.ground_state(w.terms, w.extent)
     rho0, rhos = exact.cluster_marginals(psi, w.extent, w.cluster)
