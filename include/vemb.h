@@ -316,6 +316,31 @@ int vemb_batch_dual_bounds(vemb_batch* b, double* lb_per_site, int* status);
 int vemb_batch_primal_energies(vemb_batch* b, double* e_per_site, double* feas_err);
 /* Number of eigensolver size classes and kernel launches per iteration. */
 int vemb_batch_info(const vemb_batch* b, int* classes, int* launches_per_iteration);
+/* Sampled kernel timing of a batch.  every >= 1: the iterations whose batch iteration index (counted
+ * from the batch's creation) is a multiple of `every` are enqueued directly instead of replaying the
+ * graph, with HIP events around each step kernel launch, each Jacobi class launch and each product
+ * launch of the sign-function projections, recorded on the stream the launch runs on; every = 0 turns
+ * timing off.  Resets the accumulated times.  vemb_batch_get_profile synchronises and returns the
+ * accumulated device milliseconds and launch counts per kernel id since the last reset.
+ * Errors: VEMB_E_INVALID (NULL batch, every < 0). */
+enum vemb_batch_kernel_id {
+  VEMB_BK_PAIR_UPDATE = 0,     /* steps 1-2, all instances in one launch */
+  VEMB_BK_PAIR_XSTEP = 1,      /* step 6, d != 0 */
+  VEMB_BK_CLUSTER = 2,         /* steps 4-5 + step 6, d = 0 */
+  VEMB_BK_DFT_FWD = 3,         /* step 7 */
+  VEMB_BK_DFT_INV = 4,         /* step 9 */
+  VEMB_BK_PAIR_JACOBI = 5,     /* a Jacobi pair-projection launch (one per size class) */
+  VEMB_BK_MOM_JACOBI = 6,      /* a Jacobi momentum-projection launch (one per size class) */
+  VEMB_BK_SIGN_GEMM_REAL = 7,  /* one product launch of the pair sign projections (all blocks of the class) */
+  VEMB_BK_SIGN_GEMM_CPLX = 8,  /* one product launch of the momentum sign projections */
+  VEMB_BK_COUNT = 9
+};
+typedef struct {
+  double ms[VEMB_BK_COUNT];
+  int64_t launches[VEMB_BK_COUNT];
+} vemb_batch_profile;
+int vemb_batch_set_profiling(vemb_batch* b, int every);
+int vemb_batch_get_profile(vemb_batch* b, vemb_batch_profile* out);
 int vemb_batch_sync(vemb_batch* b);
 void vemb_batch_destroy(vemb_batch* b);
 

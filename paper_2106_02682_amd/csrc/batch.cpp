@@ -43,8 +43,15 @@ struct vemb_batch {
   bool use_graph = true;
   hipGraphExec_t exec[2] = {nullptr, nullptr};  // [cold]
   std::vector<void*> allocs;
-  double ms_total = 0.0;
-  int64_t iters_timed = 0;
+  // sampled kernel timing (vemb_batch_set_profiling): iterations whose batch iteration index is a
+  // multiple of prof_every are enqueued directly with events around the timed launches
+  int prof_every = 0;
+  int64_t iter = 0;
+  struct Mark { int id; hipEvent_t start, stop; };
+  std::vector<Mark> marks;
+  std::vector<hipEvent_t> free_events;
+  double prof_ms[VEMB_BK_COUNT] = {};
+  int64_t prof_n[VEMB_BK_COUNT] = {};
 };
 
 namespace {
@@ -58,32 +65,115 @@ int balloc(vemb_batch* b, T** p, size_t count) {
   return VEMB_OK;
 }
 
-int enqueue_iteration(vemb_batch* b, int cold) {
+hipEvent_t take_event(vemb_batch* b) {
+  if (!b->free_events.empty()) {
+    hipEvent_t e = b->free_events.back();
+    b->free_events.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  return hipEventCreate(&e) == hipSuccess ? e : nullptr;
+}
+
+// Events of one timed launch: `on` false leaves the launch untimed.
+struct Timer {
+  vemb_batch* b;
+  bool on;
+  int id = 0;
+  hipEvent_t start = nullptr;
+  void before(int kid, hipStream_t st) {
+    if (!on) return;
+    id = kid;
+    start = take_event(b);
+    if (start) hipEventRecord(start, st);
+  }
+  void after(hipStream_t st) {
+    if (!on || !start) return;
+    hipEvent_t stop = take_event(b);
+    if (stop) {
+      hipEventRecord(stop, st);
+      b->marks.push_back({id, start, stop});
+    }
+    start = nullptr;
+  }
+};
+
+struct SignHookCtx {
+  Timer* timer;
+  int id;
+};
+void sign_hook(void* ctx, int phase, hipStream_t st) {
+  auto* c = static_cast<SignHookCtx*>(ctx);
+  if (phase == 0)
+    c->timer->before(c->id, st);
+  else
+    c->timer->after(st);
+}
+
+int enqueue_iteration(vemb_batch* b, int cold, bool timed = false) {
   hipStream_t s = b->stream;
   const int n_inst = (int)b->probs.size();
   const int max_sweeps = b->probs[0]->opt.max_sweeps;
+  Timer tm{b, timed}, tm_side{b, timed};
+  tm.before(VEMB_BK_PAIR_UPDATE, s);
   VEMB_TRY(hip_rc(launch_step_batched(0, b->d_args, b->d_work[0], b->nwork[0], s), "batched pair update"));
+  tm.after(s);
+  tm.before(VEMB_BK_PAIR_XSTEP, s);
   VEMB_TRY(hip_rc(launch_step_batched(1, b->d_args, b->d_work[1], b->nwork[1], s), "batched X step"));
+  tm.after(s);
   // fork: pair projections on the side stream (they feed only the next iteration)
   VEMB_TRY(hip_rc(hipEventRecord(b->fork_ev, s), "fork"));
   VEMB_TRY(hip_rc(hipStreamWaitEvent(b->side, b->fork_ev, 0), "fork"));
+  SignHookCtx side_ctx{&tm_side, VEMB_BK_SIGN_GEMM_REAL}, main_ctx{&tm, VEMB_BK_SIGN_GEMM_CPLX};
+  const LaunchHook side_hook{sign_hook, &side_ctx}, main_hook{sign_hook, &main_ctx};
   for (const auto& g : b->groups)
-    if (g.kind == 0)
-      VEMB_TRY(hip_rc(g.nscr ? launch_projection_group_sign(0, g.n, g.count, g.d_item, b->d_pair, g.nscr, b->side)
+    if (g.kind == 0) {
+      if (!g.nscr) tm_side.before(VEMB_BK_PAIR_JACOBI, b->side);
+      VEMB_TRY(hip_rc(g.nscr ? launch_projection_group_sign(0, g.n, g.count, g.d_item, b->d_pair, g.nscr, b->side,
+                                                            timed ? &side_hook : nullptr)
                              : launch_projection_group(0, g.n, g.count, g.precision, max_sweeps, cold, g.tpb,
                                                        g.d_item, b->d_pair, g.vstore_any, g.wscr, g.tscr, b->side),
                       "batched pair projection"));
+      if (!g.nscr) tm_side.after(b->side);
+    }
   VEMB_TRY(hip_rc(hipEventRecord(b->join_ev, b->side), "join"));
+  tm.before(VEMB_BK_CLUSTER, s);
   VEMB_TRY(hip_rc(launch_step_batched(2, b->d_args, nullptr, n_inst, s), "batched cluster update"));
+  tm.after(s);
+  tm.before(VEMB_BK_DFT_FWD, s);
   VEMB_TRY(hip_rc(launch_step_batched(3, b->d_args, b->d_work[3], b->nwork[3], s), "batched forward DFT"));
+  tm.after(s);
   for (const auto& g : b->groups)
-    if (g.kind == 1)
-      VEMB_TRY(hip_rc(g.nscr ? launch_projection_group_sign(1, g.n, g.count, g.d_item, b->d_mom, g.nscr, s)
+    if (g.kind == 1) {
+      if (!g.nscr) tm.before(VEMB_BK_MOM_JACOBI, s);
+      VEMB_TRY(hip_rc(g.nscr ? launch_projection_group_sign(1, g.n, g.count, g.d_item, b->d_mom, g.nscr, s,
+                                                            timed ? &main_hook : nullptr)
                              : launch_projection_group(1, g.n, g.count, g.precision, max_sweeps, cold, g.tpb,
                                                        g.d_item, b->d_mom, g.vstore_any, g.wscr, g.tscr, s),
                       "batched momentum projection"));
+      if (!g.nscr) tm.after(s);
+    }
+  tm.before(VEMB_BK_DFT_INV, s);
   VEMB_TRY(hip_rc(launch_step_batched(4, b->d_args, b->d_work[4], b->nwork[4], s), "batched inverse DFT"));
+  tm.after(s);
   VEMB_TRY(hip_rc(hipStreamWaitEvent(s, b->join_ev, 0), "join"));
+  return VEMB_OK;
+}
+
+int drain_marks(vemb_batch* b) {
+  if (b->marks.empty()) return VEMB_OK;
+  VEMB_TRY(hip_rc(hipStreamSynchronize(b->stream), "profile sync"));
+  VEMB_TRY(hip_rc(hipStreamSynchronize(b->side), "profile sync"));
+  for (auto& mk : b->marks) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, mk.start, mk.stop) == hipSuccess) {
+      b->prof_ms[mk.id] += ms;
+      b->prof_n[mk.id] += 1;
+    }
+    b->free_events.push_back(mk.start);
+    b->free_events.push_back(mk.stop);
+  }
+  b->marks.clear();
   return VEMB_OK;
 }
 
@@ -221,10 +311,12 @@ int vemb_batch_step(vemb_batch* b, int iters) {
     // one graph serves all instances: start cold if any instance would alone
     bool cold = b->refresh < 0;
     for (vemb_problem* p : b->probs) cold = cold || !p->v_valid || (b->refresh > 0 && p->t % b->refresh == 0);
-    if (b->use_graph)
+    const bool timed = b->prof_every > 0 && b->iter % b->prof_every == 0;
+    if (b->use_graph && !timed)
       VEMB_TRY(hip_rc(hipGraphLaunch(b->exec[cold ? 1 : 0], b->stream), "graph launch"));
     else
-      VEMB_TRY(enqueue_iteration(b, cold ? 1 : 0));
+      VEMB_TRY(enqueue_iteration(b, cold ? 1 : 0, timed));
+    ++b->iter;
     for (vemb_problem* p : b->probs) {
       p->v_valid = true;
       ++p->t;
@@ -270,6 +362,33 @@ int vemb_batch_info(const vemb_batch* b, int* groups, int* launches_per_iteratio
   return VEMB_OK;
 }
 
+int vemb_batch_set_profiling(vemb_batch* b, int every) {
+  if (!b || every < 0) return fail(VEMB_E_INVALID, "bad arguments to vemb_batch_set_profiling");
+  VEMB_TRY(drain_marks(b));
+  for (int k = 0; k < VEMB_BK_COUNT; ++k) {
+    b->prof_ms[k] = 0.0;
+    b->prof_n[k] = 0;
+  }
+  b->prof_every = every;
+  // events for the timings are created here, not between launches
+  while (every > 0 && b->free_events.size() < 1024) {
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) break;
+    b->free_events.push_back(e);
+  }
+  return VEMB_OK;
+}
+
+int vemb_batch_get_profile(vemb_batch* b, vemb_batch_profile* out) {
+  if (!b || !out) return fail(VEMB_E_INVALID, "NULL argument");
+  VEMB_TRY(drain_marks(b));
+  for (int k = 0; k < VEMB_BK_COUNT; ++k) {
+    out->ms[k] = b->prof_ms[k];
+    out->launches[k] = b->prof_n[k];
+  }
+  return VEMB_OK;
+}
+
 int vemb_batch_sync(vemb_batch* b) {
   if (!b) return fail(VEMB_E_INVALID, "NULL batch");
   return hip_rc(hipStreamSynchronize(b->stream), "batch sync");
@@ -281,6 +400,11 @@ void vemb_batch_destroy(vemb_batch* b) {
   for (auto& e : b->exec)
     if (e) hipGraphExecDestroy(e);
   for (void* p : b->allocs) hipFree(p);
+  for (auto& mk : b->marks) {
+    hipEventDestroy(mk.start);
+    hipEventDestroy(mk.stop);
+  }
+  for (hipEvent_t e : b->free_events) hipEventDestroy(e);
   if (b->ev) hipEventDestroy(b->ev);
   if (b->fork_ev) hipEventDestroy(b->fork_ev);
   if (b->join_ev) hipEventDestroy(b->join_ev);

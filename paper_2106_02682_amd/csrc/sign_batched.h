@@ -18,8 +18,22 @@ hipError_t launch_pair_projection_sign(const double* rho, double* Lam, double* r
                                        double mu, int* sweeps, void* work, hipStream_t st);
 // Step 8 in place (as launch_momentum_projection) for K complex blocks of size n_op.
 hipError_t launch_momentum_projection_sign(double* Xh, int n_op, int K, int* sweeps, void* work, hipStream_t st);
+// Optional callback around each product launch of a sign projection (timing): phase 0 before the
+// launch, 1 after it, on the launch's stream.  Null = none.
+struct LaunchHook {
+  void (*fn)(void* ctx, int phase, hipStream_t st);
+  void* ctx;
+};
+
 // A batch size class (kind 0 pairs, 1 momentum blocks) through the batched policies.
 hipError_t launch_projection_group_sign(int kind, int n, int count, const int2* item, const void* ptrs, void* work,
-                                        hipStream_t st);
+                                        hipStream_t st, const LaunchHook* hook = nullptr);
+
+// Real flops of one product launch over `count` blocks of size n: the upper-triangle 64 x 64 tiles
+// of each block, 2 flops per multiply-add, four real products per complex one.
+inline double sign_gemm_flops(int n, int count, bool cplx) {
+  const double t = n / 64;
+  return (cplx ? 4.0 : 1.0) * count * (t * (t + 1) / 2) * 64.0 * 64.0 * n * 2.0;
+}
 
 }  // namespace vemb

@@ -145,14 +145,18 @@ __global__ void __launch_bounds__(kSignThreads) sign_store_kernel(Policy pol, in
 }
 
 template <typename S>
-void gemm(S* work, int n, int count, int p, int q, int e, int o, double c0, double c1, hipStream_t st) {
+void gemm(S* work, int n, int count, int p, int q, int e, int o, double c0, double c1, hipStream_t st,
+          const LaunchHook* hook) {
   const int tiles = n / 64;
+  if (hook) hook->fn(hook->ctx, 0, st);
   hipLaunchKernelGGL((sign_gemm_kernel<S>), dim3(tiles * (tiles + 1) / 2, count), dim3(1024), 0, st, work, n, p, q,
                      e, o, c0, c1);
+  if (hook) hook->fn(hook->ctx, 1, st);
 }
 
 template <typename S, typename Policy>
-hipError_t sign_project(const Policy& pol, int n, int count, void* work_raw, hipStream_t st) {
+hipError_t sign_project(const Policy& pol, int n, int count, void* work_raw, hipStream_t st,
+                        const LaunchHook* hook = nullptr) {
   if (count <= 0) return hipSuccess;
   if (n % 64 || n > kSignMax) return hipErrorInvalidValue;
   S* work = static_cast<S*>(work_raw);
@@ -163,12 +167,12 @@ hipError_t sign_project(const Policy& pol, int n, int count, void* work_raw, hip
   int X = nn, T = 3 * nn;
   hipLaunchKernelGGL((sign_load_kernel<S, Policy>), dim3(count), dim3(kSignThreads), 0, st, pol, n, work);
   for (double a : sched) {
-    gemm<S>(work, n, count, X, X, -1, Y, 0.0, 1.0, st);
-    gemm<S>(work, n, count, X, Y, X, T, 1.5 * a, -0.5 * a * a * a, st);
+    gemm<S>(work, n, count, X, X, -1, Y, 0.0, 1.0, st, hook);
+    gemm<S>(work, n, count, X, Y, X, T, 1.5 * a, -0.5 * a * a * a, st, hook);
     std::swap(X, T);
   }
   // Pi(A) = (A + A S) / 2 into the slot of X^2, free after the last step
-  gemm<S>(work, n, count, A, X, A, Y, 0.5, 0.5, st);
+  gemm<S>(work, n, count, A, X, A, Y, 0.5, 0.5, st, hook);
   hipLaunchKernelGGL((sign_store_kernel<S, Policy>), dim3(count), dim3(kSignThreads), 0, st, pol, n, work, Y,
                      (int)sched.size());
   return hipGetLastError();
@@ -188,13 +192,13 @@ hipError_t launch_momentum_projection_sign(double* Xh, int n_op, int K, int* swe
 }
 
 hipError_t launch_projection_group_sign(int kind, int n, int count, const int2* item, const void* ptrs, void* work,
-                                        hipStream_t st) {
+                                        hipStream_t st, const LaunchHook* hook) {
   if (kind == 0) {
     BatchedPairPolicy pol{item, static_cast<const PairPtrs*>(ptrs), n, 1};
-    return sign_project<double>(pol, n, count, work, st);
+    return sign_project<double>(pol, n, count, work, st, hook);
   }
   BatchedMomentumPolicy pol{item, static_cast<const MomPtrs*>(ptrs), n, 1};
-  return sign_project<cplx<double>>(pol, n, count, work, st);
+  return sign_project<cplx<double>>(pol, n, count, work, st, hook);
 }
 
 }  // namespace vemb

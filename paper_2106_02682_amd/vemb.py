@@ -37,8 +37,11 @@ EXPORTS = [
     "vemb_diagnostics_collect", "vemb_set_profiling_mask", "vemb_dense_create", "vemb_dense_get_info",
     "vemb_dense_step", "vemb_dense_dual_bound", "vemb_dense_primal_energy", "vemb_dense_get_state",
     "vemb_dense_set_state", "vemb_dense_last_sweeps", "vemb_dense_destroy", "vemb_psd_project_sign",
-    "vemb_set_profiling_every", "vemb_psd_project_sign_noalloc",
+    "vemb_set_profiling_every", "vemb_psd_project_sign_noalloc", "vemb_batch_set_profiling",
+    "vemb_batch_get_profile",
 ]
+BATCH_KERNELS = ["pair_update", "pair_xstep", "cluster_update", "dft_forward", "dft_inverse", "pair_jacobi",
+                 "momentum_jacobi", "sign_gemm_real", "sign_gemm_complex"]
 KERNELS = ["pair_update", "pair_xstep", "pair_projection", "cluster_update", "dft_forward", "momentum_projection",
            "dft_inverse", "bound_build", "lambda_min", "projections"]
 
@@ -84,6 +87,10 @@ _DP = ctypes.POINTER(ctypes.c_double)
 
 class vemb_profile(ctypes.Structure):
     _fields_ = [("ms", ctypes.c_double * 10), ("launches", ctypes.c_int64 * 10)]
+
+
+class vemb_batch_profile(ctypes.Structure):
+    _fields_ = [("ms", ctypes.c_double * 9), ("launches", ctypes.c_int64 * 9)]
 
 
 class vemb_state(ctypes.Structure):
@@ -154,6 +161,8 @@ def lib():
     L.vemb_batch_primal_energies.argtypes = [vp, _DP, _DP]
     L.vemb_batch_info.argtypes = [vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
     L.vemb_batch_sync.argtypes = [vp]
+    L.vemb_batch_set_profiling.argtypes = [vp, ctypes.c_int]
+    L.vemb_batch_get_profile.argtypes = [vp, ctypes.POINTER(vemb_batch_profile)]
     L.vemb_batch_destroy.argtypes = [vp]
     L.vemb_batch_destroy.restype = None
     _FP = ctypes.POINTER(ctypes.c_float)
@@ -554,6 +563,16 @@ class Batch:
         f = np.zeros(len(self.problems))
         _check(lib().vemb_batch_primal_energies(self.h, _ptr(e), _ptr(f)))
         return e, f
+
+    def set_profiling(self, every):
+        """Time the kernels of every ``every``-th iteration (0 = off); resets the accumulated times."""
+        _check(lib().vemb_batch_set_profiling(self.h, int(every)))
+
+    def get_profile(self):
+        """{kernel: (total device ms, timed launches)} since the last set_profiling."""
+        out = vemb_batch_profile()
+        _check(lib().vemb_batch_get_profile(self.h, ctypes.byref(out)))
+        return {k: (out.ms[i], out.launches[i]) for i, k in enumerate(BATCH_KERNELS)}
 
     def info(self):
         a, b = ctypes.c_int(), ctypes.c_int()
