@@ -111,6 +111,12 @@ typedef struct {
                            Jordan-Wigner parity sign of the pair order (an odd operator of the
                            second cluster carries the first cluster's parity).  Needs
                            VEMB_OPSET_COMPLETE.  0 (default): spins. */
+  int32_t lb_every;     /* > 0: vemb_step evaluates the FP64 diagnostics (bound, energy, feasibility) every
+                           lb_every iterations, queued on the stream and read back one interval later, and
+                           stops with the watchdog's status (vemb_divergence_check) when it fires:
+                           VEMB_E_NUMERIC or VEMB_E_DIVERGED, naming the iteration.  While it is on, the
+                           library owns the queued diagnostics (vemb_diagnostics_collect returns the latest
+                           it queued).  0 (default): no diagnostics inside vemb_step. */
 } vemb_options;
 
 typedef struct vemb_problem vemb_problem;
@@ -120,6 +126,21 @@ typedef struct {
   int32_t M, P, L, m, n, n_op, Mx, My, K_unique;
   int64_t t; /* iterations done */
 } vemb_info;
+
+/* Device memory.  By default the library takes device memory with hipMalloc and returns it with
+ * hipFree.  vemb_set_allocator routes every later device allocation of the library through the caller's
+ * functions instead (e.g. torch's caching allocator): the state of problems, batches, dense problems
+ * and networks, the autotuner's buffers and the scratch of the isolated entry points.  alloc(bytes, ctx)
+ * returns device memory of at least `bytes` bytes, aligned to 256 bytes, on the current device, or NULL
+ * (the library then fails with VEMB_E_NOMEM); free(ptr, ctx) takes back a pointer alloc returned, after
+ * the library has synchronised the streams that used it.  Both NULL restores hipMalloc / hipFree.  Each
+ * object keeps the allocator in effect when it was created and returns its memory through it.  Pinned
+ * host buffers are not routed (hipHostMalloc).  The functions may be called from any thread that calls
+ * the library.  Errors: VEMB_E_INVALID when only one of the two is NULL, or while any problem, batch,
+ * dense problem or network is alive (switch allocators between objects' lifetimes). */
+typedef void* (*vemb_alloc_fn)(size_t bytes, void* ctx);
+typedef void (*vemb_free_fn)(void* ptr, void* ctx);
+int vemb_set_allocator(vemb_alloc_fn alloc_fn, vemb_free_fn free_fn, void* ctx);
 
 /* Fills *opts with the paper's parameters (mu = nu = 10, eps = 2), COMPLETE, FP64. */
 void vemb_default_options(vemb_options* opts);
@@ -196,9 +217,20 @@ int vemb_get_state(vemb_problem* p, vemb_state* s);
 int vemb_set_state(vemb_problem* p, const vemb_state* s);
 
 /* Largest Jacobi sweep count over the pair projections and over the momentum
- * projections of the last iteration (synchronises).  A value equal to the
- * sweep cap means some eigensolve stopped unconverged. */
+ * projections of the last iteration (synchronises).  An eigensolve of the LDS solver
+ * (blocks up to 64 x 64 complex / 128 x 128 real) that stopped at the sweep cap unconverged
+ * records cap + 1; its kept eigenvectors are then reset to the identity, so its next solve
+ * starts cold.  Returns VEMB_E_NOCONV (with both counts written) when a count exceeds the cap. */
 int vemb_last_sweeps(vemb_problem* p, int* pair_max, int* momentum_max);
+
+/* The divergence watchdog's rule, on the host (no device work): feas[0..count) are the feasibility
+ * errors (eq. feasErr) of successive diagnostics, oldest first; lb and energy the latest bound and
+ * energy per site.  Returns VEMB_E_NUMERIC if the latest values are not finite; VEMB_E_DIVERGED if the
+ * latest feasibility error exceeds 1e3 (marginals have unit trace, so a bounded iteration keeps it O(1)),
+ * or if it rose at each of the last 5 checks and is at least 100 times the smallest seen; else VEMB_OK.
+ * The printed "+ eps G" step (vemb_options.sign = +1) is the natural diverging case.  Errors:
+ * VEMB_E_INVALID for count < 1 or NULL feas. */
+int vemb_divergence_check(const double* feas, int count, double lb, double energy);
 
 /* Kernel-level timing.  With profiling on, every kernel the problem launches is
  * bracketed by HIP events recorded on the problem's stream; vemb_get_profile
@@ -287,6 +319,18 @@ int vemb_psd_project_sign(const double* in, double* out, int n, void* hip_stream
  * Errors: VEMB_E_INVALID, VEMB_E_HIP. */
 int vemb_psd_project_sign_noalloc(const double* in, double* out, int n, void* hip_stream);
 int vemb_eigvalsh_batched(const double* in, double* w, int n, int batch, int is_complex, void* hip_stream);
+
+/* Workgroup -> output tile map of the symmetric-product kernels, computed on the host by the same
+ * functions the kernels and their launchers use, so that callers and tests can check a launch covers
+ * every tile once and no workgroup reaches past the last one.  kind 0: the single-matrix product of the
+ * sign projection (vemb_psd_project_sign, the dense X projection), n a multiple of 16 up to 4096, 16 x 16
+ * tiles; kind 1: the batched products of the 4-site-cluster blocks, n a multiple of 64 up to 256, 64 x 64
+ * tiles, `count` blocks, a 2-D grid (upper-triangle tiles, count) listed as bx + tiles_upper * by.
+ * *grid receives the launch's workgroup count; map (host, 4 * grid ints, may be NULL to query the grid)
+ * receives per workgroup {live, block, tile row, tile column} (live 0: the workgroup returns at once;
+ * its other fields are -1).  Only the upper triangle (row <= column) is mapped.
+ * Errors: VEMB_E_INVALID. */
+int vemb_tile_map(int kind, int n, int count, int* grid, int* map);
 
 /* ---- Batches: many independent problems stepped together --------------------
  * Parameter sweeps (Section 4's tables: one solve per field value or coupling)

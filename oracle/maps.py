@@ -214,10 +214,32 @@ def pair_superoperator(m, mu, nu):
 # Projection onto the PSD cone (Section 3, definition of Pi)
 # ---------------------------------------------------------------------------
 
+def _eigh(A, vectors=True):
+    """Eigendecomposition of stacked symmetric / Hermitian matrices by LAPACK.  numpy's driver
+    (divide and conquer) can stop with "did not converge" on rare finite matrices; those matrices are
+    then decomposed one by one by the implicit QL/QR driver of the same library (same definition)."""
+    try:
+        return np.linalg.eigh(A) if vectors else (np.linalg.eigvalsh(A), None)
+    except np.linalg.LinAlgError:
+        import scipy.linalg
+
+        flat = A.reshape((-1,) + A.shape[-2:])
+        ws, Vs = [], []
+        for M in flat:
+            if vectors:
+                w, V = scipy.linalg.eigh(M, driver="ev")
+                Vs.append(V)
+            else:
+                w = scipy.linalg.eigh(M, driver="ev", eigvals_only=True)
+            ws.append(w)
+        w = np.stack(ws).reshape(A.shape[:-1])
+        return (w, np.stack(Vs).reshape(A.shape)) if vectors else (w, None)
+
+
 def psd_project(C):
     """argmin_{S >= 0} ||S - C||_F for symmetric / Hermitian C (stacked): clip negative eigenvalues."""
     Ch = 0.5 * (C + np.conj(np.swapaxes(C, -1, -2)))
-    w, V = np.linalg.eigh(Ch)
+    w, V = _eigh(Ch)
     wp = np.maximum(w, 0.0)
     P = (V * wp[..., None, :]) @ np.conj(np.swapaxes(V, -1, -2))
     return 0.5 * (P + np.conj(np.swapaxes(P, -1, -2)))
@@ -226,4 +248,4 @@ def psd_project(C):
 def lambda_min(A):
     """Smallest eigenvalue of a symmetric / Hermitian matrix (stacked)."""
     Ah = 0.5 * (A + np.conj(np.swapaxes(A, -1, -2)))
-    return np.linalg.eigvalsh(Ah)[..., 0]
+    return _eigh(Ah, vectors=False)[0][..., 0]

@@ -13,9 +13,11 @@
 #include <string>
 #include <vector>
 
+#include "alloc.h"
 #include "polar.h"
 #include "problem.h"
 #include "sign_batched.h"
+#include "tile_map.h"
 
 namespace vemb {
 
@@ -29,6 +31,25 @@ using namespace vemb;
 
 
 namespace vemb {
+namespace {
+std::mutex g_alloc_mu;
+Allocator g_alloc;
+int g_live_objects = 0;
+}  // namespace
+
+Allocator current_allocator() {
+  std::lock_guard<std::mutex> lock(g_alloc_mu);
+  return g_alloc;
+}
+void object_created() {
+  std::lock_guard<std::mutex> lock(g_alloc_mu);
+  ++g_live_objects;
+}
+void object_destroyed() {
+  std::lock_guard<std::mutex> lock(g_alloc_mu);
+  --g_live_objects;
+}
+
 int fail(int code, const std::string& msg) {
   set_error(msg);
   return code;
@@ -44,10 +65,9 @@ namespace {
 
 template <typename T>
 int dalloc(vemb_problem* p, T** ptr, size_t count) {
-  void* raw = nullptr;
   const size_t bytes = count == 0 ? 16 : count * sizeof(T);
-  if (hipMalloc(&raw, bytes) != hipSuccess) return fail(VEMB_E_NOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
-  p->allocations.push_back(raw);
+  void* raw = p->mem.get(bytes);
+  if (!raw) return fail(VEMB_E_NOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed");
   *ptr = static_cast<T*>(raw);
   return VEMB_OK;
 }
@@ -241,10 +261,13 @@ int vemb::tuned_tpb(int n, bool cplx, int precision, int count, hipStream_t st) 
           }
   }
   const size_t bytes = h.size() * sizeof(double);
-  double *din = nullptr, *din2 = nullptr, *dout = nullptr, *dv = nullptr;
+  DeviceMemory mem;
+  double* din = static_cast<double*>(mem.get(bytes));
+  double* din2 = static_cast<double*>(mem.get(bytes));
+  double* dout = static_cast<double*>(mem.get(bytes));
+  double* dv = static_cast<double*>(mem.get(bytes));
   int best = 256;
-  if (hipMalloc(&din, bytes) == hipSuccess && hipMalloc(&din2, bytes) == hipSuccess &&
-      hipMalloc(&dout, bytes) == hipSuccess && hipMalloc(&dv, bytes) == hipSuccess &&
+  if (din && din2 && dout && dv &&
       hipMemcpyAsync(din, h.data(), bytes, hipMemcpyHostToDevice, st) == hipSuccess &&
       hipMemcpyAsync(din2, h2.data(), bytes, hipMemcpyHostToDevice, st) == hipSuccess) {
     hipEvent_t e0, e1;
@@ -276,10 +299,7 @@ int vemb::tuned_tpb(int n, bool cplx, int precision, int count, hipStream_t st) 
     hipEventDestroy(e1);
   }
   hipStreamSynchronize(st);
-  if (din) hipFree(din);
-  if (din2) hipFree(din2);
-  if (dout) hipFree(dout);
-  if (dv) hipFree(dv);
+  mem.release();
   hipGetLastError();  // a failed candidate must not leak its error into the caller
   tune_store(key, best);
   return best;
@@ -298,6 +318,19 @@ bool all_finite(const double* v, size_t count) {
 extern "C" {
 
 const char* vemb_last_error(void) { return g_last_error.c_str(); }
+
+int vemb_set_allocator(vemb_alloc_fn alloc_fn, vemb_free_fn free_fn, void* ctx) {
+  if ((alloc_fn == nullptr) != (free_fn == nullptr))
+    return fail(VEMB_E_INVALID, "vemb_set_allocator needs both functions, or neither");
+  std::lock_guard<std::mutex> lock(g_alloc_mu);
+  if (g_live_objects > 0)
+    return fail(VEMB_E_INVALID, std::to_string(g_live_objects) + " library objects are alive: destroy them before "
+                                "switching allocators");
+  g_alloc.alloc = alloc_fn;
+  g_alloc.free = free_fn;
+  g_alloc.ctx = alloc_fn ? ctx : nullptr;
+  return VEMB_OK;
+}
 
 void vemb_default_options(vemb_options* o) {
   if (!o) return;
@@ -327,6 +360,7 @@ int vemb_create_problem(const vemb_hamiltonian* H, const vemb_lattice* lat, cons
   if (g.n > 256 || n_op > 256) return fail(VEMB_E_UNSUPPORTED, "matrices above 256 x 256 are not supported");
 
   auto* p = new vemb_problem();
+  object_created();
   p->g = g;
   p->P = g.M - 1;
   p->n_op = n_op;
@@ -336,6 +370,7 @@ int vemb_create_problem(const vemb_hamiltonian* H, const vemb_lattice* lat, cons
   int rc = build_model(*H, g, p->host, err, o.fermionic != 0);
   if (rc != VEMB_OK) {
     delete p;  // nothing on the device yet
+    object_destroyed();
     return fail(rc, err);
   }
   std::vector<double> tw, wk;
@@ -441,6 +476,26 @@ bool fused_projections(const vemb_problem* p, int prec) {
          p->tpb_pair == kFusedThreads && p->tpb_mom == kFusedThreads;
 }
 
+int diag_enqueue(vemb_problem* p);
+int diag_collect(vemb_problem* p, double* lb, double* e, double* f);
+
+// The watchdog of vemb_options.lb_every, after iteration t: read back the diagnostics queued one
+// interval ago, apply vemb_divergence_check to the feasibility history, queue the current ones.
+int watchdog(vemb_problem* p) {
+  if (p->diag_pending) {
+    double lb = 0.0, e = 0.0, f = 0.0;
+    const int rc = diag_collect(p, &lb, &e, &f);
+    p->feas_hist.push_back(f);
+    const int w = vemb_divergence_check(p->feas_hist.data(), (int)p->feas_hist.size(), lb, e);
+    if (rc != VEMB_OK || w != VEMB_OK) {
+      const int code = w != VEMB_OK ? w : rc;
+      return fail(code, "watchdog at iteration " + std::to_string(p->t - p->opt.lb_every) + ": " +
+                            std::string(vemb_last_error()));
+    }
+  }
+  return diag_enqueue(p);
+}
+
 int run_iterations(vemb_problem* p, int iters, int prec) {
   const StepArgs& a = p->a;
   hipStream_t s = p->stream;
@@ -461,6 +516,7 @@ int run_iterations(vemb_problem* p, int iters, int prec) {
       VEMB_TRY(timed(p, VEMB_K_DFT_INV, "inverse DFT", [&] { return launch_dft_inverse(a, s); }));
       p->v_valid = true;
       ++p->t;
+      if (p->opt.lb_every > 0 && p->t % p->opt.lb_every == 0) VEMB_TRY(watchdog(p));
       continue;
     }
     // fork: pair projection on the side stream (reads rho, Lambda; writes rho_t,
@@ -493,6 +549,7 @@ int run_iterations(vemb_problem* p, int iters, int prec) {
     VEMB_TRY(hip_rc(hipStreamWaitEvent(s, p->join_ev, 0), "join"));
     p->v_valid = true;
     ++p->t;
+    if (p->opt.lb_every > 0 && p->t % p->opt.lb_every == 0) VEMB_TRY(watchdog(p));
   }
   return VEMB_OK;
 }
@@ -667,8 +724,8 @@ int diag_reduce(vemb_problem* p, const double* lm, const double* ep, const doubl
 }
 }  // namespace
 
-int vemb_diagnostics_enqueue(vemb_problem* p) {
-  if (!p) return fail(VEMB_E_INVALID, "NULL problem");
+namespace {
+int diag_enqueue(vemb_problem* p) {
   const int P = p->P;
   hipStream_t s = p->stream;
   if (!p->diag_host) {
@@ -690,14 +747,24 @@ int vemb_diagnostics_enqueue(vemb_problem* p) {
   return VEMB_OK;
 }
 
-int vemb_diagnostics_collect(vemb_problem* p, double* lb, double* e_per_site, double* feas_err) {
-  if (!p || !lb) return fail(VEMB_E_INVALID, "NULL argument");
-  if (!p->diag_pending) return fail(VEMB_E_INVALID, "no diagnostics enqueued");
+int diag_collect(vemb_problem* p, double* lb, double* e_per_site, double* feas_err) {
   VEMB_TRY(hip_rc(hipEventSynchronize(p->diag_ev), "diagnostics wait"));
   p->diag_pending = false;
   const int P = p->P;
   const double* h = p->diag_host;
   return diag_reduce(p, h, h + P + 1, h + 2 * P + 1, h + 3 * P + 1, lb, e_per_site, feas_err);
+}
+}  // namespace
+
+int vemb_diagnostics_enqueue(vemb_problem* p) {
+  if (!p) return fail(VEMB_E_INVALID, "NULL problem");
+  return diag_enqueue(p);
+}
+
+int vemb_diagnostics_collect(vemb_problem* p, double* lb, double* e_per_site, double* feas_err) {
+  if (!p || !lb) return fail(VEMB_E_INVALID, "NULL argument");
+  if (!p->diag_pending) return fail(VEMB_E_INVALID, "no diagnostics enqueued");
+  return diag_collect(p, lb, e_per_site, feas_err);
 }
 
 int vemb_marginals(vemb_problem* p, int which, double* rho0, double* rho_pairs) {
@@ -762,6 +829,25 @@ int vemb_set_state(vemb_problem* p, const vemb_state* st) {
   return VEMB_OK;
 }
 
+int vemb_divergence_check(const double* feas, int count, double lb, double energy) {
+  if (!feas || count < 1) return fail(VEMB_E_INVALID, "vemb_divergence_check needs at least one value");
+  const double last = feas[count - 1];
+  if (!std::isfinite(lb) || !std::isfinite(energy) || !std::isfinite(last))
+    return fail(VEMB_E_NUMERIC, "non-finite bound, energy or feasibility error");
+  if (last > 1e3) return fail(VEMB_E_DIVERGED, "feasibility error " + std::to_string(last) + " above 1e3");
+  constexpr int kRises = 5;
+  if (count > kRises) {
+    bool rising = true;
+    for (int i = count - kRises; i < count; ++i) rising = rising && feas[i] > feas[i - 1];
+    double lo = feas[0];
+    for (int i = 1; i < count; ++i) lo = std::min(lo, feas[i]);
+    if (rising && last >= 100.0 * lo)
+      return fail(VEMB_E_DIVERGED, "feasibility error rose at each of the last 5 checks to " + std::to_string(last) +
+                                       ", 100 times its smallest value");
+  }
+  return VEMB_OK;
+}
+
 int vemb_tuned_threads(int n, int is_complex, int precision, int batch, void* hip_stream) {
   if (n <= 0 || batch <= 0) return fail(VEMB_E_INVALID, "bad arguments to vemb_tuned_threads");
   return tuned_tpb(n, is_complex != 0, precision, batch, static_cast<hipStream_t>(hip_stream));
@@ -785,6 +871,9 @@ int vemb_last_sweeps(vemb_problem* p, int* pair_max, int* momentum_max) {
   for (int i = 0; i < p->Ku; ++i) b = std::max(b, sw[p->P + i]);
   if (pair_max) *pair_max = a;
   if (momentum_max) *momentum_max = b;
+  if (std::max(a, b) > p->opt.max_sweeps)
+    return fail(VEMB_E_NOCONV, "an eigensolve stopped at the sweep cap of " + std::to_string(p->opt.max_sweeps) +
+                                   " unconverged (its next solve starts cold)");
   return VEMB_OK;
 }
 
@@ -837,13 +926,14 @@ void vemb_destroy(vemb_problem* p) {
     hipEventDestroy(mk.stop);
   }
   for (hipEvent_t e : p->free_events) hipEventDestroy(e);
-  for (void* ptr : p->allocations) hipFree(ptr);
+  p->mem.release();
   if (p->diag_ev) hipEventDestroy(p->diag_ev);
   if (p->diag_host) hipHostFree(p->diag_host);
   if (p->fork_ev) hipEventDestroy(p->fork_ev);
   if (p->join_ev) hipEventDestroy(p->join_ev);
   if (p->side) hipStreamDestroy(p->side);
   delete p;
+  object_destroyed();
 }
 
 int vemb_psd_project_batched(const double* in, double* out, int n, int batch, int is_complex, int precision,
@@ -855,14 +945,11 @@ namespace {
 // Large matrices (streamed solver) need per-matrix scratch: allocated for the call,
 // freed after the stream drains (these calls synchronise).
 struct Scratch {
+  DeviceMemory mem;
   void* w = nullptr;
   void* t = nullptr;
   void* v = nullptr;
-  ~Scratch() {
-    if (w) hipFree(w);
-    if (t) hipFree(t);
-    if (v) hipFree(v);
-  }
+  ~Scratch() { mem.release(); }
 };
 }  // namespace
 
@@ -877,7 +964,7 @@ int vemb_psd_project_batched_ex(const double* in, double* out, int n, int batch,
   const bool need_v = precision == VEMB_MIXED && !(n > 64 && n <= 128);  // MIXED keeps eigenvectors between passes
   const size_t bytes = (size_t)batch * n * n * (is_complex ? 16 : 8);
   Scratch sc;
-  if (need_v && hipMalloc(&sc.v, bytes) != hipSuccess) return fail(VEMB_E_NOMEM, "eigenvector scratch");
+  if (need_v && !(sc.v = sc.mem.get(bytes))) return fail(VEMB_E_NOMEM, "eigenvector scratch");
   if (lds) {
     const int t = tpb > 0 ? tpb : tuned_tpb(n, is_complex != 0, precision, batch, st);
     VEMB_TRY(hip_rc(launch_psd_batched(in, out, n, batch, is_complex != 0, precision, ms, sweeps, (double*)sc.v, t,
@@ -886,7 +973,7 @@ int vemb_psd_project_batched_ex(const double* in, double* out, int n, int batch,
     return sc.v ? hip_rc(hipStreamSynchronize(st), "batched projection sync") : VEMB_OK;
   }
   if (n % 32) return fail(VEMB_E_UNSUPPORTED, "streamed solver needs n divisible by 32");
-  if (hipMalloc(&sc.w, bytes) != hipSuccess || hipMalloc(&sc.t, bytes) != hipSuccess)
+  if (!(sc.w = sc.mem.get(bytes)) || !(sc.t = sc.mem.get(bytes)))
     return fail(VEMB_E_NOMEM, "scratch for the streamed solver");
   VEMB_TRY(hip_rc(launch_psd_batched_big(in, out, n, batch, is_complex != 0, precision, ms, sweeps, (double*)sc.v,
                                          sc.w, sc.t, st),
@@ -898,12 +985,14 @@ int vemb_psd_project_sign(const double* in, double* out, int n, void* hip_stream
   if (!in || !out) return fail(VEMB_E_INVALID, "NULL argument");
   if (n <= 0 || n % 16 || n > 4096) return fail(VEMB_E_INVALID, "n must be a positive multiple of 16, at most 4096");
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
-  double* work = nullptr;
+  DeviceMemory mem;
   const size_t words = 4 * (size_t)n * n + 64;
-  if (hipMalloc(&work, words * sizeof(double)) != hipSuccess) return fail(VEMB_E_NOMEM, "sign-projection scratch");
+  double* work = static_cast<double*>(mem.get(words * sizeof(double)));
+  if (!work) return fail(VEMB_E_NOMEM, "sign-projection scratch");
   int rc = hip_rc(launch_psd_project_ns(in, out, n, work, ns_schedule(kNsResolved), st), "sign projection");
   if (rc == VEMB_OK) rc = hip_rc(hipStreamSynchronize(st), "sign projection sync");
-  hipFree(work);
+  hipStreamSynchronize(st);  // the scratch goes back only after the stream has drained
+  mem.release();
   return rc;
 }
 
@@ -919,6 +1008,34 @@ int vemb_psd_project_sign_noalloc(const double* in, double* out, int n, void* hi
                 "sign projection");
 }
 
+int vemb_tile_map(int kind, int n, int count, int* grid, int* map) {
+  if (!grid) return fail(VEMB_E_INVALID, "NULL grid");
+  int g = 0;
+  if (kind == 0) {
+    if (n <= 0 || n % 16 || n > 4096) return fail(VEMB_E_INVALID, "kind 0: n a positive multiple of 16, at most 4096");
+    g = upper_tile_count(n / 16);
+  } else if (kind == 1) {
+    if (n <= 0 || n % 64 || n > kSignMax || count <= 0)
+      return fail(VEMB_E_INVALID, "kind 1: n a positive multiple of 64 up to 256, count > 0");
+    g = upper_tile_count(n / 64) * count;
+  } else {
+    return fail(VEMB_E_INVALID, "kind must be 0 or 1");
+  }
+  *grid = g;
+  if (!map) return VEMB_OK;
+  for (int w = 0; w < g; ++w) {
+    int b = 0, ti = -1, tj = -1;
+    const int tu = upper_tile_count(n / 64);  // kind 1: grid (tu, count), linear index bx + tu * by
+    const bool live = kind == 0 ? upper_tile(w, n / 16, &ti, &tj)
+                                : batched_tile_of(w % tu, w / tu, count, n / 64, &b, &ti, &tj);
+    map[4 * w] = live ? 1 : 0;
+    map[4 * w + 1] = live ? b : -1;
+    map[4 * w + 2] = live ? ti : -1;
+    map[4 * w + 3] = live ? tj : -1;
+  }
+  return VEMB_OK;
+}
+
 int vemb_eigvalsh_batched(const double* in, double* w, int n, int batch, int is_complex, void* hip_stream) {
   if (!in || !w || n <= 0 || batch < 0) return fail(VEMB_E_INVALID, "bad arguments to vemb_eigvalsh_batched");
   if (n > 256) return fail(VEMB_E_UNSUPPORTED, "matrices above 256 x 256 are not supported");
@@ -928,7 +1045,7 @@ int vemb_eigvalsh_batched(const double* in, double* w, int n, int batch, int is_
   if (n % 32) return fail(VEMB_E_UNSUPPORTED, "streamed solver needs n divisible by 32");
   Scratch sc;
   const size_t bytes = (size_t)batch * n * n * (is_complex ? 16 : 8);
-  if (hipMalloc(&sc.w, bytes) != hipSuccess || hipMalloc(&sc.t, bytes) != hipSuccess)
+  if (!(sc.w = sc.mem.get(bytes)) || !(sc.t = sc.mem.get(bytes)))
     return fail(VEMB_E_NOMEM, "scratch for the streamed solver");
   VEMB_TRY(hip_rc(launch_eigvals_big(in, w, nullptr, n, batch, is_complex != 0, 40, nullptr, sc.w, sc.t, st),
                   "batched eigenvalues"));

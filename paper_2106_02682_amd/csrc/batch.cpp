@@ -42,7 +42,7 @@ struct vemb_batch {
   std::vector<Group> groups;
   bool use_graph = true;
   hipGraphExec_t exec[2] = {nullptr, nullptr};  // [cold]
-  std::vector<void*> allocs;
+  DeviceMemory mem;  // every device allocation of the batch
   // sampled kernel timing (vemb_batch_set_profiling): iterations whose batch iteration index is a
   // multiple of prof_every are enqueued directly with events around the timed launches
   int prof_every = 0;
@@ -58,9 +58,8 @@ namespace {
 
 template <typename T>
 int balloc(vemb_batch* b, T** p, size_t count) {
-  void* raw = nullptr;
-  if (hipMalloc(&raw, std::max<size_t>(count, 1) * sizeof(T)) != hipSuccess) return fail(VEMB_E_NOMEM, "batch allocation");
-  b->allocs.push_back(raw);
+  void* raw = b->mem.get(std::max<size_t>(count, 1) * sizeof(T));
+  if (!raw) return fail(VEMB_E_NOMEM, "batch allocation");
   *p = static_cast<T*>(raw);
   return VEMB_OK;
 }
@@ -208,6 +207,7 @@ int vemb_batch_create(vemb_problem* const* problems, int count, int use_graph, v
       if (problems[j] == problems[i]) return fail(VEMB_E_INVALID, "a problem appears twice in the batch");
   }
   auto* b = new vemb_batch();
+  object_created();
   b->probs.assign(problems, problems + count);
   b->use_graph = use_graph != 0;
   b->refresh = problems[0]->opt.warm_refresh;
@@ -399,7 +399,8 @@ void vemb_batch_destroy(vemb_batch* b) {
   if (b->stream) hipStreamSynchronize(b->stream);
   for (auto& e : b->exec)
     if (e) hipGraphExecDestroy(e);
-  for (void* p : b->allocs) hipFree(p);
+  if (b->side) hipStreamSynchronize(b->side);
+  b->mem.release();
   for (auto& mk : b->marks) {
     hipEventDestroy(mk.start);
     hipEventDestroy(mk.stop);
@@ -411,6 +412,7 @@ void vemb_batch_destroy(vemb_batch* b) {
   if (b->side) hipStreamDestroy(b->side);
   if (b->stream) hipStreamDestroy(b->stream);
   delete b;
+  object_destroyed();
 }
 
 }  // extern "C"

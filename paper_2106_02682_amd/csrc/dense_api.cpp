@@ -8,6 +8,7 @@
 #include <string>
 #include <vector>
 
+#include "alloc.h"
 #include "dense.h"
 #include "polar.h"
 #include "problem.h"
@@ -26,7 +27,7 @@ struct vemb_dense {
   OpTables ops_host{};
   std::vector<int2> pairs_host;
   DenseArgs a{};
-  std::vector<void*> allocations;
+  DeviceMemory mem;  // every device allocation of the dense problem
   double* lmin = nullptr;   // Q + M smallest eigenvalues of the bound matrices
   double* feas = nullptr;   // Q: ||rho_ij - rho~_ij||^2 from the pair projection
   int* sweeps = nullptr;    // Q pair projections, then the X projection
@@ -41,10 +42,9 @@ namespace {
 
 template <typename T>
 int dalloc(vemb_dense* d, T** ptr, size_t count) {
-  void* raw = nullptr;
   const size_t bytes = count == 0 ? 16 : count * sizeof(T);
-  if (hipMalloc(&raw, bytes) != hipSuccess) return fail(VEMB_E_NOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
-  d->allocations.push_back(raw);
+  void* raw = d->mem.get(bytes);
+  if (!raw) return fail(VEMB_E_NOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed");
   *ptr = static_cast<T*>(raw);
   return VEMB_OK;
 }
@@ -133,6 +133,7 @@ int vemb_dense_create(const vemb_hamiltonian* H, const vemb_lattice* lat, const 
   }
 
   auto* d = new vemb_dense();
+  object_created();
   d->g = g;
   d->k = k;
   d->ld = ld;
@@ -360,11 +361,12 @@ void vemb_dense_destroy(vemb_dense* d) {
   if (!d) return;
   if (d->stream) hipStreamSynchronize(d->stream);
   if (d->side) hipStreamSynchronize(d->side);
-  for (void* p : d->allocations) hipFree(p);
+  d->mem.release();
   if (d->fork_ev) hipEventDestroy(d->fork_ev);
   if (d->join_ev) hipEventDestroy(d->join_ev);
   if (d->side) hipStreamDestroy(d->side);
   delete d;
+  object_destroyed();
 }
 
 }  // extern "C"

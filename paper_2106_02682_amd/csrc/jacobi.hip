@@ -266,8 +266,10 @@ __device__ __attribute__((always_inline)) void jacobi_body(Policy pol, int n, in
   // 3. sweeps
   const R tol = R(n > 16 ? n : 16) * eps_of<R>::v;
   int sweep = 0;
+  bool converged = false;  // a sweep rotated nothing, or the early stop applied, before the cap
   if constexpr (REG) {
     sweep = rr_sweeps<S, WARM, (NT == 256 ? 8 : 4)>(W, V, LD, max_sweeps, tol, floor2, rr_flags);
+    converged = sweep < max_sweeps;
   } else {
     const int np = (n + 1) & ~1;
     const int npair = np / 2;
@@ -362,14 +364,19 @@ __device__ __attribute__((always_inline)) void jacobi_body(Policy pol, int n, in
       }
       const int any = rotated;
       __syncthreads();
-      if (!any) break;
+      if (!any) {
+        converged = true;
+        break;
+      }
       if (block_max(rnum / rden, red) < early) {
         ++sweep;
+        converged = true;
         break;
       }
     }
   }
-  if (tid == 0) pol.record_sweeps(mat, sweep);
+  // an unconverged solve (stopped by the cap) records cap + 1
+  if (tid == 0) pol.record_sweeps(mat, converged ? sweep : max_sweeps + 1);
   if constexpr (WARM && !VFW) {
     D* vout = pol.template vslot<D>(vstore_raw, mat, (size_t)nn);
     for (int idx = tid; idx < nn; idx += NT) {
@@ -389,7 +396,11 @@ __device__ __attribute__((always_inline)) void jacobi_body(Policy pol, int n, in
   }
   __syncthreads();
   if constexpr (VFW) {
-    const bool ident = block_max(noise, red) > R(0);
+    // The normalised columns of W are an orthonormal eigenbasis of B only at convergence: a block with a
+    // noise-floor column or an unconverged solve keeps the identity, so its next solve starts cold.  (The
+    // short FP64 refinement of MIXED, cold == 2, is capped on purpose; its vectors are orthonormalised
+    // again before every use.)
+    const bool ident = block_max(noise, red) > R(0) || (!converged && cold != 2);
     D* vout = pol.template vslot<D>(vstore_raw, mat, (size_t)nn);
     for (int idx = tid; idx < nn; idx += NT) {
       const int j = idx / n, i = idx - (idx / n) * n;

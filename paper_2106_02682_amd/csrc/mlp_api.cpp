@@ -26,7 +26,7 @@ struct vemb_mlp {
   float* ws = nullptr;  // split-K workspace
   long ws_floats = 0;
   int64_t t = 0;
-  std::vector<void*> allocs;
+  vemb::DeviceMemory mem;  // every device allocation of the network
 };
 
 namespace {
@@ -36,9 +36,8 @@ constexpr int kSplitSlices = 64;
 
 template <typename T>
 int malloc_into(vemb_mlp* n, T** p, size_t count) {
-  void* raw = nullptr;
-  if (hipMalloc(&raw, std::max<size_t>(count, 1) * sizeof(T)) != hipSuccess) return fail(VEMB_E_NOMEM, "network allocation");
-  n->allocs.push_back(raw);
+  void* raw = n->mem.get(std::max<size_t>(count, 1) * sizeof(T));
+  if (!raw) return fail(VEMB_E_NOMEM, "network allocation");
   *p = static_cast<T*>(raw);
   return VEMB_OK;
 }
@@ -147,6 +146,7 @@ int vemb_mlp_create(const int32_t* dims, int n_dims, const float* params, int ma
   for (int i = 0; i < n_dims; ++i)
     if (dims[i] <= 0) return fail(VEMB_E_INVALID, "layer widths must be positive");
   auto* n = new vemb_mlp();
+  object_created();
   n->dims.assign(dims, dims + n_dims);
   n->layers = n_dims - 1;
   n->max_batch = max_batch;
@@ -301,8 +301,9 @@ void vemb_mlp_destroy(vemb_mlp* n) {
   if (!n) return;
   if (n->stream) hipStreamSynchronize(n->stream);
   else hipDeviceSynchronize();
-  for (void* p : n->allocs) hipFree(p);
+  n->mem.release();
   delete n;
+  object_destroyed();
 }
 
 }  // extern "C"

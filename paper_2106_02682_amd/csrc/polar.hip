@@ -20,6 +20,7 @@
 #include <vector>
 
 #include "mfma_tile.h"
+#include "tile_map.h"
 
 namespace vemb {
 namespace {
@@ -67,14 +68,8 @@ __global__ void __launch_bounds__(256) ns_init_kernel(const double* in, double* 
 template <int KW>
 __global__ void __launch_bounds__(64 * KW) ns_gemm_kernel(const double* P, const double* Q, const double* E,
                                                           double* out, int ld, double c0, double c1) {
-  const int tiles = ld / 16;
-  if ((int)blockIdx.x >= tiles * (tiles + 1) / 2) return;  // the grid holds the upper-triangle tiles only
-  int ti = 0, rem = blockIdx.x;
-  while (rem >= tiles - ti) {
-    rem -= tiles - ti;
-    ++ti;
-  }
-  const int tj = ti + rem;
+  int ti = 0, tj = 0;
+  if (!upper_tile((int)blockIdx.x, ld / 16, &ti, &tj)) return;  // the grid holds the upper-triangle tiles only
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
   const int r16 = l & 15, kk = l >> 4;
   const int chunk = ld / KW;  // reduction range of one wavefront (a multiple of 4)
@@ -177,7 +172,7 @@ hipError_t launch_psd_project_ns(const double* in, double* out, int ld, double* 
   double* T = Y + nn;
   double* partial = T + nn;
   const int eblocks = (int)((nn + 255) / 256);
-  const int tiles = (ld / 16) * (ld / 16 + 1) / 2;  // upper-triangle tiles
+  const int tiles = upper_tile_count(ld / 16);  // one workgroup per upper-triangle tile
   hipLaunchKernelGGL(ns_norm_kernel, dim3(kNormBlocks), dim3(256), 0, st, in, nn, partial);
   hipLaunchKernelGGL(ns_init_kernel, dim3(eblocks), dim3(256), 0, st, in, A, X, ld, partial);
   for (double a : sched) {

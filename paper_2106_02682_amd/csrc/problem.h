@@ -6,6 +6,7 @@
 #include <string>
 #include <vector>
 
+#include "alloc.h"
 #include "host_model.h"
 #include "kernels.h"
 
@@ -23,7 +24,7 @@ struct vemb_problem {
   vemb::HostModel host;
   vemb::OpTables ops_host{};
   vemb::StepArgs a{};
-  std::vector<void*> allocations;
+  vemb::DeviceMemory mem;  // every device allocation of the problem
   // device fixed data
   double *H0 = nullptr, *Hd = nullptr, *tw = nullptr, *wk = nullptr;
   int* hd_index = nullptr;
@@ -36,6 +37,7 @@ struct vemb_problem {
   double* diag_host = nullptr;
   hipEvent_t diag_ev = nullptr;
   bool diag_pending = false;
+  std::vector<double> feas_hist;  // feasibility errors of the watchdog's checks (vemb_options.lb_every)
   struct Mark { int id; hipEvent_t start, stop; };
   std::vector<Mark> marks;
   std::vector<hipEvent_t> free_events;

@@ -15,6 +15,7 @@
 #include "mfma_tile.h"
 #include "polar.h"
 #include "sign_batched.h"
+#include "tile_map.h"
 
 namespace vemb {
 namespace {
@@ -49,40 +50,58 @@ __global__ void __launch_bounds__(kSignThreads) sign_load_kernel(Policy pol, int
   for (size_t e = threadIdx.x; e < nn; e += kSignThreads) X[e] = scale_s(inv, A[e]);
 }
 
-// Per block: out(i, j) = c0 E(i, j) + c1 (P Q)(i, j) over the upper-triangle 64 x 64 tiles
-// (blockIdx.x) of block blockIdx.y; P, Q, E, out are offsets (in scalars) inside the block's 4 n^2
-// work area.  Sixteen wavefronts, one 16 x 16 sub-tile each; the reduction runs in chunks of 32:
-// the 32 x 64 slices P(k0.., i-range) and Q(k0.., j-range) are staged in LDS with coalesced row
-// reads (P(i, k) = conj(P(k, i)) read as rows of P), so every operand is read from memory once per
-// 64 x 64 tile instead of once per 16 x 16 tile.  The finished tile passes through the same LDS to
-// be written (with its conjugate mirror, or its Hermitian part on the diagonal) row by row.
+// Per block: out(i, j) = c0 E(i, j) + c1 (P Q)(i, j) over the upper-triangle 64 x 64 tiles (blockIdx.x)
+// of block blockIdx.y; P, Q, E, out are offsets (in scalars) inside the block's 4 n^2 work area.  The
+// reduction runs in chunks of KC: the KC x 64 slices P(k0.., i-range) and Q(k0.., j-range) are staged in
+// LDS with coalesced row reads (P(i, k) = conj(P(k, i)) read as rows of P).
+//   real blocks: four wavefronts, one 32 x 32 quadrant each as 2 x 2 matrix-core sub-tiles of 16 x 16,
+//     so every operand value read from LDS feeds two products (4 waves per SIMD);
+//   complex blocks: sixteen wavefronts, one 16 x 16 sub-tile each (fewer accumulator registers keep 8
+//     waves per SIMD), four real products per complex one.  (The 2 x 2 blocking of the real kernel drops
+//     the complex one to 2 waves per SIMD and measured slower; Gauss's three-product form measured no
+//     faster: these products wait on operand traffic, not on the matrix cores.)
+// The finished tile passes through LDS (rows padded by one element) and is written row by row, and an
+// off-diagonal tile's conjugate mirror row by row too: the mirror's rows are the tile's columns, read
+// across the padded rows, and E's mirror entries are the conjugates of E's entries at the mirror
+// position (E is Hermitian), so every global write and read is coalesced.  A diagonal tile stores its
+// Hermitian part.
+template <typename S> struct GemmShape;
+template <> struct GemmShape<double> { static constexpr int NT = 256, KC = 32, SUB = 2; };
+template <> struct GemmShape<cplx<double>> { static constexpr int NT = 1024, KC = 32, SUB = 1; };
+
 template <typename S>
-__global__ void __launch_bounds__(1024) sign_gemm_kernel(S* work, int n, int p_off, int q_off, int e_off, int o_off,
-                                                         double c0, double c1) {
-  constexpr int TB = 64, KC = 32;
+__global__ void __launch_bounds__(GemmShape<S>::NT) sign_gemm_kernel(S* work, int n, int count, int p_off, int q_off,
+                                                                     int e_off, int o_off, double c0, double c1) {
+  constexpr bool CPLX = scalar_traits<S>::is_complex;
+  constexpr int TB = 64, LDT = TB + 1;
+  constexpr int NT = GemmShape<S>::NT, KC = GemmShape<S>::KC, SUB = GemmShape<S>::SUB;
+  constexpr int STAGE = 2 * KC * TB, TILE = TB * LDT;
+  constexpr int NACC = CPLX ? 2 : 1;
+  constexpr int WSIDE = TB / (16 * SUB);  // wavefronts along a tile side
   const int tiles = n / TB;
-  if ((int)blockIdx.x >= tiles * (tiles + 1) / 2) return;
-  int ti = 0, rem = blockIdx.x;
-  while (rem >= tiles - ti) {
-    rem -= tiles - ti;
-    ++ti;
-  }
-  const int tj = ti + rem;
-  S* base = work + (size_t)blockIdx.y * 4 * n * n;
+  int blk = 0, ti = 0, tj = 0;
+  if (!batched_tile_of((int)blockIdx.x, (int)blockIdx.y, count, tiles, &blk, &ti, &tj)) return;  // whole workgroup
+  S* base = work + (size_t)blk * 4 * n * n;
   const S* P = base + p_off;
   const S* Q = base + q_off;
   const S* E = e_off >= 0 ? base + e_off : nullptr;
   S* out = base + o_off;
   const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
   const int r16 = l & 15, kk = l >> 4;
-  const int sr = w >> 2, sc = w & 3;  // sub-tile of this wavefront
+  const int wr = (w / WSIDE) * 16 * SUB, wc = (w % WSIDE) * 16 * SUB;  // this wavefront's corner in the tile
   // staging: Ps[k][i] = P(k0 + k, ti*64 + i), Qs[k][j] = Q(k0 + k, tj*64 + j); later the result tile
-  __shared__ S lds[2 * KC * TB];
+  __shared__ S lds[STAGE > TILE ? STAGE : TILE];
   S* Ps = lds;
   S* Qs = lds + KC * TB;
-  mf_d4 re = {0.0, 0.0, 0.0, 0.0}, im = {0.0, 0.0, 0.0, 0.0};
+  mf_d4 acc[NACC][SUB][SUB];
+#pragma unroll
+  for (int q = 0; q < NACC; ++q)
+#pragma unroll
+    for (int a = 0; a < SUB; ++a)
+#pragma unroll
+      for (int b = 0; b < SUB; ++b) acc[q][a][b] = mf_d4{0.0, 0.0, 0.0, 0.0};
   for (int k0 = 0; k0 < n; k0 += KC) {
-    for (int e = tid; e < KC * TB; e += 1024) {
+    for (int e = tid; e < KC * TB; e += NT) {
       const int k = e / TB, c = e % TB;
       Ps[e] = P[(size_t)(k0 + k) * n + ti * TB + c];
       Qs[e] = Q[(size_t)(k0 + k) * n + tj * TB + c];
@@ -90,39 +109,61 @@ __global__ void __launch_bounds__(1024) sign_gemm_kernel(S* work, int n, int p_o
     __syncthreads();
 #pragma unroll
     for (int u = 0; u < KC / 4; ++u) {
-      const S av = Ps[(4 * u + kk) * TB + sr * 16 + r16];  // A(i, k) = conj(av)
-      const S bv = Qs[(4 * u + kk) * TB + sc * 16 + r16];  // B(k, j)
-      if constexpr (scalar_traits<S>::is_complex) {
-        re = mfma_k4(av.re, bv.re, re);
-        re = mfma_k4(av.im, bv.im, re);
-        im = mfma_k4(av.re, bv.im, im);
-        im = mfma_k4(-av.im, bv.re, im);
-      } else {
-        re = mfma_k4(av, bv, re);
-      }
+      S av[SUB], bv[SUB];
+#pragma unroll
+      for (int a = 0; a < SUB; ++a) av[a] = Ps[(4 * u + kk) * TB + wr + a * 16 + r16];  // A(i, k) = conj(av)
+#pragma unroll
+      for (int b = 0; b < SUB; ++b) bv[b] = Qs[(4 * u + kk) * TB + wc + b * 16 + r16];  // B(k, j)
+#pragma unroll
+      for (int a = 0; a < SUB; ++a)
+#pragma unroll
+        for (int b = 0; b < SUB; ++b) {
+          if constexpr (CPLX) {  // conj(a) b: real a_r b_r + a_i b_i, imaginary a_r b_i - a_i b_r
+            acc[0][a][b] = mfma_k4(av[a].re, bv[b].re, acc[0][a][b]);
+            acc[0][a][b] = mfma_k4(av[a].im, bv[b].im, acc[0][a][b]);
+            acc[1][a][b] = mfma_k4(av[a].re, bv[b].im, acc[1][a][b]);
+            acc[1][a][b] = mfma_k4(-av[a].im, bv[b].re, acc[1][a][b]);
+          } else {
+            acc[0][a][b] = mfma_k4(av[a], bv[b], acc[0][a][b]);
+          }
+        }
     }
     __syncthreads();
   }
-  // the finished 64 x 64 tile into LDS: Ts[r][c]
+  // the finished 64 x 64 tile into LDS: Ts[r][c] with padded rows
   S* Ts = lds;
 #pragma unroll
-  for (int g = 0; g < 4; ++g) {
-    const int r = sr * 16 + mfma_row<double>(l, g), c = sc * 16 + r16;
-    if constexpr (scalar_traits<S>::is_complex)
-      Ts[r * TB + c] = S{re[g], im[g]};
-    else
-      Ts[r * TB + c] = re[g];
-  }
+  for (int a = 0; a < SUB; ++a)
+#pragma unroll
+    for (int b = 0; b < SUB; ++b)
+#pragma unroll
+      for (int g = 0; g < 4; ++g) {
+        const int r = wr + a * 16 + mfma_row<double>(l, g), c = wc + b * 16 + r16;
+        if constexpr (CPLX) {
+          Ts[r * LDT + c] = S{acc[0][a][b][g], acc[1][a][b][g]};
+        } else {
+          Ts[r * LDT + c] = acc[0][a][b][g];
+        }
+      }
   __syncthreads();
-  for (int e = tid; e < TB * TB; e += 1024) {
+  // the tile, row by row: out(ti*64 + r, tj*64 + c)
+  for (int e = tid; e < TB * TB; e += NT) {
     const int r = e / TB, c = e % TB;
-    S v = Ts[e];
-    if (ti == tj) v = herm_part<S>(v, Ts[c * TB + r]);
+    S v = Ts[r * LDT + c];
+    if (ti == tj) v = herm_part<S>(v, Ts[c * LDT + r]);
     S val = scale_s(c1, v);
     const size_t o = (size_t)(ti * TB + r) * n + tj * TB + c;
     if (E) val = val + scale_s(c0, E[o]);
     out[o] = val;
-    if (ti != tj) out[(size_t)(tj * TB + c) * n + ti * TB + r] = conjugate(val);
+  }
+  if (ti == tj) return;
+  // the conjugate mirror, row by row: out(tj*64 + r, ti*64 + c) = conj(value at (ti*64 + c, tj*64 + r))
+  for (int e = tid; e < TB * TB; e += NT) {
+    const int r = e / TB, c = e % TB;
+    const size_t o = (size_t)(tj * TB + r) * n + ti * TB + c;
+    S val = scale_s(c1, conjugate(Ts[c * LDT + r]));
+    if (E) val = val + scale_s(c0, E[o]);  // conj(E(ti*64 + c, tj*64 + r)) = E(o)
+    out[o] = val;
   }
 }
 
@@ -149,8 +190,8 @@ void gemm(S* work, int n, int count, int p, int q, int e, int o, double c0, doub
           const LaunchHook* hook) {
   const int tiles = n / 64;
   if (hook) hook->fn(hook->ctx, 0, st);
-  hipLaunchKernelGGL((sign_gemm_kernel<S>), dim3(tiles * (tiles + 1) / 2, count), dim3(1024), 0, st, work, n, p, q,
-                     e, o, c0, c1);
+  hipLaunchKernelGGL((sign_gemm_kernel<S>), dim3(upper_tile_count(tiles), count), dim3(GemmShape<S>::NT), 0, st, work,
+                     n, count, p, q, e, o, c0, c1);
   if (hook) hook->fn(hook->ctx, 1, st);
 }
 

@@ -38,7 +38,7 @@ EXPORTS = [
     "vemb_dense_step", "vemb_dense_dual_bound", "vemb_dense_primal_energy", "vemb_dense_get_state",
     "vemb_dense_set_state", "vemb_dense_last_sweeps", "vemb_dense_destroy", "vemb_psd_project_sign",
     "vemb_set_profiling_every", "vemb_psd_project_sign_noalloc", "vemb_batch_set_profiling",
-    "vemb_batch_get_profile",
+    "vemb_batch_get_profile", "vemb_tile_map", "vemb_set_allocator", "vemb_divergence_check",
 ]
 BATCH_KERNELS = ["pair_update", "pair_xstep", "cluster_update", "dft_forward", "dft_inverse", "pair_jacobi",
                  "momentum_jacobi", "sign_gemm_real", "sign_gemm_complex"]
@@ -73,7 +73,7 @@ class vemb_options(ctypes.Structure):
     _fields_ = [("mu", ctypes.c_double), ("nu", ctypes.c_double), ("eps", ctypes.c_double),
                 ("opset", ctypes.c_int32), ("precision", ctypes.c_int32), ("max_sweeps", ctypes.c_int32),
                 ("sign", ctypes.c_int32), ("warm_refresh", ctypes.c_int32), ("tpb", ctypes.c_int32),
-                ("fermionic", ctypes.c_int32)]
+                ("fermionic", ctypes.c_int32), ("lb_every", ctypes.c_int32)]
 
 
 class vemb_info(ctypes.Structure):
@@ -161,6 +161,10 @@ def lib():
     L.vemb_batch_primal_energies.argtypes = [vp, _DP, _DP]
     L.vemb_batch_info.argtypes = [vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
     L.vemb_batch_sync.argtypes = [vp]
+    L.vemb_set_allocator.argtypes = [ALLOC_FN, FREE_FN, vp]
+    L.vemb_divergence_check.argtypes = [_DP, ctypes.c_int, ctypes.c_double, ctypes.c_double]
+    L.vemb_tile_map.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
+                                ctypes.POINTER(ctypes.c_int)]
     L.vemb_batch_set_profiling.argtypes = [vp, ctypes.c_int]
     L.vemb_batch_get_profile.argtypes = [vp, ctypes.POINTER(vemb_batch_profile)]
     L.vemb_batch_destroy.argtypes = [vp]
@@ -216,12 +220,91 @@ def _ptr(a):
     return a.ctypes.data_as(_DP) if a is not None else None
 
 
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
+
+class TorchAllocator:
+    """Device memory of the library from torch's caching allocator (vemb_set_allocator).
+
+    Each request becomes a uint8 tensor on the current device, kept alive here until the library
+    returns its pointer; the library frees only after synchronising the streams that used the memory.
+    ``count`` / ``bytes`` tally every request, ``live`` maps the outstanding pointers to their tensors."""
+
+    def __init__(self):
+        self.live = {}
+        self.count = 0
+        self.bytes = 0
+        self.frees = 0
+
+        def _alloc(nbytes, ctx):
+            try:
+                import torch
+
+                t = torch.empty(int(nbytes) + 256, dtype=torch.uint8, device="cuda")
+                ptr = (t.data_ptr() + 255) & ~255
+                self.live[ptr] = t
+                self.count += 1
+                self.bytes += int(nbytes)
+                return ptr
+            except Exception:  # noqa: BLE001 -- no exception may cross into the library
+                return None
+
+        def _free(ptr, ctx):
+            try:
+                if self.live.pop(int(ptr), None) is not None:
+                    self.frees += 1
+            except Exception:  # noqa: BLE001
+                pass
+
+        self._alloc = ALLOC_FN(_alloc)
+        self._free = FREE_FN(_free)
+
+    def install(self):
+        _check(lib().vemb_set_allocator(self._alloc, self._free, None))
+
+    @staticmethod
+    def uninstall():
+        """Back to hipMalloc / hipFree (no library object may be alive)."""
+        _check(lib().vemb_set_allocator(ALLOC_FN(), FREE_FN(), None))
+
+
+_allocator = None
+_allocator_decided = False
+
+
+def torch_allocator():
+    """The TorchAllocator the binding installed, or None (no GPU, or VEMB_ALLOCATOR=hip)."""
+    _ensure_allocator()
+    return _allocator
+
+
+def _ensure_allocator():
+    """Before the first device allocation: route the library's device memory through torch's caching
+    allocator when torch has a GPU (set VEMB_ALLOCATOR=hip to keep hipMalloc)."""
+    global _allocator, _allocator_decided
+    if _allocator_decided:
+        return
+    _allocator_decided = True
+    if os.environ.get("VEMB_ALLOCATOR", "torch") == "hip":
+        return
+    try:
+        import torch
+    except ImportError:
+        return
+    if torch.cuda.is_available():
+        a = TorchAllocator()
+        a.install()
+        _allocator = a
+
+
 def current_stream():
     """torch's current HIP stream as a void pointer (NULL when torch has no GPU)."""
     try:
         import torch
 
         if torch.cuda.is_available():
+            _ensure_allocator()
             return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
     except ImportError:
         pass
@@ -235,7 +318,7 @@ def default_options():
 
 
 def _marshal(terms, extent, cluster, opset, precision, mu, nu, eps, max_sweeps, sign, warm_refresh, tpb,
-             fermionic=False):
+             fermionic=False, lb_every=0):
     """ctypes structs of a term list (``synth`` format: (coeff, ((pauli, (ox, oy)), ...))), lattice,
     clusters and options; the term array is returned too, to stay alive with the Hamiltonian."""
     arr = (vemb_term * max(1, len(terms)))()
@@ -259,16 +342,18 @@ def _marshal(terms, extent, cluster, opset, precision, mu, nu, eps, max_sweeps, 
     o.warm_refresh = warm_refresh
     o.tpb = tpb
     o.fermionic = 1 if fermionic else 0
+    o.lb_every = int(lb_every)
     return H, lat, cl, o, arr
 
 
 def create_problem(terms, extent, cluster, opset="complete", precision="fp64", mu=10.0, nu=10.0, eps=2.0,
-                   max_sweeps=40, sign=-1, warm_refresh=64, tpb=0, stream=None, fermionic=False):
+                   max_sweeps=40, sign=-1, warm_refresh=64, tpb=0, stream=None, fermionic=False, lb_every=0):
     """Terms in the ``synth`` format: (coeff, ((pauli, (ox, oy)), ...)); "F" letters are the ends of a
     fermionic hopping (fermionic problems)."""
     H, lat, cl, o, _keep = _marshal(terms, extent, cluster, opset, precision, mu, nu, eps, max_sweeps, sign,
-                                    warm_refresh, tpb, fermionic)
+                                    warm_refresh, tpb, fermionic, lb_every)
     h = ctypes.c_void_p()
+    _ensure_allocator()
     st = stream if stream is not None else current_stream()
     _check(lib().vemb_create_problem(ctypes.byref(H), ctypes.byref(lat), ctypes.byref(cl), ctypes.byref(o), st,
                                      ctypes.byref(h)))
@@ -391,6 +476,17 @@ def psd_project_sign_noalloc(inp, out, stream=None):
                                                st))
 
 
+def tile_map(kind, n, count=1):
+    """(grid, map) of the symmetric-product kernels (see vemb_tile_map): map is an int array (grid, 4) of
+    {live, block, tile row, tile column} per workgroup.  Host only: needs no GPU."""
+    g = ctypes.c_int()
+    _check(lib().vemb_tile_map(int(kind), int(n), int(count), ctypes.byref(g), None))
+    m = np.zeros((g.value, 4), dtype=np.int32)
+    _check(lib().vemb_tile_map(int(kind), int(n), int(count), ctypes.byref(g),
+                               m.ctypes.data_as(ctypes.POINTER(ctypes.c_int))))
+    return g.value, m
+
+
 def psd_project_batched_ex(inp, out, is_complex=False, precision="fp64", max_sweeps=0, sweeps=None, tpb=0,
                            stream=None):
     """As psd_project_batched; ``sweeps`` is an optional int32 device tensor of length batch, ``tpb`` the
@@ -436,10 +532,21 @@ def problem_threads(h):
     return a.value, b.value
 
 
-def last_sweeps(h):
+def last_sweeps(h, check=True):
+    """(pair max, momentum max) sweeps of the last iteration; raises VembError (VEMB_E_NOCONV) when an
+    eigensolve stopped unconverged, unless check=False, which returns (pair, momentum, status)."""
     a, b = ctypes.c_int(), ctypes.c_int()
-    _check(lib().vemb_last_sweeps(h, ctypes.byref(a), ctypes.byref(b)))
+    rc = lib().vemb_last_sweeps(h, ctypes.byref(a), ctypes.byref(b))
+    if not check:
+        return a.value, b.value, rc
+    _check(rc)
     return a.value, b.value
+
+
+def divergence_check(feas, lb, energy):
+    """The watchdog's decision (vemb_divergence_check) on a feasibility history: 0, or the status code."""
+    f = np.ascontiguousarray(feas, dtype=np.float64)
+    return lib().vemb_divergence_check(_ptr(f), len(f), float(lb), float(energy))
 
 
 def eigvalsh_batched(inp, w, is_complex=False, stream=None):
@@ -475,8 +582,8 @@ class Problem:
     def dual_bound(self):
         return dual_bound(self.h)
 
-    def last_sweeps(self):
-        return last_sweeps(self.h)
+    def last_sweeps(self, check=True):
+        return last_sweeps(self.h, check)
 
     def set_profiling(self, enable=True, kernels=None):
         set_profiling(self.h, enable, kernels)
@@ -639,6 +746,7 @@ class MLP:
         if params is not None:
             params = np.ascontiguousarray(params, dtype=np.float32)
             p = _fp(params)
+        _ensure_allocator()
         st = current_stream() if stream is None else stream
         _check(lib().vemb_mlp_create(arr, len(self.dims), p, int(max_batch), st, ctypes.byref(out)))
         self.h = out
@@ -728,6 +836,7 @@ class Dense:
             farr[f].pauli = PAULI[letter]
             farr[f].coeff = float(coeff)
         self.h = ctypes.c_void_p()
+        _ensure_allocator()
         st = stream if stream is not None else current_stream()
         _check(lib().vemb_dense_create(ctypes.byref(H), ctypes.byref(lat), ctypes.byref(cl), farr, len(fields),
                                        ctypes.byref(o), st, ctypes.byref(self.h)))
