@@ -93,12 +93,12 @@ def batch_work(infos):
         w["pair_xstep"] += 8.0 * P * (2 * k * k + n * n)
         w["dft_forward"] += 8.0 * (M + 2 * Ku) * k * k
         w["dft_inverse"] += 8.0 * (M + 2 * Ku) * k * k
-        if n > 64 and i.get("precision", "fp64") == "fp64":
+        if n > 64:  # 256 x 256 blocks: sign-function products in every precision
             sign["sign_gemm_real"][n] = sign["sign_gemm_real"].get(n, 0) + P
         else:
             jac["pair_jacobi"][0] += 11.0 * n ** 3 * P
             jac["pair_jacobi"][1].add(n)
-        if k > 64 and i.get("precision", "fp64") == "fp64":
+        if k > 64:
             sign["sign_gemm_complex"][k] = sign["sign_gemm_complex"].get(k, 0) + Ku
         else:
             jac["momentum_jacobi"][0] += 44.0 * k ** 3 * Ku
@@ -387,6 +387,52 @@ def c2b_leg(args):
     }, w
 
 
+def precision_leg(args):
+    """FP64 against MIXED (FP32 eigensolves: Jacobi sweeps, matrix-core rebuilds and sign-function products;
+    FP64 state and diagnostics) on the batched sweep, the N = 384 ring and the 16 x 16 torus with 2 x 2
+    clusters: ms per step of each, timed like the headline (warm-up, then synchronised steps)."""
+    import torch
+
+    import synth
+    from paper_2106_02682_amd import vemb
+
+    def time_problem(w, prec, steps):
+        with vemb.Problem.from_workload(w, precision=prec) as g:
+            g.step(args.warmup)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            g.step(steps)
+            torch.cuda.synchronize()
+            return (time.perf_counter() - t0) / steps * 1e3, g.info["P"]
+
+    def time_batch(prec, steps):
+        probs = [vemb.Problem.from_workload(synth.instance_workload(d, name=f"c4_{i}"), precision=prec)
+                 for i, d in enumerate(synth.c4_instances(64))]
+        P = sum(p.info["P"] for p in probs)
+        with vemb.Batch(probs) as b:
+            b.step(args.warmup)
+            b.sync()
+            t0 = time.perf_counter()
+            b.step(steps)
+            b.sync()
+            dt = (time.perf_counter() - t0) / steps * 1e3
+        for p in probs:
+            p.close()
+        return dt, P
+
+    out = {}
+    log("precision modes: batched sweep in MIXED")
+    ms, P = time_batch("mixed", args.steps)
+    out["c4"] = {"mixed_ms_per_step": ms, "mixed_projections_per_s": P / ms * 1e3}
+    for name, w, steps in (("c2b", synth.config_c2(args.h)[1], 300), ("c3b", synth.config_c3()[1], 20)):
+        log(f"precision modes: {w.name}")
+        m64, P = time_problem(w, "fp64", steps)
+        m32, _ = time_problem(w, "mixed", steps)
+        out[name] = {"fp64_ms_per_step": m64, "mixed_ms_per_step": m32, "speedup": m64 / m32,
+                     "pair_blocks": P}
+    return out
+
+
 def profile_leg(args):
     """A fixed run for rocprofv3 (kernel traces and counters): the workload's steps after a warm-up, then one
     plain device copy of 256 MiB (torch's elementwise copy) whose FETCH_SIZE / WRITE_SIZE readings calibrate
@@ -592,6 +638,7 @@ def main():
                                                                     "the CPU baseline)")
     ap.add_argument("--cpu-workers", type=int, default=16, help="processes of the all-cores oracle baseline")
     ap.add_argument("--c2b", type=int, default=1, help="add the c2b object to the c4 line (0 skips it)")
+    ap.add_argument("--mixed", type=int, default=1, help="add the FP64-vs-MIXED timings to the c4 line (0 skips)")
     ap.add_argument("--warm", type=int, default=1, help="run the learned warm-start leg (0 skips it)")
     ap.add_argument("--warm-train", type=int, default=256)
     ap.add_argument("--warm-train-iters", type=int, default=30000)
@@ -637,6 +684,10 @@ def main():
         out, _ = c4_leg(args)
         if args.c2b:
             out["c2b"], _ = c2b_leg(args)
+        if args.mixed and args.precision == "fp64":
+            out["precision_modes"] = precision_leg(args)
+            out["precision_modes"]["c4"]["fp64_ms_per_step"] = out["ms_per_step"]
+            out["precision_modes"]["c4"]["speedup"] = out["ms_per_step"] / out["precision_modes"]["c4"]["mixed_ms_per_step"]
     else:
         c2, _ = c2b_leg(args)
         out = {"metric": METRIC, "value": c2["value"], "unit": "projections/s", "n_gpus": 1, "steps": c2["steps"],

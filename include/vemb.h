@@ -86,9 +86,15 @@ typedef struct {
 } vemb_clusters;
 
 enum vemb_opset { VEMB_OPSET_COMPLETE = 0, VEMB_OPSET_PAULI1 = 1 };
-/* VEMB_FP64: FP64 eigensolves.  VEMB_MIXED: FP32 Jacobi sweeps find the eigenvectors,
- * then one FP64 sweep warm-started from them and an FP64 rebuild.  VEMB_FP32: FP32
- * sweeps and rebuilds (state, diagnostics and vemb_refine stay FP64). */
+/* Precision of a problem's iterations.  VEMB_FP64: every eigensolve in FP64.  VEMB_MIXED: the
+ * eigensolves of vemb_step run in FP32 -- Jacobi rotations, the rebuild on FP32 matrix cores with FP32
+ * accumulation, and for 256 x 256 blocks the sign-function products on FP32 matrix cores (eigenvalues
+ * above 1e-6 of the block's norm resolved); the state stays FP64, and so do the diagnostics (bound,
+ * energy, feasibility residuals) and vemb_refine, the closing FP64 iterations warm-started from the FP32
+ * eigenvectors.  The bound of an FP32 iterate is evaluated in FP64 on an X that is PSD to FP32 rounding;
+ * after vemb_refine it is certified.  VEMB_FP32: the same as VEMB_MIXED for problems.  For the isolated
+ * vemb_psd_project_batched, VEMB_MIXED means FP32 sweeps followed by one FP64 refinement sweep and an
+ * FP64 rebuild, VEMB_FP32 FP32 throughout. */
 enum vemb_precision { VEMB_FP64 = 0, VEMB_MIXED = 1, VEMB_FP32 = 2 };
 
 typedef struct {
@@ -158,10 +164,10 @@ int vemb_problem_info(const vemb_problem* p, vemb_info* info);
  * Asynchronous: returns once the work is enqueued. */
 int vemb_step(vemb_problem* p, int iters);
 
-/* Mixed precision's final refinement: enqueues `iters` iterations whose
- * eigensolves run in FP64, warm-started from the eigenvectors the FP32 solves
- * kept, so one or two FP64 sweeps each remain.  Same as vemb_step for an FP64
- * problem.  Asynchronous. */
+/* Mixed precision's final refinement: enqueues `iters` iterations whose eigensolves run in FP64;
+ * the first starts from the eigenvectors the FP32 solves kept, orthonormalised by one Newton-Schulz
+ * step (256 x 256 blocks: the FP64 sign function).  Same as vemb_step for an FP64 problem.
+ * Asynchronous. */
 int vemb_refine(vemb_problem* p, int iters);
 
 /* FP64 Lagrangian lower bound per site (valid for any PSD X and any symmetric
@@ -405,7 +411,8 @@ void vemb_batch_destroy(vemb_batch* b);
  * (H_ij = H_0d with d the offset from i to j); one-site fields may differ from
  * site to site (disorder), which translation invariance cannot represent.
  * Limits: K <= 1024, pair matrices n <= 256.  K <= 64: the X projection is a
- * one-sided Jacobi eigensolve (precision modes and warm starts as vemb_problem).
+ * one-sided Jacobi eigensolve (warm starts as vemb_problem; precision modes as the isolated
+ * vemb_psd_project_batched: MIXED = FP32 sweeps, one FP64 refinement sweep and an FP64 rebuild).
  * K > 64: Pi(A) = (A + A sign(A)) / 2 with sign(A) from a fixed schedule of 38
  * scaled Newton-Schulz steps on matrix cores (FP64 in every precision mode; X
  * stored padded with zeros to a multiple of 32), resolving every eigenvalue

@@ -419,8 +419,8 @@ int vemb_create_problem(const vemb_hamiltonian* H, const vemb_lattice* lat, cons
       (rc = dalloc(p, &a.Vpair, (size_t)P * n * n)) || (rc = dalloc(p, &a.Vmom, (size_t)2 * Ku * k * k)) ||
       (n > 64 && ((rc = dalloc(p, (double**)&a.wscr_pair, (size_t)P * n * n)) ||
                   (rc = dalloc(p, (double**)&a.tscr_pair, (size_t)P * n * n)))) ||
-      (n > 64 && o.precision == VEMB_FP64 && (rc = dalloc(p, (char**)&p->sign_pair, sign_work_bytes(n, P, false)))) ||
-      (k > 64 && o.precision == VEMB_FP64 && (rc = dalloc(p, (char**)&p->sign_mom, sign_work_bytes(k, Ku, true)))) ||
+      (n > 64 && (rc = dalloc(p, (char**)&p->sign_pair, sign_work_bytes(n, P, false)))) ||
+      (k > 64 && (rc = dalloc(p, (char**)&p->sign_mom, sign_work_bytes(k, Ku, true)))) ||
       (k > 64 && ((rc = dalloc(p, (double**)&a.wscr_mom, (size_t)2 * Ku * k * k)) ||
                   (rc = dalloc(p, (double**)&a.tscr_mom, (size_t)2 * Ku * k * k)))))
     return cleanup(rc);
@@ -446,8 +446,8 @@ int vemb_create_problem(const vemb_hamiltonian* H, const vemb_lattice* lat, cons
   if (o.tpb == kTpbRegister8 || o.tpb == kTpbRegister4 || o.tpb == 256 || o.tpb == 512 || o.tpb == 1024) {
     p->tpb_pair = p->tpb_mom = o.tpb;
   } else {
-    p->tpb_pair = tuned_tpb(n, false, o.precision, P, s);
-    p->tpb_mom = tuned_tpb(k, true, o.precision, Ku, s);
+    p->tpb_pair = tuned_tpb(n, false, solve_precision(o.precision), P, s);
+    p->tpb_mom = tuned_tpb(k, true, solve_precision(o.precision), Ku, s);
   }
   *out = p;
   return VEMB_OK;
@@ -469,10 +469,10 @@ int vemb_problem_info(const vemb_problem* p, vemb_info* info) {
 }
 
 namespace {
-// FP64 iterations with pair and momentum blocks of 33..64 that the autotuner gave the same LDS solver
-// variant run both projections in one launch.
-bool fused_projections(const vemb_problem* p, int prec) {
-  return prec == VEMB_FP64 && !p->sign_pair && !p->sign_mom && fused_projection_fits(p->a.n, p->a.n_op) &&
+// Iterations with pair and momentum blocks of 33..64 that the autotuner gave the same LDS solver variant
+// run both projections in one launch.
+bool fused_projections(const vemb_problem* p) {
+  return !p->sign_pair && !p->sign_mom && fused_projection_fits(p->a.n, p->a.n_op) &&
          p->tpb_pair == kFusedThreads && p->tpb_mom == kFusedThreads;
 }
 
@@ -496,25 +496,31 @@ int watchdog(vemb_problem* p) {
   return diag_enqueue(p);
 }
 
+// prec: VEMB_FP64, or the problem's MIXED / FP32 mode, whose eigensolves run in FP32 (sweeps, rebuild and
+// sign-function products; state and diagnostics stay FP64).
 int run_iterations(vemb_problem* p, int iters, int prec) {
   const StepArgs& a = p->a;
   hipStream_t s = p->stream;
   const int ms = p->opt.max_sweeps;
+  const int sp = solve_precision(prec);
   for (int it = 0; it < iters; ++it) {
     const int refresh = p->opt.warm_refresh;
-    const int cold = (!p->v_valid || refresh < 0 || p->t % refresh == 0) ? 1 : 0;
+    int cold = (!p->v_valid || refresh < 0 || p->t % refresh == 0) ? 1 : 0;
+    // FP64 solves warm-started from FP32 eigenvectors restore their orthonormality first
+    if (!cold && sp == VEMB_FP64 && p->v_fp32) cold = 2;
     VEMB_TRY(timed(p, VEMB_K_PAIR_UPDATE, "pair update", [&] { return launch_pair_update(a, s); }));
     VEMB_TRY(timed(p, VEMB_K_PAIR_XSTEP, "pair X step", [&] { return launch_pair_xstep(a, s); }));
-    if (fused_projections(p, prec)) {
+    if (fused_projections(p)) {
       // both projections in one launch after the forward DFT: one stream, no fork and join
       VEMB_TRY(timed(p, VEMB_K_CLUSTER, "cluster update", [&] { return launch_cluster_update(a, s); }));
       VEMB_TRY(timed(p, VEMB_K_DFT_FWD, "forward DFT", [&] { return launch_dft_forward(a, s); }));
       VEMB_TRY(timed(p, VEMB_K_PROJ, "projections", [&] {
         return launch_projections_fused(a.rho, a.Lam, a.rho_t, a.feas, a.n, a.P, a.mu, a.Xh, a.n_op, a.Ku, ms,
-                                        a.sweeps, a.Vpair, a.Vmom, cold, s);
+                                        a.sweeps, a.Vpair, a.Vmom, cold, s, sp);
       }));
       VEMB_TRY(timed(p, VEMB_K_DFT_INV, "inverse DFT", [&] { return launch_dft_inverse(a, s); }));
       p->v_valid = true;
+      p->v_fp32 = sp != VEMB_FP64;
       ++p->t;
       if (p->opt.lb_every > 0 && p->t % p->opt.lb_every == 0) VEMB_TRY(watchdog(p));
       continue;
@@ -525,29 +531,23 @@ int run_iterations(vemb_problem* p, int iters, int prec) {
     VEMB_TRY(hip_rc(hipEventRecord(p->fork_ev, s), "fork"));
     VEMB_TRY(hip_rc(hipStreamWaitEvent(s2, p->fork_ev, 0), "fork"));
     VEMB_TRY(timed(p, VEMB_K_PAIR_PROJ, "pair projection", [&] {
-      if (prec == VEMB_FP64 && p->sign_pair)
+      if (p->sign_pair)
         return launch_pair_projection_sign(a.rho, a.Lam, a.rho_t, a.feas, a.n, a.P, a.mu, a.sweeps, p->sign_pair,
-                                           s2);
-      if (a.n > 64)
-        return launch_pair_projection_big(a.rho, a.Lam, a.rho_t, a.feas, a.n, a.P, a.mu, prec, ms, a.sweeps, a.Vpair,
-                                          cold, a.wscr_pair, a.tscr_pair, s2);
-      return launch_pair_projection(a.rho, a.Lam, a.rho_t, a.feas, a.n, a.P, a.mu, prec, ms, a.sweeps, a.Vpair, cold,
+                                           s2, sp);
+      return launch_pair_projection(a.rho, a.Lam, a.rho_t, a.feas, a.n, a.P, a.mu, sp, ms, a.sweeps, a.Vpair, cold,
                                     p->tpb_pair, s2);
     }, s2));
     VEMB_TRY(hip_rc(hipEventRecord(p->join_ev, s2), "join"));
     VEMB_TRY(timed(p, VEMB_K_CLUSTER, "cluster update", [&] { return launch_cluster_update(a, s); }));
     VEMB_TRY(timed(p, VEMB_K_DFT_FWD, "forward DFT", [&] { return launch_dft_forward(a, s); }));
     VEMB_TRY(timed(p, VEMB_K_MOM_PROJ, "momentum projection", [&] {
-      if (prec == VEMB_FP64 && p->sign_mom)
-        return launch_momentum_projection_sign(a.Xh, a.n_op, a.Ku, a.sweeps + a.P, p->sign_mom, s);
-      if (a.n_op > 64)
-        return launch_momentum_projection_big(a.Xh, a.n_op, a.Ku, prec, ms, a.sweeps + a.P, a.Vmom, cold, a.wscr_mom,
-                                              a.tscr_mom, s);
-      return launch_momentum_projection(a.Xh, a.n_op, a.Ku, prec, ms, a.sweeps + a.P, a.Vmom, cold, p->tpb_mom, s);
+      if (p->sign_mom) return launch_momentum_projection_sign(a.Xh, a.n_op, a.Ku, a.sweeps + a.P, p->sign_mom, s, sp);
+      return launch_momentum_projection(a.Xh, a.n_op, a.Ku, sp, ms, a.sweeps + a.P, a.Vmom, cold, p->tpb_mom, s);
     }));
     VEMB_TRY(timed(p, VEMB_K_DFT_INV, "inverse DFT", [&] { return launch_dft_inverse(a, s); }));
     VEMB_TRY(hip_rc(hipStreamWaitEvent(s, p->join_ev, 0), "join"));
     p->v_valid = true;
+    p->v_fp32 = sp != VEMB_FP64;
     ++p->t;
     if (p->opt.lb_every > 0 && p->t % p->opt.lb_every == 0) VEMB_TRY(watchdog(p));
   }
@@ -562,7 +562,10 @@ int project_x(vemb_problem* p) {
   hipStream_t s = p->stream;
   const int ms = p->opt.max_sweeps;
   VEMB_TRY(hip_rc(launch_dft_forward(a, s), "forward DFT"));
-  if (a.n_op > 64)
+  if (p->sign_mom)
+    VEMB_TRY(hip_rc(launch_momentum_projection_sign(a.Xh, a.n_op, a.Ku, a.sweeps + a.P, p->sign_mom, s, VEMB_FP64),
+                    "momentum projection"));
+  else if (a.n_op > 64)
     VEMB_TRY(hip_rc(launch_momentum_projection_big(a.Xh, a.n_op, a.Ku, VEMB_FP64, ms, a.sweeps + a.P, a.Vmom, 1,
                                                    a.wscr_mom, a.tscr_mom, s),
                     "momentum projection"));

@@ -129,9 +129,10 @@ int enqueue_iteration(vemb_batch* b, int cold, bool timed = false) {
     if (g.kind == 0) {
       if (!g.nscr) tm_side.before(VEMB_BK_PAIR_JACOBI, b->side);
       VEMB_TRY(hip_rc(g.nscr ? launch_projection_group_sign(0, g.n, g.count, g.d_item, b->d_pair, g.nscr, b->side,
-                                                            timed ? &side_hook : nullptr)
-                             : launch_projection_group(0, g.n, g.count, g.precision, max_sweeps, cold, g.tpb,
-                                                       g.d_item, b->d_pair, g.vstore_any, g.wscr, g.tscr, b->side),
+                                                            timed ? &side_hook : nullptr, solve_precision(g.precision))
+                             : launch_projection_group(0, g.n, g.count, solve_precision(g.precision), max_sweeps, cold,
+                                                       g.tpb, g.d_item, b->d_pair, g.vstore_any, g.wscr, g.tscr,
+                                                       b->side),
                       "batched pair projection"));
       if (!g.nscr) tm_side.after(b->side);
     }
@@ -146,9 +147,9 @@ int enqueue_iteration(vemb_batch* b, int cold, bool timed = false) {
     if (g.kind == 1) {
       if (!g.nscr) tm.before(VEMB_BK_MOM_JACOBI, s);
       VEMB_TRY(hip_rc(g.nscr ? launch_projection_group_sign(1, g.n, g.count, g.d_item, b->d_mom, g.nscr, s,
-                                                            timed ? &main_hook : nullptr)
-                             : launch_projection_group(1, g.n, g.count, g.precision, max_sweeps, cold, g.tpb,
-                                                       g.d_item, b->d_mom, g.vstore_any, g.wscr, g.tscr, s),
+                                                            timed ? &main_hook : nullptr, solve_precision(g.precision))
+                             : launch_projection_group(1, g.n, g.count, solve_precision(g.precision), max_sweeps, cold,
+                                                       g.tpb, g.d_item, b->d_mom, g.vstore_any, g.wscr, g.tscr, s),
                       "batched momentum projection"));
       if (!g.nscr) tm.after(s);
     }
@@ -271,7 +272,7 @@ int vemb_batch_create(vemb_problem* const* problems, int count, int use_graph, v
         (rc = hip_rc(hipMemcpyAsync(g.d_item, items.data(), sizeof(int2) * items.size(), hipMemcpyHostToDevice, s),
                      "class table")))
       return cleanup(rc);
-    if (g.n > 64 && g.precision == VEMB_FP64) {  // sign-function projection on matrix cores
+    if (g.n > 64) {  // sign-function projection on matrix cores (FP64, or FP32 for MIXED / FP32)
       char* w = nullptr;
       if ((rc = balloc(b, &w, sign_work_bytes(g.n, g.count, g.kind == 1)))) return cleanup(rc);
       g.nscr = w;
@@ -287,7 +288,7 @@ int vemb_batch_create(vemb_problem* const* problems, int count, int use_graph, v
       // a fixed opts->tpb is honoured; otherwise tune for the class's batch size
       const vemb_problem* first = problems[items[0].x];
       g.tpb = first->opt.tpb > 0 ? (g.kind == 0 ? first->tpb_pair : first->tpb_mom)
-                                 : tuned_tpb(g.n, g.kind == 1, g.precision, g.count, s);
+                                 : tuned_tpb(g.n, g.kind == 1, solve_precision(g.precision), g.count, s);
       if (g.tpb <= 0) return cleanup(g.tpb);
     }
     b->groups.push_back(g);
@@ -319,6 +320,7 @@ int vemb_batch_step(vemb_batch* b, int iters) {
     ++b->iter;
     for (vemb_problem* p : b->probs) {
       p->v_valid = true;
+      p->v_fp32 = solve_precision(p->opt.precision) != VEMB_FP64;
       ++p->t;
     }
   }
@@ -356,7 +358,7 @@ int vemb_batch_info(const vemb_batch* b, int* groups, int* launches_per_iteratio
   if (groups) *groups = (int)b->groups.size();
   if (launches_per_iteration) {
     int l = 5;
-    for (const auto& g : b->groups) l += g.precision == VEMB_MIXED ? 2 : 1;
+    for (const auto& g : b->groups) l += g.nscr ? sign_launches(solve_precision(g.precision)) : 1;
     *launches_per_iteration = l;
   }
   return VEMB_OK;

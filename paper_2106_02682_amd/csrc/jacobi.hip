@@ -488,19 +488,19 @@ __global__ void __launch_bounds__(NT) jacobi_kernel(Policy pol, int n, int max_s
 }
 
 // The pair and momentum projections of one iteration in one launch: workgroups below P take the
-// (real) pair blocks, the rest the (complex) momentum blocks, both warm-started FP64 solves of
-// blocks of 33..64 with NT threads.  The two sets touch disjoint data, and one launch on one stream
-// needs no fork and join between streams.
-template <int NT>
+// (real) pair blocks, the rest the (complex) momentum blocks, both warm-started solves of blocks of
+// 33..64 with NT threads, in the real type R (FP64, or FP32 with the FP32 rebuild).  The two sets touch
+// disjoint data, and one launch on one stream needs no fork and join between streams.
+template <int NT, typename R>
 __global__ void __launch_bounds__(NT) fused_projection_kernel(PairPolicy pp, int n, int P, MomentumPolicy mp, int n_op,
                                                               int max_sweeps, void* vpair, void* vmom, int cold) {
-  constexpr size_t bp = JacobiLds<double, 64, true, NT>::bytes, bm = JacobiLds<cplx<double>, 64, true, NT>::bytes;
+  constexpr size_t bp = JacobiLds<R, 64, true, NT>::bytes, bm = JacobiLds<cplx<R>, 64, true, NT>::bytes;
   __shared__ __attribute__((aligned(16))) unsigned char smem[bp > bm ? bp : bm];
   if ((int)blockIdx.x < P)
-    jacobi_body<double, 64, kProject, true, NT, PairPolicy>(pp, n, max_sweeps, vpair, cold, blockIdx.x, smem);
+    jacobi_body<R, 64, kProject, true, NT, PairPolicy>(pp, n, max_sweeps, vpair, cold, blockIdx.x, smem);
   else
-    jacobi_body<cplx<double>, 64, kProject, true, NT, MomentumPolicy>(mp, n_op, max_sweeps, vmom, cold,
-                                                                       (int)blockIdx.x - P, smem);
+    jacobi_body<cplx<R>, 64, kProject, true, NT, MomentumPolicy>(mp, n_op, max_sweeps, vmom, cold,
+                                                                  (int)blockIdx.x - P, smem);
 }
 
 // vstore == nullptr: cold solve without eigenvector storage.  Otherwise the
@@ -588,12 +588,16 @@ hipError_t launch_momentum_projection(double* Xh, int n_op, int K, int precision
 
 hipError_t launch_projections_fused(const double* rho, double* Lam, double* rho_t, double* feas, int n, int P,
                                    double mu, double* Xh, int n_op, int K, int max_sweeps, int* sweeps, double* vpair,
-                                   double* vmom, int cold, hipStream_t st) {
+                                   double* vmom, int cold, hipStream_t st, int precision) {
   if (!fused_projection_fits(n, n_op) || !vpair || !vmom || P <= 0 || K <= 0) return hipErrorInvalidValue;
   PairPolicy pp{rho, Lam, rho_t, feas, sweeps, n, mu};
   MomentumPolicy mp{Xh, sweeps + P, n_op};
-  hipLaunchKernelGGL(fused_projection_kernel<kFusedThreads>, dim3(P + K), dim3(kFusedThreads), 0, st, pp, n, P, mp,
-                     n_op, max_sweeps, vpair, vmom, cold);
+  if (precision == VEMB_FP64)
+    hipLaunchKernelGGL((fused_projection_kernel<kFusedThreads, double>), dim3(P + K), dim3(kFusedThreads), 0, st, pp, n,
+                       P, mp, n_op, max_sweeps, vpair, vmom, cold);
+  else
+    hipLaunchKernelGGL((fused_projection_kernel<kFusedThreads, float>), dim3(P + K), dim3(kFusedThreads), 0, st, pp, n,
+                       P, mp, n_op, max_sweeps, vpair, vmom, cold);
   return hipGetLastError();
 }
 

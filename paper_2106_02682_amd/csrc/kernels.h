@@ -44,14 +44,15 @@ hipError_t launch_pair_projection(const double* rho, double* Lam, double* rho_t,
 hipError_t launch_momentum_projection(double* Xh, int n_op, int K, int precision, int max_sweeps, int* sweeps,
                                       double* vstore, int cold, int tpb, hipStream_t st);
 
-// Both of the above in one launch (FP64, warm-started, kFusedThreads threads per workgroup), for
-// pair and momentum blocks of 33..64: workgroups [0, P) take the pair blocks, [P, P + K) the
-// momentum blocks.  vpair / vmom: the two eigenvector stores; sweeps[0, P) and sweeps[P, P + K).
+// Both of the above in one launch (warm-started, kFusedThreads threads per workgroup), for pair and
+// momentum blocks of 33..64: workgroups [0, P) take the pair blocks, [P, P + K) the momentum blocks.
+// vpair / vmom: the two eigenvector stores; sweeps[0, P) and sweeps[P, P + K).  precision: VEMB_FP64
+// solves in FP64, VEMB_FP32 in FP32 (sweeps and matrix-core rebuild; state stays FP64).
 constexpr int kFusedThreads = 512;
 inline bool fused_projection_fits(int n, int n_op) { return n > 32 && n <= 64 && n_op > 32 && n_op <= 64; }
 hipError_t launch_projections_fused(const double* rho, double* Lam, double* rho_t, double* feas, int n, int P,
                                    double mu, double* Xh, int n_op, int K, int max_sweeps, int* sweeps, double* vpair,
-                                   double* vmom, int cold, hipStream_t st);
+                                   double* vmom, int cold, hipStream_t st, int precision = VEMB_FP64);
 
 // Isolated batched projection / eigenvalues (ABI entry points).
 // vstore: eigenvector scratch (batch x n x n, complex doubles for Hermitian), needed by MIXED.

@@ -8,8 +8,9 @@
 
 namespace vemb {
 
-// Scaling factors a_k of the iteration for a resolved fraction l0 of ||A||_F (host).
-std::vector<double> ns_schedule(double l0);
+// Scaling factors a_k of the iteration for a resolved fraction l0 of ||A||_F (host), until the
+// resolved bound l_k is within `stop` of 1.
+std::vector<double> ns_schedule(double l0, double stop = 1e-15);
 
 // out = Pi((in + in^T) / 2) for one ld x ld matrix, ld a multiple of 16 (row-major, FP64).
 // work: 4 ld^2 + 64 doubles of device scratch.  `in` may alias `out`.  Enqueued on st.
@@ -18,6 +19,11 @@ hipError_t launch_psd_project_ns(const double* in, double* out, int ld, double* 
 
 // Resolved fraction used by the library: eigenvalues below 1e-14 ||A||_F may stay partly unresolved.
 constexpr double kNsResolved = 1e-14;
+constexpr double kNsStop = 1e-15;
+// FP32 iterations: eigenvalues below 1e-6 ||A||_F, and the last 1e-7 of the convergence to 1 (FP32
+// rounding), are left.
+constexpr double kNsResolved32 = 1e-6;
+constexpr double kNsStop32 = 1e-7;
 
 // The schedule for kNsResolved, computed once on the host.
 const std::vector<double>& ns_schedule_resolved();

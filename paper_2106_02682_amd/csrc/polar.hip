@@ -151,10 +151,10 @@ const std::vector<double>& ns_schedule_resolved() {
   return sched;
 }
 
-std::vector<double> ns_schedule(double l0) {
+std::vector<double> ns_schedule(double l0, double stop) {
   std::vector<double> a;
   double l = l0;
-  while (1.0 - l > 1e-15 && a.size() < 64) {
+  while (1.0 - l > stop && a.size() < 64) {
     const double al = std::sqrt(3.0 / (1.0 + l + l * l));
     a.push_back(al);
     l = 0.5 * al * l * (3.0 - al * al * l * l);

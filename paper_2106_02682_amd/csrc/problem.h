@@ -43,6 +43,7 @@ struct vemb_problem {
   std::vector<hipEvent_t> free_events;
   double prof_ms[VEMB_K_COUNT] = {};
   bool v_valid = false;  // Vpair / Vmom hold eigenvectors of the previous iteration
+  bool v_fp32 = false;   // ... found by FP32 solves (an FP64 solve orthonormalises them first)
   double* Kv = nullptr;   // eigenvectors of the bound matrices (pair blocks up to 128), kept between bounds
   bool k_valid = false;
   int64_t k_uses = 0;  // bound evaluations; every 16th restarts them cold (orthogonality drift)
@@ -54,6 +55,9 @@ struct vemb_problem {
 };
 
 namespace vemb {
+// The arithmetic of a mode's per-iteration eigensolves: FP64 for VEMB_FP64, FP32 for MIXED and FP32
+// (state, diagnostics and vemb_refine stay FP64).
+inline int solve_precision(int precision) { return precision == VEMB_FP64 ? VEMB_FP64 : VEMB_FP32; }
 int fail(int code, const std::string& msg);
 int hip_rc(hipError_t e, const char* what);
 int tuned_tpb(int n, bool cplx, int precision, int count, hipStream_t st);

@@ -8,16 +8,19 @@ namespace vemb {
 
 constexpr int kSignMax = 256;  // block size handled (a multiple of 64, at most this)
 
-// Scratch per block: 4 n^2 scalars (doubles for pairs, complex doubles for momentum blocks).
+// Scratch per block: 4 n^2 scalars (doubles for pairs, complex doubles for momentum blocks; half for
+// FP32), sized here for FP64, which covers both precisions.
 inline size_t sign_work_bytes(int n, int count, bool cplx) {
   return (size_t)count * 4 * n * n * (cplx ? 16 : 8);
 }
 
+// precision: VEMB_FP64 computes in FP64; any other mode in FP32 (matrix cores in FP32, state in FP64).
 // Pair step 3 + Lambda update (as launch_pair_projection) for P blocks of size n.
 hipError_t launch_pair_projection_sign(const double* rho, double* Lam, double* rho_t, double* feas, int n, int P,
-                                       double mu, int* sweeps, void* work, hipStream_t st);
+                                       double mu, int* sweeps, void* work, hipStream_t st, int precision = VEMB_FP64);
 // Step 8 in place (as launch_momentum_projection) for K complex blocks of size n_op.
-hipError_t launch_momentum_projection_sign(double* Xh, int n_op, int K, int* sweeps, void* work, hipStream_t st);
+hipError_t launch_momentum_projection_sign(double* Xh, int n_op, int K, int* sweeps, void* work, hipStream_t st,
+                                           int precision = VEMB_FP64);
 // Optional callback around each product launch of a sign projection (timing): phase 0 before the
 // launch, 1 after it, on the launch's stream.  Null = none.
 struct LaunchHook {
@@ -27,7 +30,10 @@ struct LaunchHook {
 
 // A batch size class (kind 0 pairs, 1 momentum blocks) through the batched policies.
 hipError_t launch_projection_group_sign(int kind, int n, int count, const int2* item, const void* ptrs, void* work,
-                                        hipStream_t st, const LaunchHook* hook = nullptr);
+                                        hipStream_t st, const LaunchHook* hook = nullptr, int precision = VEMB_FP64);
+
+// Kernel launches of one sign-function projection (load, the products, store) in a precision.
+int sign_launches(int precision);
 
 // Real flops of one product launch over `count` blocks of size n: the upper-triangle 64 x 64 tiles
 // of each block, 2 flops per multiply-add, four real products per complex one.

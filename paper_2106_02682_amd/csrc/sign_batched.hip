@@ -1,9 +1,10 @@
 // PSD projections of many 256 x 256 blocks (pair blocks of 4-site clusters, real; momentum blocks,
-// complex Hermitian) through the matrix sign function on matrix cores, FP64.
+// complex Hermitian) through the matrix sign function on matrix cores, in FP64 or FP32.
 //
 // Pi(A) = (A + A sign(A)) / 2 with sign(A) from the scaled Newton-Schulz schedule of polar.hip
-// (X_0 = A / (1.01 ||A||_F), 38 steps X <- (a/2) X (3I - a^2 X^2), every eigenvalue above
-// 1e-14 ||A||_F resolved).  A one-sided Jacobi solve of one 256 x 256 block runs on one workgroup
+// (X_0 = A / (1.01 ||A||_F), steps X <- (a/2) X (3I - a^2 X^2)): FP64 resolves every eigenvalue above
+// 1e-14 ||A||_F (38 steps), FP32 every eigenvalue above 1e-6 ||A||_F, about its own rounding level
+// (v_mfma_f32_16x16x4_f32, twice the FP64 rate, half the bytes, and fewer steps).  A one-sided Jacobi solve of one 256 x 256 block runs on one workgroup
 // with its columns streamed through L2; here every step is a batched product over all blocks, one
 // workgroup per upper-triangle 64 x 64 tile per block, so the chip is filled by tiles.  The blocks
 // are read and written through the eigensolver's policies (pair: C = rho - Lambda/mu in, rho~ and the
@@ -22,13 +23,12 @@ namespace {
 
 constexpr int kSignThreads = 256;
 
-template <typename S> __device__ inline S herm_part(S a, S at);
-template <> __device__ inline double herm_part<double>(double a, double at) { return 0.5 * (a + at); }
-template <> __device__ inline cplx<double> herm_part<cplx<double>>(cplx<double> a, cplx<double> at) {
-  return {0.5 * (a.re + at.re), 0.5 * (a.im - at.im)};
+template <typename R> __device__ inline R herm_part(R a, R at) { return R(0.5) * (a + at); }
+template <typename R> __device__ inline cplx<R> herm_part(cplx<R> a, cplx<R> at) {
+  return {R(0.5) * (a.re + at.re), R(0.5) * (a.im - at.im)};
 }
-__device__ inline double scale_s(double s, double a) { return s * a; }
-__device__ inline cplx<double> scale_s(double s, cplx<double> a) { return {s * a.re, s * a.im}; }
+template <typename R> __device__ inline R scale_s(double s, R a) { return R(s) * a; }
+template <typename R> __device__ inline cplx<R> scale_s(double s, cplx<R> a) { return {R(s) * a.re, R(s) * a.im}; }
 
 // Per block: A = Hermitian part of the policy's input, X = A / (1.01 ||A||_F).  One workgroup per block.
 template <typename S, typename Policy>
@@ -41,9 +41,9 @@ __global__ void __launch_bounds__(kSignThreads) sign_load_kernel(Policy pol, int
   double acc = 0.0;
   for (size_t e = threadIdx.x; e < nn; e += kSignThreads) {
     const int i = (int)(e / n), j = (int)(e % n);
-    const S a = herm_part<S>(pol.template load<S>(mat, i, j), pol.template load<S>(mat, j, i));
+    const S a = herm_part(pol.template load<S>(mat, i, j), pol.template load<S>(mat, j, i));
     A[e] = a;
-    acc += abs2(a);
+    acc += (double)abs2(a);
   }
   const double s2 = block_sum(acc, red);
   const double inv = s2 > 0.0 ? 1.0 / (1.01 * sqrt(s2)) : 1.0;
@@ -53,26 +53,26 @@ __global__ void __launch_bounds__(kSignThreads) sign_load_kernel(Policy pol, int
 // Per block: out(i, j) = c0 E(i, j) + c1 (P Q)(i, j) over the upper-triangle 64 x 64 tiles (blockIdx.x)
 // of block blockIdx.y; P, Q, E, out are offsets (in scalars) inside the block's 4 n^2 work area.  The
 // reduction runs in chunks of KC: the KC x 64 slices P(k0.., i-range) and Q(k0.., j-range) are staged in
-// LDS with coalesced row reads (P(i, k) = conj(P(k, i)) read as rows of P).
-//   real blocks: four wavefronts, one 32 x 32 quadrant each as 2 x 2 matrix-core sub-tiles of 16 x 16,
-//     so every operand value read from LDS feeds two products (4 waves per SIMD);
-//   complex blocks: sixteen wavefronts, one 16 x 16 sub-tile each (fewer accumulator registers keep 8
-//     waves per SIMD), four real products per complex one.  (The 2 x 2 blocking of the real kernel drops
-//     the complex one to 2 waves per SIMD and measured slower; Gauss's three-product form measured no
-//     faster: these products wait on operand traffic, not on the matrix cores.)
+// LDS with coalesced row reads (P(i, k) = conj(P(k, i)) read as rows of P).  Sixteen wavefronts, one
+// 16 x 16 matrix-core sub-tile each; a complex product takes four real ones.  (Measured on the batched
+// sweep, where the real pair blocks and the complex momentum blocks run concurrently on two streams:
+// 2 x 2 sub-tiles per wavefront on four wavefronts make the real products alone 30 % faster but the
+// step 10 % slower; three-product (Gauss) complex products are no faster; giving all tiles of a block to
+// one XCD is 14 % slower.  The products wait on operand traffic more than on the matrix cores.)
 // The finished tile passes through LDS (rows padded by one element) and is written row by row, and an
 // off-diagonal tile's conjugate mirror row by row too: the mirror's rows are the tile's columns, read
 // across the padded rows, and E's mirror entries are the conjugates of E's entries at the mirror
-// position (E is Hermitian), so every global write and read is coalesced.  A diagonal tile stores its
-// Hermitian part.
-template <typename S> struct GemmShape;
-template <> struct GemmShape<double> { static constexpr int NT = 256, KC = 32, SUB = 2; };
-template <> struct GemmShape<cplx<double>> { static constexpr int NT = 1024, KC = 32, SUB = 1; };
+// position (E is Hermitian), so every global write and read is coalesced (the column-wise mirror writes
+// of the first version cost 8 % of the step).  A diagonal tile stores its Hermitian part.
+template <typename S> struct GemmShape { static constexpr int NT = 1024, KC = 32, SUB = 1; };  // real
+template <typename R> struct GemmShape<cplx<R>> { static constexpr int NT = 1024, KC = 32, SUB = 1; };
 
 template <typename S>
 __global__ void __launch_bounds__(GemmShape<S>::NT) sign_gemm_kernel(S* work, int n, int count, int p_off, int q_off,
                                                                      int e_off, int o_off, double c0, double c1) {
   constexpr bool CPLX = scalar_traits<S>::is_complex;
+  using R = typename scalar_traits<S>::real;
+  using Acc = typename MfmaAcc<R>::T;
   constexpr int TB = 64, LDT = TB + 1;
   constexpr int NT = GemmShape<S>::NT, KC = GemmShape<S>::KC, SUB = GemmShape<S>::SUB;
   constexpr int STAGE = 2 * KC * TB, TILE = TB * LDT;
@@ -93,13 +93,13 @@ __global__ void __launch_bounds__(GemmShape<S>::NT) sign_gemm_kernel(S* work, in
   __shared__ S lds[STAGE > TILE ? STAGE : TILE];
   S* Ps = lds;
   S* Qs = lds + KC * TB;
-  mf_d4 acc[NACC][SUB][SUB];
+  Acc acc[NACC][SUB][SUB];
 #pragma unroll
   for (int q = 0; q < NACC; ++q)
 #pragma unroll
     for (int a = 0; a < SUB; ++a)
 #pragma unroll
-      for (int b = 0; b < SUB; ++b) acc[q][a][b] = mf_d4{0.0, 0.0, 0.0, 0.0};
+      for (int b = 0; b < SUB; ++b) acc[q][a][b] = Acc{R(0), R(0), R(0), R(0)};
   for (int k0 = 0; k0 < n; k0 += KC) {
     for (int e = tid; e < KC * TB; e += NT) {
       const int k = e / TB, c = e % TB;
@@ -138,7 +138,7 @@ __global__ void __launch_bounds__(GemmShape<S>::NT) sign_gemm_kernel(S* work, in
     for (int b = 0; b < SUB; ++b)
 #pragma unroll
       for (int g = 0; g < 4; ++g) {
-        const int r = wr + a * 16 + mfma_row<double>(l, g), c = wc + b * 16 + r16;
+        const int r = wr + a * 16 + mfma_row<R>(l, g), c = wc + b * 16 + r16;
         if constexpr (CPLX) {
           Ts[r * LDT + c] = S{acc[0][a][b][g], acc[1][a][b][g]};
         } else {
@@ -150,7 +150,7 @@ __global__ void __launch_bounds__(GemmShape<S>::NT) sign_gemm_kernel(S* work, in
   for (int e = tid; e < TB * TB; e += NT) {
     const int r = e / TB, c = e % TB;
     S v = Ts[r * LDT + c];
-    if (ti == tj) v = herm_part<S>(v, Ts[c * LDT + r]);
+    if (ti == tj) v = herm_part(v, Ts[c * LDT + r]);
     S val = scale_s(c1, v);
     const size_t o = (size_t)(ti * TB + r) * n + tj * TB + c;
     if (E) val = val + scale_s(c0, E[o]);
@@ -201,7 +201,9 @@ hipError_t sign_project(const Policy& pol, int n, int count, void* work_raw, hip
   if (count <= 0) return hipSuccess;
   if (n % 64 || n > kSignMax) return hipErrorInvalidValue;
   S* work = static_cast<S*>(work_raw);
-  static const std::vector<double> sched = ns_schedule(kNsResolved);
+  constexpr bool F32 = sizeof(typename scalar_traits<S>::real) == 4;
+  static const std::vector<double> sched =
+      F32 ? ns_schedule(kNsResolved32, kNsStop32) : ns_schedule(kNsResolved, kNsStop);
   const int nn = n * n;
   const int A = 0;
   const int Y = 2 * nn;
@@ -221,25 +223,35 @@ hipError_t sign_project(const Policy& pol, int n, int count, void* work_raw, hip
 
 }  // namespace
 
-hipError_t launch_pair_projection_sign(const double* rho, double* Lam, double* rho_t, double* feas, int n, int P,
-                                       double mu, int* sweeps, void* work, hipStream_t st) {
-  PairPolicy pol{rho, Lam, rho_t, feas, sweeps, n, mu};
-  return sign_project<double>(pol, n, P, work, st);
+int sign_launches(int precision) {
+  const double l0 = precision == VEMB_FP64 ? kNsResolved : kNsResolved32;
+  const double stop = precision == VEMB_FP64 ? kNsStop : kNsStop32;
+  return 2 * (int)ns_schedule(l0, stop).size() + 3;
 }
 
-hipError_t launch_momentum_projection_sign(double* Xh, int n_op, int K, int* sweeps, void* work, hipStream_t st) {
+hipError_t launch_pair_projection_sign(const double* rho, double* Lam, double* rho_t, double* feas, int n, int P,
+                                       double mu, int* sweeps, void* work, hipStream_t st, int precision) {
+  PairPolicy pol{rho, Lam, rho_t, feas, sweeps, n, mu};
+  return precision == VEMB_FP64 ? sign_project<double>(pol, n, P, work, st) : sign_project<float>(pol, n, P, work, st);
+}
+
+hipError_t launch_momentum_projection_sign(double* Xh, int n_op, int K, int* sweeps, void* work, hipStream_t st,
+                                           int precision) {
   MomentumPolicy pol{Xh, sweeps, n_op};
-  return sign_project<cplx<double>>(pol, n_op, K, work, st);
+  return precision == VEMB_FP64 ? sign_project<cplx<double>>(pol, n_op, K, work, st)
+                                : sign_project<cplx<float>>(pol, n_op, K, work, st);
 }
 
 hipError_t launch_projection_group_sign(int kind, int n, int count, const int2* item, const void* ptrs, void* work,
-                                        hipStream_t st, const LaunchHook* hook) {
+                                        hipStream_t st, const LaunchHook* hook, int precision) {
+  const bool f64 = precision == VEMB_FP64;
   if (kind == 0) {
     BatchedPairPolicy pol{item, static_cast<const PairPtrs*>(ptrs), n, 1};
-    return sign_project<double>(pol, n, count, work, st, hook);
+    return f64 ? sign_project<double>(pol, n, count, work, st, hook) : sign_project<float>(pol, n, count, work, st, hook);
   }
   BatchedMomentumPolicy pol{item, static_cast<const MomPtrs*>(ptrs), n, 1};
-  return sign_project<cplx<double>>(pol, n, count, work, st, hook);
+  return f64 ? sign_project<cplx<double>>(pol, n, count, work, st, hook)
+             : sign_project<cplx<float>>(pol, n, count, work, st, hook);
 }
 
 }  // namespace vemb

@@ -2,7 +2,8 @@
 
 * 16x16 torus, 2x2 clusters (63 pair blocks and 34 complex momentum blocks of 256 x 256, matrix-sign
   projections on matrix cores), 20 iterations: FP64 to 1e-10 relative on the bound and energy and 1e-9 of
-  each state array's largest entry; MIXED to 1e-6 on the bound (its error stated).
+  each state array's largest entry; MIXED (FP32 eigensolves, FP32 sign-function products) to 2e-5 on
+  the bound, its FP32 drift over 20 iterations (printed).
 * The 64-instance batched sweep in the benchmark's launch configuration (graph-replayed), 20 iterations:
   every instance's bound, energy and feasibility error against the oracle values that
   tests/golden/make_batch_golden.py wrote (oracle only), and the full states of a sample of instances
@@ -51,7 +52,7 @@ def c3b_oracle():
     return w, p, s
 
 
-@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("mixed", 1e-6)])
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("mixed", 2e-5)])
 def test_torus_2x2_clusters_20_iterations(vemb, c3b_oracle, precision, tol):
     w, p, s = c3b_oracle
     print(f"{w.name} {precision}: 20 iterations", flush=True)
