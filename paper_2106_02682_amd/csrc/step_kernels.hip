@@ -64,45 +64,61 @@ __device__ double rhs_value(const StepArgs& A, int pd, int i, int j) {
 // ---------------------------------------------------------------------------
 // Steps 1-2 and X'_0d.  One workgroup per offset d.
 // ---------------------------------------------------------------------------
-// Pair blocks up to this size stage R in LDS: it is formed once (coalesced reads of every input)
-// and the partial traces and the update read it from there; larger blocks form each entry of R
-// where it is needed.
+// R is formed block by block: block (x, x') is the m x m submatrix of rows x m + y and columns
+// x' m + y' (y, y' < m).  Thread t owns the entry (y, y') = ((t mod m^2) / m, t mod m) of every block
+// it visits (the thread count is a multiple of m^2), so
+//   * the pair corrections of eq. effHam read rows x' m + x and x m + x' of X_0d whole within a
+//     wavefront (entries y m + y' and y' m + y), and the blocks of rho~, Lambda, H_0d as row segments;
+//   * Tr_1 R (the sum of the diagonal blocks) accumulates in the thread's registers, and Tr_2 R (the
+//     traces of the blocks) from the diagonal entries, without strided gathers.
+// Blocks up to kStageN keep R in LDS; larger ones store R in the rho buffer of the pair between the two
+// passes (a coalesced write and read of n^2 words) and overwrite it with rho.
 constexpr int kStageN = 64;
 // Threads of a pair-update workgroup: four entries of a 64 x 64 block per thread keep enough loads
 // in flight (the step is bound by memory latency, one workgroup per pair).
 constexpr int kPairThreads = 1024;
+static_assert(kPairThreads % (kMaxM * kMaxM) == 0, "a thread keeps one (y, y') entry of every block");
 
 __device__ void pair_update_body(const StepArgs& A, int bx) {
   constexpr int NT = kPairThreads;
   const int pd = bx;  // offset d = pd + 1
-  const int m = A.m, n = A.n, mm = m * m;
+  const int m = A.m, n = A.n, mm = m * m, nn = n * n;
   const int tid = threadIdx.x;
   __shared__ double T2[kMaxM * kMaxM];  // Tr_2 R
   __shared__ double T1[kMaxM * kMaxM];  // Tr_1 R
-  __shared__ double Rs[kStageN * kStageN];
+  __shared__ double Rs[kStageN * kStageN];  // R (staged blocks) or the blocks' diagonals (larger ones)
   __shared__ double red[NT];
   __shared__ double trR_s;
   const bool staged = n <= kStageN;
-  if (staged) {
-    for (int idx = tid; idx < n * n; idx += NT) Rs[idx] = rhs_value(A, pd, idx / n, idx % n);
-    __syncthreads();
-  }
-  auto R = [&](int i, int j) { return staged ? Rs[i * n + j] : rhs_value(A, pd, i, j); };
-
-  // partial traces of R: Tr_2 R(x,x') = sum_y R(xy, x'y); Tr_1 R(y,y') = sum_x R(xy, xy')
-  for (int e = tid; e < 2 * mm; e += NT) {
-    const int which = e / mm, u = (e % mm) / m, w = e % m;
-    double acc = 0.0;
-    for (int k = 0; k < m; ++k) {
-      if (which == 0)
-        acc += R(u * m + k, w * m + k);
-      else
-        acc += R(k * m + u, k * m + w);
-    }
-    if (which == 0)
-      T2[u * m + w] = acc;
+  double* rho = A.rho + (size_t)pd * nn;
+  // pass 1: every entry of R, block by block; Tr_1 R in registers, the blocks' diagonals in LDS
+  // (forming several entries per step with all their loads first measured slower: the extra registers
+  // cost the second workgroup per CU)
+  const int r = tid % mm, y = r / m, yp = r % m;
+  double t1 = 0.0;
+  for (int e = tid; e < nn; e += NT) {
+    const int blk = e / mm, x = blk / m, xp = blk % m;
+    const int i = x * m + y, j = xp * m + yp;
+    const double v = rhs_value(A, pd, i, j);
+    if (staged)
+      Rs[i * n + j] = v;
     else
-      T1[u * m + w] = acc;
+      rho[(size_t)i * n + j] = v;  // R, overwritten by rho in pass 2
+    if (x == xp) t1 += v;
+    if (y == yp && !staged) Rs[blk * m + y] = v;  // m^2 blocks x m diagonal entries <= kStageN^2 words
+  }
+  red[tid] = t1;
+  __syncthreads();
+  for (int e = tid; e < mm; e += NT) {
+    double acc = 0.0;
+    for (int q = e; q < NT; q += mm) acc += red[q];  // the threads that own entry e of the blocks
+    T1[e] = acc;
+  }
+  for (int e = tid; e < mm; e += NT) {  // Tr_2 R (x, x') = the trace of block (x, x')
+    const int x = e / m, xp = e % m;
+    double acc = 0.0;
+    for (int k = 0; k < m; ++k) acc += staged ? Rs[(x * m + k) * n + xp * m + k] : Rs[e * m + k];
+    T2[e] = acc;
   }
   __syncthreads();
   if (tid == 0) {
@@ -110,24 +126,26 @@ __device__ void pair_update_body(const StepArgs& A, int bx) {
     for (int u = 0; u < m; ++u) t += T2[u * m + u];
     trR_s = t;
   }
+  __threadfence_block();  // R stored in rho (larger blocks) is read back by other threads below
   __syncthreads();
   const double trR = trR_s;
   const double a = A.a, bm = A.b / m, cm2 = A.c / ((double)m * m) * trR;
 
-  // rho = a R + (b/m)(Tr_2 R x I + I x Tr_1 R) + (c/m^2) Tr R I, and Tr(H_0d rho)
+  // pass 2, row-major: rho = a R + (b/m)(Tr_2 R x I + I x Tr_1 R) + (c/m^2) Tr R I, and Tr(H_0d rho)
+  // (H_0d is symmetric: the real case)
   const int h = A.hd_index[pd];
   double epart = 0.0;
-  for (int idx = tid; idx < n * n; idx += NT) {
+  for (int idx = tid; idx < nn; idx += NT) {
     const int i = idx / n, j = idx % n;
-    const int x = i / m, y = i % m, xp = j / m, yp = j % m;
-    double v = a * R(i, j);
+    const int x = i / m, y2 = i % m, xp = j / m, yp2 = j % m;
+    double v = a * (staged ? Rs[idx] : rho[idx]);
     double corr = 0.0;
-    if (y == yp) corr += T2[x * m + xp];
-    if (x == xp) corr += T1[y * m + yp];
+    if (y2 == yp2) corr += T2[x * m + xp];
+    if (x == xp) corr += T1[y2 * m + yp2];
     v += bm * corr;
     if (i == j) v += cm2;
-    A.rho[(size_t)pd * n * n + idx] = v;
-    if (h >= 0) epart += A.Hd[(size_t)h * n * n + (size_t)j * n + i] * v;
+    rho[idx] = v;
+    if (h >= 0) epart += A.Hd[(size_t)h * nn + idx] * v;
   }
   // A_1 rho = (a + b) Tr_2 R + ((b + c)/m) Tr R I ;  A_2 rho likewise with Tr_1 R
   const double ab = A.a + A.b, bc = (A.b + A.c) / m * trR;
@@ -136,10 +154,11 @@ __device__ void pair_update_body(const StepArgs& A, int bx) {
     A.tr2[(size_t)pd * mm + e] = ab * T2[e] + (u == w ? bc : 0.0);
     A.tr1[(size_t)pd * mm + e] = ab * T1[e] + (u == w ? bc : 0.0);
   }
+  __syncthreads();  // red is reused for the energy
   red[tid] = epart;
   __syncthreads();
-  for (int s = NT / 2; s > 0; s >>= 1) {
-    if (tid < s) red[tid] += red[tid + s];
+  for (int s2 = NT / 2; s2 > 0; s2 >>= 1) {
+    if (tid < s2) red[tid] += red[tid + s2];
     __syncthreads();
   }
   if (tid == 0) A.e_pair[pd] = red[0];

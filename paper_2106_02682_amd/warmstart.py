@@ -5,10 +5,14 @@ state encoding and decoding, the network's forward / backward / Adam); this modu
 only sequences the calls and keeps the host-side bookkeeping (which instance is in
 which row, when each run reached the gap).
 
-Gap.  The Lagrangian bound LB_t of every iterate is a certified lower bound (X PSD).
-For an instance, LB_ref is the best bound seen over a long cold reference run and the
-warm run; the relative gap of iterate t is (LB_ref - LB_t) / |LB_ref|, and a run has
-converged when it stays at or below the tolerance from then on (every later check).
+Two convergence rules are reported.
+* SDP gap: the first check at which the primal-dual gap of the iterate, (E_p - LB) / |LB|, and the
+  equality residual (eq. feasErr) are both at or below the tolerance (E_p the energy of the iterate's
+  marginals, LB its Lagrangian bound).
+* Bound gap: the Lagrangian bound LB_t of every iterate is a certified lower bound (X PSD).  For an
+  instance, LB_ref is the best bound seen over a long cold reference run and the warm run; the relative
+  gap of iterate t is (LB_ref - LB_t) / |LB_ref|, and a run has converged when it stays at or below the
+  tolerance from then on (every later check).
 """
 from __future__ import annotations
 
@@ -109,27 +113,42 @@ def predict(net, X):
 
 
 def bound_trajectory(probs, iters, every, warm_vecs=None, near=None, log=None, tag=""):
-    """Step a batch of problems `iters` iterations, reading the bounds every `every`.
-    Returns (its, lbs[len(its), count], secs[len(its)]) with wall-clock seconds since the
-    start (the start includes decoding the warm vectors, if given)."""
+    """Step a batch of problems `iters` iterations, reading the bounds, energies and feasibility errors
+    every `every`.  Returns (its, lbs[len(its), count], secs[len(its)], es, fs) with wall-clock seconds
+    since the start (the start includes decoding the warm vectors, if given; the energies are read after
+    each time stamp)."""
     torch = _torch()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     if warm_vecs is not None:
         for p, v in zip(probs, warm_vecs):
             vemb.warm_start(p.h, v, near)
-    its, lbs, secs = [], [], []
+    its, lbs, secs, es, fs = [], [], [], [], []
     with vemb.Batch(probs) as b:
         done = 0
         while done < iters:
             b.step(every)
             done += every
             lbs.append(b.dual_bounds())
-            its.append(done)
             secs.append(time.perf_counter() - t0)
+            e, f = b.primal_energies()
+            es.append(e)
+            fs.append(f)
+            its.append(done)
             if log and done % 2000 == 0:
                 log(f"{tag}: {done}/{iters} iterations")
-    return np.array(its), np.array(lbs), np.array(secs)
+    return np.array(its), np.array(lbs), np.array(secs), np.array(es), np.array(fs)
+
+
+def first_sdp_gap(its, lbs, es, fs, secs, tol):
+    """Per instance: (iterations, seconds) of the first check with (E_p - LB) / |LB| <= tol and
+    feasErr <= tol, or (None, None)."""
+    gap = np.abs(es - lbs) / np.abs(lbs)
+    out = []
+    for j in range(lbs.shape[1]):
+        ok = np.nonzero((gap[:, j] <= tol) & (fs[:, j] <= tol))[0]
+        out.append((int(its[ok[0]]), float(secs[ok[0]])) if len(ok) else (None, None))
+    return out
 
 
 def first_converged(its, lbs, secs, lb_ref, tol):
@@ -153,7 +172,7 @@ def compare(draws, net, near, iters, ref_iters, every=20, tol=1e-6, log=None):
     torch = _torch()
     probs = open_problems(draws)
     try:
-        c_its, c_lbs, c_secs = bound_trajectory(probs, ref_iters, every, log=log, tag="cold")
+        c_its, c_lbs, c_secs, c_es, c_fs = bound_trajectory(probs, ref_iters, every, log=log, tag="cold")
     finally:
         for p in probs:
             p.close()
@@ -165,8 +184,9 @@ def compare(draws, net, near, iters, ref_iters, every=20, tol=1e-6, log=None):
         V = predict(net, Xh)
         torch.cuda.synchronize()
         t_pred = time.perf_counter() - t0
-        w_its, w_lbs, w_secs = bound_trajectory(probs, iters, every, warm_vecs=[V[i] for i in range(len(probs))],
-                                                near=near, log=log, tag="warm")
+        w_its, w_lbs, w_secs, w_es, w_fs = bound_trajectory(probs, iters, every,
+                                                            warm_vecs=[V[i] for i in range(len(probs))], near=near,
+                                                            log=log, tag="warm")
         w_secs = w_secs + t_pred
     finally:
         for p in probs:
@@ -180,6 +200,7 @@ def compare(draws, net, near, iters, ref_iters, every=20, tol=1e-6, log=None):
         "lb_ref": lb_ref, "cold": cold, "warm": warm, "predict_seconds": t_pred,
         "first_gap_cold": c0, "first_gap_warm": w0,
         "cold_traj": (c_its, c_lbs, c_secs), "warm_traj": (w_its, w_lbs, w_secs),
+        "cold_primal": (c_es, c_fs), "warm_primal": (w_es, w_fs),
     }
 
 
@@ -197,8 +218,24 @@ def gap_report(res, tol, horizon):
         v = float(np.median([p[k] if p[k] is not None else math.inf for p in pairs]))
         return v if math.isfinite(v) else None
 
+    def sdp(traj, primal, limit):
+        its, lbs, secs = traj
+        es, fs = primal
+        k = its <= limit
+        return first_sdp_gap(its[k], lbs[k], es[k], fs[k], secs[k], tol)
+
+    sdp_cold = sdp(res["cold_traj"], res["cold_primal"], c_its[-1])  # the whole cold reference run
+    sdp_warm = sdp(res["warm_traj"], res["warm_primal"], horizon)
     return {
         "tol": tol, "horizon_iters": horizon,
+        "sdp_gap": {"rule": "first check with (E_p - LB)/|LB| <= tol and feasErr <= tol",
+                    "cold_horizon_iters": int(c_its[-1]), "warm_horizon_iters": horizon,
+                    "cold_reached": sum(p[0] is not None for p in sdp_cold),
+                    "warm_reached": sum(p[0] is not None for p in sdp_warm),
+                    "median_iters_cold": med(sdp_cold, 0), "median_iters_warm": med(sdp_warm, 0),
+                    "median_seconds_cold": med(sdp_cold, 1), "median_seconds_warm": med(sdp_warm, 1),
+                    "iters_cold": [p[0] for p in sdp_cold], "iters_warm": [p[0] for p in sdp_warm]},
+        "bound_gap_rule": "the gap (LB_ref - LB_t)/|LB_ref| stays <= tol from this check on",
         "cold_reached": sum(p[0] is not None for p in cold), "warm_reached": sum(p[0] is not None for p in warm),
         "median_iters_cold": med(cold, 0), "median_iters_warm": med(warm, 0),
         "median_seconds_cold": med(cold, 1), "median_seconds_warm": med(warm, 1),
