@@ -45,6 +45,8 @@ KERNEL_SOURCES = {
     "momentum_projection": ("jacobi.hip", "jacobi_common.h"), "pair_jacobi": ("jacobi.hip", "jacobi_common.h"),
     "momentum_jacobi": ("jacobi.hip", "jacobi_common.h"),
     "sign_gemm_real": ("sign_batched.hip", "mfma_tile.h"), "sign_gemm_complex": ("sign_batched.hip", "mfma_tile.h"),
+    "sign_load_real": ("sign_batched.hip",), "sign_load_complex": ("sign_batched.hip",),
+    "sign_store_real": ("sign_batched.hip",), "sign_store_complex": ("sign_batched.hip",),
     "pair_update": ("step_kernels.hip",), "pair_xstep": ("step_kernels.hip",), "cluster_update": ("step_kernels.hip",),
     "dft_forward": ("step_kernels.hip", "mfma_tile.h"), "dft_inverse": ("step_kernels.hip", "mfma_tile.h"),
 }
@@ -435,8 +437,8 @@ def precision_leg(args):
 
 def profile_leg(args):
     """A fixed run for rocprofv3 (kernel traces and counters): the workload's steps after a warm-up, then one
-    plain device copy of 256 MiB (torch's elementwise copy) whose FETCH_SIZE / WRITE_SIZE readings calibrate
-    the byte counters."""
+    plain device-to-device copy of 256 MiB (the HIP runtime's copy kernel) whose FETCH_SIZE / WRITE_SIZE
+    readings calibrate the byte counters."""
     import torch
 
     import synth
@@ -477,12 +479,14 @@ COPY_BYTES = 256 << 20
 TRAFFIC_KERNELS = [
     ("momentum_projection", r"jacobi_kernel<vemb::cplx<double>, 64, 0, true, \d+, vemb::\(anonymous namespace\)::MomentumPolicy"),
     ("pair_projection", r"jacobi_kernel<double, 64, 0, true, \d+, vemb::\(anonymous namespace\)::PairPolicy"),
-    ("projections", r"fused_projection_kernel<\d+>"),
+    ("projections", r"fused_projection_kernel<\d+, double>"),
     ("pair_update", r"pair_update_(kernel|batched)"), ("pair_xstep", r"pair_xstep_(kernel|batched)"),
     ("cluster_update", r"cluster_update_(kernel|batched)"),
     ("dft_forward", r"dft_mfma_kernel<true>|dft_forward_batched"),
     ("dft_inverse", r"dft_mfma_kernel<false>|dft_inverse_batched"),
     ("sign_gemm_real", r"sign_gemm_kernel<double>"), ("sign_gemm_complex", r"sign_gemm_kernel<vemb::cplx<double> >"),
+    ("sign_load_real", r"sign_load_kernel<double,"), ("sign_load_complex", r"sign_load_kernel<vemb::cplx<double>,"),
+    ("sign_store_real", r"sign_store_kernel<double,"), ("sign_store_complex", r"sign_store_kernel<vemb::cplx<double>,"),
     ("pair_jacobi", r"jacobi_kernel<double, \d+, 0, true, \d+, vemb::\(anonymous namespace\)::BatchedPairPolicy"),
     ("momentum_jacobi", r"jacobi_kernel<vemb::cplx<double>, \d+, 0, true, \d+, vemb::\(anonymous namespace\)::BatchedMomentumPolicy"),
 ]
@@ -504,7 +508,9 @@ def summarize_traffic(workload, precision, fetch_dir, write_dir):
         raise FileNotFoundError(f"no counter_collection.csv under {d}")
 
     def calib(rs):
-        copies = [r for r in rs if "copyBuffer" in r["Kernel_Name"] or "elementwise" in r["Kernel_Name"]]
+        # the HIP runtime's device-to-device copy kernel of the 256 MiB copy: the largest grid of that name
+        # (torch's fill of the source, an elementwise kernel, reads nothing and is not a calibration)
+        copies = [r for r in rs if "copyBuffer" in r["Kernel_Name"]]
         return float(max(copies, key=lambda r: int(r["Grid_Size"]))["Counter_Value"])
 
     def mean(rs, pat):
@@ -618,6 +624,66 @@ def tune_leg(args):
             "config": {"workload": "parameter race on a ring family"}, "tuning": out}
 
 
+def summarize_stats(stats_dir, title, command, out_name):
+    """profiles/<out_name>.md from the kernel statistics CSV of a `rocprofv3 --kernel-trace --stats` run:
+    calls, average / min / max microseconds and share of every kernel (the top 25 by total time)."""
+    import csv
+
+    path = None
+    for root, _, files in os.walk(stats_dir):
+        for f in files:
+            if f.endswith("kernel_stats.csv"):
+                path = os.path.join(root, f)
+    if path is None:
+        raise FileNotFoundError(f"no kernel_stats.csv under {stats_dir}")
+    with open(path) as fh:
+        rows = list(csv.DictReader(fh))
+    rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    lines = [f"# rocprofv3 kernel statistics: {title}", "", f"Command: `{command}`", "",
+             "| kernel | calls | average µs | min µs | max µs | share % |", "|---|---|---|---|---|---|"]
+    for r in rows[:25]:
+        name = r["Name"].replace("|", "\\|")
+        if len(name) > 150:
+            name = name[:147] + "..."
+        lines.append(f"| `{name}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | {float(r['MinNs']) / 1e3:.1f} | "
+                     f"{float(r['MaxNs']) / 1e3:.1f} | {float(r['Percentage']):.2f} |")
+    with open(os.path.join(ROOT, "profiles", f"{out_name}.md"), "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
+def summarize_counters(counter_dirs, title, commands, out_name, kernels):
+    """profiles/<out_name>.md from `rocprofv3 --pmc` runs: the average of each counter per dispatch for the
+    kernels named by the (label, regex) pairs, plus ratios the design notes use."""
+    import csv
+    import re
+
+    vals = {}
+    for d in counter_dirs:
+        for root, _, files in os.walk(d):
+            for f in files:
+                if f.endswith("counter_collection.csv"):
+                    with open(os.path.join(root, f)) as fh:
+                        for r in csv.DictReader(fh):
+                            for label, pat in kernels:
+                                if re.search(pat, r["Kernel_Name"]):
+                                    vals.setdefault((label, r["Counter_Name"]), []).append(float(r["Counter_Value"]))
+    counters = sorted({c for _, c in vals})
+    labels = [k for k, _ in kernels]
+    lines = [f"# Hardware counters per dispatch: {title}", "", "Commands (one pass each):", ""]
+    lines += [f"* `{c}`" for c in commands]
+    lines += ["", "| counter | " + " | ".join(labels) + " |", "|---|" + "---|" * len(labels)]
+    for c in counters:
+        row = []
+        for k in labels:
+            v = vals.get((k, c))
+            row.append(f"{sum(v) / len(v):.4g}" if v else "")
+        lines.append(f"| {c} | " + " | ".join(row) + " |")
+    with open(os.path.join(ROOT, "profiles", f"{out_name}.md"), "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -632,6 +698,8 @@ def main():
                          "fixed run for rocprofv3")
     ap.add_argument("--profile-workload", choices=["c4", "c2b", "c3a", "c3b"], default="c4")
     ap.add_argument("--summarize-traffic", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
+    ap.add_argument("--summarize-stats", nargs=4, metavar=("STATS_DIR", "TITLE", "COMMAND", "OUT_NAME"),
+                    help="write profiles/OUT_NAME.md from a rocprofv3 --stats run")
     ap.add_argument("--lb-every", type=int, default=10)
     ap.add_argument("--prof-every", type=int, default=5, help="time the kernels of every N-th step")
     ap.add_argument("--cpu-seconds", type=float, default=10.0, help="single-core oracle sample length (0 disables "
@@ -653,6 +721,9 @@ def main():
         sys.exit(2)
     if args.summarize_traffic:
         summarize_traffic(args.profile_workload, args.precision, *args.summarize_traffic)
+        return
+    if args.summarize_stats:
+        summarize_stats(*args.summarize_stats)
         return
 
     import synth

@@ -420,6 +420,8 @@ int vemb_create_problem(const vemb_hamiltonian* H, const vemb_lattice* lat, cons
       (n > 64 && ((rc = dalloc(p, (double**)&a.wscr_pair, (size_t)P * n * n)) ||
                   (rc = dalloc(p, (double**)&a.tscr_pair, (size_t)P * n * n)))) ||
       (n > 64 && (rc = dalloc(p, (char**)&p->sign_pair, sign_work_bytes(n, P, false)))) ||
+      (n > 128 && ((rc = dalloc(p, &p->slice_x, (size_t)P * n)) || (rc = dalloc(p, &p->slice_sigma, (size_t)P)) ||
+                   (rc = dalloc(p, &p->slice_flags, (size_t)P)) || (rc = dalloc(p, &p->slice_nflag, 1)))) ||
       (k > 64 && (rc = dalloc(p, (char**)&p->sign_mom, sign_work_bytes(k, Ku, true)))) ||
       (k > 64 && ((rc = dalloc(p, (double**)&a.wscr_mom, (size_t)2 * Ku * k * k)) ||
                   (rc = dalloc(p, (double**)&a.tscr_mom, (size_t)2 * Ku * k * k)))))
@@ -434,7 +436,8 @@ int vemb_create_problem(const vemb_hamiltonian* H, const vemb_lattice* lat, cons
       (rc = hip_rc(hipMemsetAsync(a.sweeps, 0, sizeof(int) * (2 * P + Ku + 1), s), "zero sweeps")) ||
       (rc = hip_rc(hipMemsetAsync(a.e_pair, 0, sizeof(double) * P, s), "zero e_pair")) ||
       (rc = hip_rc(hipMemsetAsync(a.feas, 0, sizeof(double) * P, s), "zero feas")) ||
-      (rc = hip_rc(hipMemsetAsync(a.scal, 0, sizeof(double) * 4, s), "zero scal")))
+      (rc = hip_rc(hipMemsetAsync(a.scal, 0, sizeof(double) * 4, s), "zero scal")) ||
+      (p->slice_x && (rc = hip_rc(hipMemsetAsync(p->slice_x, 0, sizeof(double) * P * n, s), "zero slice vectors"))))
     return cleanup(rc);
   a.H0 = p->H0;
   a.Hd = p->Hd;
@@ -646,9 +649,18 @@ int enqueue_bound(vemb_problem* p) {
   const int P = p->P, n = a.n, m = a.m;
   VEMB_TRY(timed(p, VEMB_K_BOUND_BUILD, "bound build", [&] { return launch_bound_build(a, s); }));
   VEMB_TRY(timed(p, VEMB_K_LMIN, "pair lambda_min", [&] {
-    if (n > 128)
-      return launch_eigvals_big(a.Kbuf, nullptr, a.lmin, n, P, false, p->opt.max_sweeps, a.sweeps + P + a.Ku,
-                                a.wscr_pair, a.tscr_pair, s);
+    if (n > 128) {
+      // spectral slicing, in FP64 in every precision mode (an FP32 sign function leaves ~1e-5 of other
+      // eigenvectors in the Ritz space, ~1e-9 in the value); the first evaluation (no Ritz vectors yet)
+      // takes two passes up front
+      const int passes = p->slice_started ? 1 : 2;
+      p->slice_started = true;
+      hipError_t e = hipSuccess;
+      for (int k = 0; k < passes && e == hipSuccess; ++k)
+        e = launch_lambda_min_slice(a.Kbuf, p->slice_x, p->slice_sigma, a.lmin, p->slice_flags, p->slice_nflag, n, P,
+                                    p->sign_pair, s, VEMB_FP64);
+      return e;
+    }
     const int cold = (!p->k_valid || p->k_uses % 16 == 0) ? 1 : 0;
     return launch_lambda_min(a.Kbuf, a.lmin, n, P, p->opt.max_sweeps, a.sweeps + P + a.Ku, s, p->tpb_pair, p->Kv,
                              cold);
@@ -660,6 +672,38 @@ int enqueue_bound(vemb_problem* p) {
   return timed(p, VEMB_K_LMIN, "cluster lambda_min", [&] {
     return launch_lambda_min(a.Kbuf + (size_t)P * n * n, a.lmin + P, m, 1, p->opt.max_sweeps, nullptr, s);
   });
+}
+
+constexpr int kSlicePasses = 4;
+
+// After a synchronised bound evaluation with matrices above 128: blocks whose slicing pass was flagged
+// (more eigenvalues below the shift than the Ritz space can hold) get further passes, each starting from
+// its latest Ritz vector, then the streamed Jacobi solve if any is still flagged; lm (host, P values) is
+// refreshed when anything ran.  Later work already queued on the stream runs first (the bound buffers are
+// only rewritten by the next evaluation).
+int slice_fixup(vemb_problem* p, double* lm) {
+  const StepArgs& a = p->a;
+  if (a.n <= 128) return VEMB_OK;
+  hipStream_t s = p->stream;
+  int nf = 0;
+  auto read_flags = [&] {
+    VEMB_TRY(hip_rc(hipMemcpyAsync(&nf, p->slice_nflag, sizeof(int), hipMemcpyDeviceToHost, s), "copy slice flags"));
+    return hip_rc(hipStreamSynchronize(s), "slice flags sync");
+  };
+  VEMB_TRY(read_flags());
+  if (!nf) return VEMB_OK;
+  for (int pass = 1; pass < kSlicePasses && nf; ++pass) {
+    VEMB_TRY(hip_rc(launch_lambda_min_slice(a.Kbuf, p->slice_x, p->slice_sigma, a.lmin, p->slice_flags,
+                                            p->slice_nflag, a.n, p->P, p->sign_pair, s, VEMB_FP64),
+                    "slicing pass"));
+    VEMB_TRY(read_flags());
+  }
+  if (nf)
+    VEMB_TRY(hip_rc(launch_eigvals_big(a.Kbuf, nullptr, a.lmin, a.n, p->P, false, p->opt.max_sweeps,
+                                       a.sweeps + p->P + a.Ku, a.wscr_pair, a.tscr_pair, s),
+                    "pair lambda_min (streamed)"));
+  VEMB_TRY(hip_rc(hipMemcpyAsync(lm, a.lmin, (size_t)p->P * 8, hipMemcpyDeviceToHost, s), "copy lambda_min"));
+  return hip_rc(hipStreamSynchronize(s), "lambda_min sync");
 }
 
 double bound_from(const vemb_problem* p, const std::vector<double>& lm) {
@@ -677,6 +721,7 @@ int vemb_dual_bound(vemb_problem* p, double* lb) {
   VEMB_TRY(hip_rc(hipMemcpyAsync(lm.data(), p->a.lmin, (p->P + 1) * 8, hipMemcpyDeviceToHost, p->stream),
                   "copy lambda_min"));
   VEMB_TRY(hip_rc(hipStreamSynchronize(p->stream), "dual bound sync"));
+  VEMB_TRY(slice_fixup(p, lm.data()));
   VEMB_TRY(drain_marks(p));  // the stream is idle: recycle the timing events now
   *lb = bound_from(p, lm);
   if (!std::isfinite(*lb)) return fail(VEMB_E_NUMERIC, "non-finite lower bound");
@@ -694,6 +739,7 @@ int vemb_diagnostics(vemb_problem* p, double* lb, double* e_per_site, double* fe
   VEMB_TRY(enqueue_bound(p));
   VEMB_TRY(hip_rc(hipMemcpyAsync(lm.data(), p->a.lmin, (P + 1) * 8, hipMemcpyDeviceToHost, s), "copy lambda_min"));
   VEMB_TRY(hip_rc(hipStreamSynchronize(s), "diagnostics sync"));
+  VEMB_TRY(slice_fixup(p, lm.data()));
   VEMB_TRY(drain_marks(p));  // the stream is idle: recycle the timing events now
   *lb = bound_from(p, lm);
   double e = sc[0], f = sc[1];
@@ -754,6 +800,7 @@ int diag_collect(vemb_problem* p, double* lb, double* e_per_site, double* feas_e
   VEMB_TRY(hip_rc(hipEventSynchronize(p->diag_ev), "diagnostics wait"));
   p->diag_pending = false;
   const int P = p->P;
+  VEMB_TRY(slice_fixup(p, p->diag_host));
   const double* h = p->diag_host;
   return diag_reduce(p, h, h + P + 1, h + 2 * P + 1, h + 3 * P + 1, lb, e_per_site, feas_err);
 }

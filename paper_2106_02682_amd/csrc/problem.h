@@ -51,6 +51,13 @@ struct vemb_problem {
   // FP64 blocks above 64 (4-site clusters): scratch of the sign-function projections (else null)
   void* sign_pair = nullptr;
   void* sign_mom = nullptr;
+  // Bound matrices above 128 (spectral slicing): last Ritz vectors (P x n, zero before the first
+  // evaluation), shifts, per-block flags and their count
+  double* slice_x = nullptr;
+  double* slice_sigma = nullptr;
+  int* slice_flags = nullptr;
+  int* slice_nflag = nullptr;
+  bool slice_started = false;
   int64_t prof_n[VEMB_K_COUNT] = {};
 };
 

@@ -32,6 +32,18 @@ struct LaunchHook {
 hipError_t launch_projection_group_sign(int kind, int n, int count, const int2* item, const void* ptrs, void* work,
                                         hipStream_t st, const LaunchHook* hook = nullptr, int precision = VEMB_FP64);
 
+// Smallest eigenvalue of `count` symmetric n x n matrices K (row-major, contiguous; n a multiple of 64,
+// at most kSignMax) by one pass of spectral slicing: sigma_d from x_d (the Rayleigh quotient of the last
+// Ritz vector, or the smallest diagonal entry where x_d = 0), sign(sigma_d I - K_d) by the sign-function
+// products in `precision` in `work` (sign_work_bytes(n, count, false)), then the FP64 Rayleigh-Ritz value
+// of K_d on x_d and kSliceCols - 1 projected columns into lmin[d] and its Ritz vector into x_d.
+// flags[d] = 1 where more than kSliceCols - 2 eigenvalues lay below sigma_d (or no column survived): the
+// value is then only an upper estimate and another pass (starting from the new x_d) is needed; *nflag
+// counts the flagged blocks.  x: count x n, sigma: count, all device memory.
+constexpr int kSliceCols = 16;
+hipError_t launch_lambda_min_slice(const double* K, double* x, double* sigma, double* lmin, int* flags, int* nflag,
+                                   int n, int count, void* work, hipStream_t st, int precision);
+
 // Kernel launches of one sign-function projection (load, the products, store) in a precision.
 int sign_launches(int precision);
 

@@ -31,23 +31,61 @@ template <typename R> __device__ inline R scale_s(double s, R a) { return R(s) *
 template <typename R> __device__ inline cplx<R> scale_s(double s, cplx<R> a) { return {R(s) * a.re, R(s) * a.im}; }
 
 // Per block: A = Hermitian part of the policy's input, X = A / (1.01 ||A||_F).  One workgroup per block.
+// The input is read as pairs of 32 x 32 tiles, (i-range, j-range) and its transpose position, each with
+// row-wise (coalesced) reads staged in LDS, so the transposed entry that the Hermitian part needs costs
+// no cache line of its own (entry-wise column reads fetched 17x the block's bytes from HBM); A's tile and
+// its conjugate mirror are written row by row.  The scaling pass visits the entries in the same
+// thread-to-entry order, so each thread reads back only its own stores.
 template <typename S, typename Policy>
 __global__ void __launch_bounds__(kSignThreads) sign_load_kernel(Policy pol, int n, S* work) {
-  const int mat = blockIdx.x;
+  constexpr int TB = 32, LDT = TB + 1, TT = TB * TB;
+  const int mat = blockIdx.x, tid = threadIdx.x;
   const size_t nn = (size_t)n * n;
   S* A = work + (size_t)mat * 4 * nn;
   S* X = A + nn;
+  __shared__ S t1[TB * LDT], t2[TB * LDT];
   __shared__ double red[kSignThreads];
+  const int tiles = n / TB, pairs = upper_tile_count(tiles);
   double acc = 0.0;
-  for (size_t e = threadIdx.x; e < nn; e += kSignThreads) {
-    const int i = (int)(e / n), j = (int)(e % n);
-    const S a = herm_part(pol.template load<S>(mat, i, j), pol.template load<S>(mat, j, i));
-    A[e] = a;
-    acc += (double)abs2(a);
+  for (int idx = 0; idx < pairs; ++idx) {
+    int ti = 0, tj = 0;
+    upper_tile(idx, tiles, &ti, &tj);
+    const int i0 = ti * TB, j0 = tj * TB;
+    for (int e = tid; e < TT; e += kSignThreads) {
+      const int r = e / TB, c = e % TB;
+      t1[r * LDT + c] = pol.template load<S>(mat, i0 + r, j0 + c);
+      t2[r * LDT + c] = pol.template load<S>(mat, j0 + r, i0 + c);
+    }
+    __syncthreads();
+    for (int e = tid; e < TT; e += kSignThreads) {
+      const int r = e / TB, c = e % TB;
+      const S a = herm_part(t1[r * LDT + c], t2[c * LDT + r]);  // from M(i0+r, j0+c) and M(j0+c, i0+r)
+      A[(size_t)(i0 + r) * n + j0 + c] = a;
+      acc += (double)abs2(a);
+      if (ti != tj) {
+        const S b = herm_part(t2[r * LDT + c], t1[c * LDT + r]);  // A(j0+r, i0+c), the mirror's row r
+        A[(size_t)(j0 + r) * n + i0 + c] = b;
+        acc += (double)abs2(b);
+      }
+    }
+    __syncthreads();
   }
   const double s2 = block_sum(acc, red);
   const double inv = s2 > 0.0 ? 1.0 / (1.01 * sqrt(s2)) : 1.0;
-  for (size_t e = threadIdx.x; e < nn; e += kSignThreads) X[e] = scale_s(inv, A[e]);
+  for (int idx = 0; idx < pairs; ++idx) {
+    int ti = 0, tj = 0;
+    upper_tile(idx, tiles, &ti, &tj);
+    const int i0 = ti * TB, j0 = tj * TB;
+    for (int e = tid; e < TT; e += kSignThreads) {
+      const int r = e / TB, c = e % TB;
+      const size_t o = (size_t)(i0 + r) * n + j0 + c;
+      X[o] = scale_s(inv, A[o]);
+      if (ti != tj) {
+        const size_t m = (size_t)(j0 + r) * n + i0 + c;
+        X[m] = scale_s(inv, A[m]);
+      }
+    }
+  }
 }
 
 // Per block: out(i, j) = c0 E(i, j) + c1 (P Q)(i, j) over the upper-triangle 64 x 64 tiles (blockIdx.x)
@@ -195,17 +233,17 @@ void gemm(S* work, int n, int count, int p, int q, int e, int o, double c0, doub
   if (hook) hook->fn(hook->ctx, 1, st);
 }
 
+// sign(A) of every block by the scaled Newton-Schulz schedule (polar.hip) after the policy's load; on
+// return *x_off is the slot (offset in scalars inside a block's 4 n^2 work area) that holds sign(A),
+// slot 0 holds A, and the slot 2 n^2 is free.
 template <typename S, typename Policy>
-hipError_t sign_project(const Policy& pol, int n, int count, void* work_raw, hipStream_t st,
-                        const LaunchHook* hook = nullptr) {
-  if (count <= 0) return hipSuccess;
+hipError_t sign_function(const Policy& pol, int n, int count, S* work, hipStream_t st, const LaunchHook* hook,
+                         int* x_off, int* steps) {
   if (n % 64 || n > kSignMax) return hipErrorInvalidValue;
-  S* work = static_cast<S*>(work_raw);
   constexpr bool F32 = sizeof(typename scalar_traits<S>::real) == 4;
   static const std::vector<double> sched =
       F32 ? ns_schedule(kNsResolved32, kNsStop32) : ns_schedule(kNsResolved, kNsStop);
   const int nn = n * n;
-  const int A = 0;
   const int Y = 2 * nn;
   int X = nn, T = 3 * nn;
   hipLaunchKernelGGL((sign_load_kernel<S, Policy>), dim3(count), dim3(kSignThreads), 0, st, pol, n, work);
@@ -214,10 +252,313 @@ hipError_t sign_project(const Policy& pol, int n, int count, void* work_raw, hip
     gemm<S>(work, n, count, X, Y, X, T, 1.5 * a, -0.5 * a * a * a, st, hook);
     std::swap(X, T);
   }
+  *x_off = X;
+  *steps = (int)sched.size();
+  return hipSuccess;
+}
+
+template <typename S, typename Policy>
+hipError_t sign_project(const Policy& pol, int n, int count, void* work_raw, hipStream_t st,
+                        const LaunchHook* hook = nullptr) {
+  if (count <= 0) return hipSuccess;
+  S* work = static_cast<S*>(work_raw);
+  int X = 0, steps = 0;
+  const hipError_t e = sign_function<S>(pol, n, count, work, st, hook, &X, &steps);
+  if (e != hipSuccess) return e;
+  const int A = 0, Y = 2 * n * n;
   // Pi(A) = (A + A S) / 2 into the slot of X^2, free after the last step
   gemm<S>(work, n, count, A, X, A, Y, 0.5, 0.5, st, hook);
-  hipLaunchKernelGGL((sign_store_kernel<S, Policy>), dim3(count), dim3(kSignThreads), 0, st, pol, n, work, Y,
-                     (int)sched.size());
+  hipLaunchKernelGGL((sign_store_kernel<S, Policy>), dim3(count), dim3(kSignThreads), 0, st, pol, n, work, Y, steps);
+  return hipGetLastError();
+}
+
+// ----- Smallest eigenvalue by spectral slicing (the bound's 256 x 256 matrices) -----
+//
+// For a shift sigma, P = (I + sign(sigma I - K)) / 2 projects onto the eigenvectors of K with eigenvalues
+// below sigma (one within the schedule's resolution of sigma enters with a weight in (0, 1)).  If sigma
+// is at least lambda_min(K) and at most kSliceCols - 2 eigenvalues lie below it, the span of x and P z_c
+// (c = 1 .. kSliceCols - 1, fixed pseudo-random +-1 columns) contains the lowest eigenvector, and the
+// smallest Rayleigh-Ritz value of K on that span, computed in FP64 from K itself, is lambda_min to
+// rounding (Ritz values are never below lambda_min, and extra directions do not move the smallest).
+// sigma is the Rayleigh quotient of x, the Ritz vector of the previous evaluation (an upper bound of
+// lambda_min), or the smallest diagonal entry on the first; a block with more eigenvalues below sigma
+// is flagged, and the next pass starts from its Ritz vector, whose Rayleigh quotient lies lower.
+
+struct ShiftPolicy {  // A = sigma_d I - K_d
+  const double* K;
+  const double* sigma;
+  int n;
+  template <typename S> __device__ S load(int mat, int i, int j) const {
+    double v = -K[(size_t)mat * n * n + (size_t)i * n + j];
+    if (i == j) v += sigma[mat];
+    return from_double<S>(v);
+  }
+};
+
+// sigma_d = x^T K x / x^T x, or, for x = 0, the smallest diagonal entry with x = its unit vector.
+__global__ void __launch_bounds__(kSignThreads) slice_shift_kernel(const double* K, double* x, double* sigma,
+                                                                   int* nflag, int n) {
+  const int mat = blockIdx.x, tid = threadIdx.x;
+  const double* Km = K + (size_t)mat * n * n;
+  double* xm = x + (size_t)mat * n;
+  __shared__ double red[kSignThreads];
+  __shared__ int ridx[kSignThreads];
+  __shared__ double xs[kSignMax];
+  if (mat == 0 && tid == 0) *nflag = 0;
+  double x2 = 0.0;
+  for (int i = tid; i < n; i += kSignThreads) {
+    xs[i] = xm[i];
+    x2 += xs[i] * xs[i];
+  }
+  const double nx = block_sum(x2, red);
+  if (nx > 0.5) {
+    double q = 0.0;
+    for (int i = tid; i < n; i += kSignThreads) {
+      double y = 0.0;
+      for (int j = 0; j < n; ++j) y += Km[(size_t)j * n + i] * xs[j];  // K symmetric: coalesced over i
+      q += xs[i] * y;
+    }
+    const double num = block_sum(q, red);
+    if (tid == 0) sigma[mat] = num / nx;
+    return;
+  }
+  double best = INFINITY;
+  int bi = n;
+  for (int i = tid; i < n; i += kSignThreads) {
+    const double v = Km[(size_t)i * n + i];
+    if (v < best) {
+      best = v;
+      bi = i;
+    }
+  }
+  red[tid] = best;
+  ridx[tid] = bi;
+  __syncthreads();
+  for (int s = kSignThreads / 2; s > 0; s >>= 1) {
+    if (tid < s) {
+      const double o = red[tid + s];
+      const int oi = ridx[tid + s];
+      if (o < red[tid] || (o == red[tid] && oi < ridx[tid])) {
+        red[tid] = o;
+        ridx[tid] = oi;
+      }
+    }
+    __syncthreads();
+  }
+  const int k = ridx[0];  // n when the diagonal holds no number: x stays 0 and sigma is not finite
+  for (int i = tid; i < n; i += kSignThreads) xm[i] = i == k ? 1.0 : 0.0;
+  if (tid == 0) sigma[mat] = red[0];
+}
+
+__device__ inline double slice_sign(int c, int i) {
+  unsigned h = (unsigned)c * 0x9E3779B9u ^ ((unsigned)i + 0x7F4A7C15u) * 0x85EBCA6Bu;
+  h ^= h >> 15;
+  h *= 0x2C1B3C6Du;
+  h ^= h >> 12;
+  h *= 0x297A2D39u;
+  h ^= h >> 15;
+  return (h & 1u) ? 1.0 : -1.0;
+}
+
+__device__ inline double wave_sum(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  return v;
+}
+
+template <typename S>
+__global__ void __launch_bounds__(kSignThreads) slice_ritz_kernel(const double* K, const S* work, int s_off,
+                                                                  double* x, double* lmin, int* flags, int* nflag,
+                                                                  int n) {
+  constexpr int R = kSliceCols, NT = kSignThreads, RH = R / 2;
+  static_assert(NT == R * R, "one thread per entry of the Ritz matrix");
+  const int mat = blockIdx.x, tid = threadIdx.x;
+  const size_t nn = (size_t)n * n;
+  const double* Km = K + (size_t)mat * nn;
+  const S* Sm = work + (size_t)mat * 4 * nn + s_off;
+  double* xm = x + (size_t)mat * n;
+  __shared__ double Z[kSignMax * R];  // start columns, then the orthonormal basis Q (row i at Z + i R)
+  __shared__ double Y[kSignMax * R];  // P Z, then K Q
+  __shared__ double T[R * R], V[R * R];
+  __shared__ double red[NT];
+  __shared__ double rc[RH], rs[RH];
+  __shared__ int rp[RH], rq[RH];
+  __shared__ unsigned kept_mask;
+  __shared__ int best_idx;
+
+  // 1. trace of sign(A) (eigenvalues of K below sigma: (n + tr) / 2) and the start columns
+  double tr = 0.0;
+  for (int i = tid; i < n; i += NT) tr += (double)Sm[(size_t)i * n + i];
+  const double rs_n = 1.0 / sqrt((double)n);
+  for (int e = tid; e < n * R; e += NT) {
+    const int i = e / R, c = e % R;
+    Z[e] = c == 0 ? xm[i] : slice_sign(c, i) * rs_n;
+  }
+  const double below = 0.5 * ((double)n + block_sum(tr, red));
+
+  // 2. Y = [x, P z_1, ..., P z_{R-1}], P = (I + S) / 2 (S symmetric: column reads coalesced over rows)
+  for (int i = tid; i < n; i += NT) {
+    double acc[R];
+#pragma unroll
+    for (int c = 0; c < R; ++c) acc[c] = Z[i * R + c];
+    for (int j = 0; j < n; ++j) {
+      const double sv = (double)Sm[(size_t)j * n + i];
+#pragma unroll
+      for (int c = 1; c < R; ++c) acc[c] += sv * Z[j * R + c];
+    }
+    Y[i * R] = acc[0];
+#pragma unroll
+    for (int c = 1; c < R; ++c) Y[i * R + c] = 0.5 * acc[c];
+  }
+  __syncthreads();
+
+  // 3. orthonormal basis by classical Gram-Schmidt applied twice, on the first wavefront (lane l holds
+  //    rows l, l + 64, ...; each lane reads back only its own rows); negligible columns are dropped
+  if (tid < 64) {
+    const int rows = n / 64;
+    unsigned mask = 0u;
+    for (int c = 0; c < R; ++c) {
+      double v[kSignMax / 64];
+      double n0 = 0.0;
+      for (int t = 0; t < rows; ++t) {
+        v[t] = Y[(tid + 64 * t) * R + c];
+        n0 += v[t] * v[t];
+      }
+      n0 = wave_sum(n0);
+      for (int pass = 0; pass < 2; ++pass)
+        for (int k = 0; k < c; ++k) {
+          if (!(mask >> k & 1u)) continue;
+          double h = 0.0;
+          for (int t = 0; t < rows; ++t) h += Z[(tid + 64 * t) * R + k] * v[t];
+          h = wave_sum(h);
+          for (int t = 0; t < rows; ++t) v[t] -= h * Z[(tid + 64 * t) * R + k];
+        }
+      double n1 = 0.0;
+      for (int t = 0; t < rows; ++t) n1 += v[t] * v[t];
+      n1 = wave_sum(n1);
+      const bool keep = n0 > 0.0 && n1 > 1e-24 * n0 && n1 < INFINITY;
+      const double inv = keep ? 1.0 / sqrt(n1) : 0.0;
+      for (int t = 0; t < rows; ++t) Z[(tid + 64 * t) * R + c] = v[t] * inv;
+      if (keep) mask |= 1u << c;
+    }
+    if (tid == 0) kept_mask = mask;
+  }
+  __syncthreads();
+  const unsigned mask = kept_mask;
+
+  // 4. W = K Q (into Y), T = Q^T W, symmetrised; V = I
+  for (int i = tid; i < n; i += NT) {
+    double acc[R];
+#pragma unroll
+    for (int c = 0; c < R; ++c) acc[c] = 0.0;
+    for (int j = 0; j < n; ++j) {
+      const double kv = Km[(size_t)j * n + i];
+#pragma unroll
+      for (int c = 0; c < R; ++c) acc[c] += kv * Z[j * R + c];
+    }
+#pragma unroll
+    for (int c = 0; c < R; ++c) Y[i * R + c] = acc[c];
+  }
+  __syncthreads();
+  {
+    const int a = tid / R, b = tid % R;
+    double t = 0.0;
+    for (int i = 0; i < n; ++i) t += Z[i * R + a] * Y[i * R + b];
+    red[tid] = t;
+    V[tid] = a == b ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  {
+    const int a = tid / R, b = tid % R;
+    const bool on = (mask >> a & 1u) && (mask >> b & 1u);
+    T[tid] = on ? 0.5 * (red[a * R + b] + red[b * R + a]) : 0.0;  // dropped columns decoupled
+  }
+  __syncthreads();
+
+  // 5. two-sided cyclic Jacobi on T (round-robin ordering, R/2 disjoint rotations per round)
+  for (int sweep = 0; sweep < 40; ++sweep) {
+    const int a = tid / R, b = tid % R;
+    const double v = T[tid];
+    const double off = block_sum(a != b ? v * v : 0.0, red);
+    const double dia = block_sum(a == b ? v * v : 0.0, red);
+    if (!(off > 1e-32 * dia)) break;  // also ends on a non-finite T
+    for (int round = 0; round < R - 1; ++round) {
+      if (tid < RH) {
+        int p, q;
+        if (tid == 0) {
+          p = R - 1;
+          q = round;
+        } else {
+          p = (round + tid) % (R - 1);
+          q = (round - tid + R - 1) % (R - 1);
+        }
+        const double app = T[p * R + p], aqq = T[q * R + q], apq = T[p * R + q];
+        double c = 1.0, s = 0.0;
+        if (apq != 0.0) {
+          const double tau = (aqq - app) / (2.0 * apq);
+          const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+          c = 1.0 / sqrt(1.0 + t * t);
+          s = t * c;
+        }
+        rc[tid] = c;
+        rs[tid] = s;
+        rp[tid] = p;
+        rq[tid] = q;
+      }
+      __syncthreads();
+      if (tid < RH * R) {  // rows p, q of T
+        const int g = tid / R, j = tid % R, p = rp[g], q = rq[g];
+        const double c = rc[g], s = rs[g], tp = T[p * R + j], tq = T[q * R + j];
+        T[p * R + j] = c * tp - s * tq;
+        T[q * R + j] = s * tp + c * tq;
+      }
+      __syncthreads();
+      {  // columns p, q of T (first half of the threads) and of V (second half)
+        const int g = (tid / R) % RH, i = tid % R, p = rp[g], q = rq[g];
+        double* Mx = tid < RH * R ? T : V;
+        const double c = rc[g], s = rs[g], tp = Mx[i * R + p], tq = Mx[i * R + q];
+        Mx[i * R + p] = c * tp - s * tq;
+        Mx[i * R + q] = s * tp + c * tq;
+      }
+      __syncthreads();
+    }
+  }
+
+  // 6. smallest Ritz value over the kept columns, its Ritz vector as the next start
+  if (tid == 0) {
+    int bi = -1;
+    double bv = INFINITY;
+    for (int a = 0; a < R; ++a)
+      if ((mask >> a & 1u) && T[a * R + a] < bv) {
+        bv = T[a * R + a];
+        bi = a;
+      }
+    best_idx = bi;
+    lmin[mat] = bi >= 0 ? bv : NAN;
+    const bool bad = bi < 0 || !(below <= R - 1.5);
+    flags[mat] = bad ? 1 : 0;
+    if (bad) atomicAdd(nflag, 1);
+  }
+  __syncthreads();
+  const int bi = best_idx;
+  if (bi >= 0)
+    for (int i = tid; i < n; i += NT) {
+      double v = 0.0;
+#pragma unroll
+      for (int c = 0; c < R; ++c) v += Z[i * R + c] * V[c * R + bi];
+      xm[i] = v;
+    }
+}
+
+template <typename S>
+hipError_t slice_pass(const double* K, double* x, double* sigma, double* lmin, int* flags, int* nflag, int n,
+                      int count, void* work_raw, hipStream_t st) {
+  S* work = static_cast<S*>(work_raw);
+  hipLaunchKernelGGL(slice_shift_kernel, dim3(count), dim3(kSignThreads), 0, st, K, x, sigma, nflag, n);
+  int X = 0, steps = 0;
+  const hipError_t e = sign_function<S>(ShiftPolicy{K, sigma, n}, n, count, work, st, nullptr, &X, &steps);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((slice_ritz_kernel<S>), dim3(count), dim3(kSignThreads), 0, st, K, work, X, x, lmin, flags,
+                     nflag, n);
   return hipGetLastError();
 }
 
@@ -240,6 +581,14 @@ hipError_t launch_momentum_projection_sign(double* Xh, int n_op, int K, int* swe
   MomentumPolicy pol{Xh, sweeps, n_op};
   return precision == VEMB_FP64 ? sign_project<cplx<double>>(pol, n_op, K, work, st)
                                 : sign_project<cplx<float>>(pol, n_op, K, work, st);
+}
+
+hipError_t launch_lambda_min_slice(const double* K, double* x, double* sigma, double* lmin, int* flags, int* nflag,
+                                   int n, int count, void* work, hipStream_t st, int precision) {
+  if (count <= 0) return hipSuccess;
+  if (n % 64 || n > kSignMax) return hipErrorInvalidValue;
+  return precision == VEMB_FP64 ? slice_pass<double>(K, x, sigma, lmin, flags, nflag, n, count, work, st)
+                                : slice_pass<float>(K, x, sigma, lmin, flags, nflag, n, count, work, st);
 }
 
 hipError_t launch_projection_group_sign(int kind, int n, int count, const int2* item, const void* ptrs, void* work,
