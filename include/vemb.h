@@ -123,6 +123,17 @@ typedef struct {
                            VEMB_E_NUMERIC or VEMB_E_DIVERGED, naming the iteration.  While it is on, the
                            library owns the queued diagnostics (vemb_diagnostics_collect returns the latest
                            it queued).  0 (default): no diagnostics inside vemb_step. */
+  int32_t adapt_every;  /* > 0: adaptive parameters (Section 4 notes that tuning mu, nu, eps to a problem could
+                           smooth convergence).  (mu, nu, eps) = c (mu_0, nu_0, eps_0) from the values above;
+                           every adapt_every iterations vemb_step evaluates the FP64 diagnostics after the
+                           iteration (the equality residual of eq. feasErr and the relative primal-dual gap
+                           |E_p - LB| / |LB|, a bound evaluation) and multiplies c by 1.25 when both fell since
+                           the previous check by more than a relative 1e-6, by 0.5 when either rose by more (a
+                           quantity whose two values lie below 1e-12 counts as neither), c within [1, 8]; the
+                           first check only records them.  The multipliers are unscaled, so a change keeps every
+                           fixed point.  Single translation-invariant problems only (vemb_batch_create and
+                           vemb_dense_create refuse it).  0 (default): the fixed parameters of the paper's
+                           runs. */
 } vemb_options;
 
 typedef struct vemb_problem vemb_problem;
@@ -228,6 +239,17 @@ int vemb_set_state(vemb_problem* p, const vemb_state* s);
  * records cap + 1; its kept eigenvectors are then reset to the identity, so its next solve
  * starts cold.  Returns VEMB_E_NOCONV (with both counts written) when a count exceeds the cap. */
 int vemb_last_sweeps(vemb_problem* p, int* pair_max, int* momentum_max);
+
+/* Parameters in force (adaptive mode, vemb_options.adapt_every): *mu, *nu, *eps, the joint scale *scale
+ * (1 without adaptation), and *last_feas, *last_gap, feasErr (eq. feasErr) and the relative primal-dual gap
+ * at the last check (-1 before the first).  Any output pointer may be NULL.  Errors: VEMB_E_INVALID for a
+ * NULL problem. */
+int vemb_penalties(const vemb_problem* p, double* mu, double* nu, double* eps, double* scale, double* last_feas,
+                   double* last_gap);
+/* Resume an adaptive run: sets the joint scale (within [1, 8]) and the values of the last check (either
+ * negative: none, the next check only records); the parameters become scale times the created ones.
+ * Errors: VEMB_E_INVALID (NULL problem, scale outside [1, 8] or not finite). */
+int vemb_set_penalty_scale(vemb_problem* p, double scale, double last_feas, double last_gap);
 
 /* The divergence watchdog's rule, on the host (no device work): feas[0..count) are the feasibility
  * errors (eq. feasErr) of successive diagnostics, oldest first; lb and energy the latest bound and

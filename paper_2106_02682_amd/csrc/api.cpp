@@ -313,6 +313,18 @@ bool all_finite(const double* v, size_t count) {
   return true;
 }
 
+// Penalties, step and the coefficients of the pair update's closed-form inverse (eq. rhoijUpdate):
+// rho = a R + (b/m)(Tr_2 R x I + I x Tr_1 R) + (c/m^2) Tr R I.
+void set_parameters(StepArgs& a, double mu, double nu, double eps) {
+  const int m = a.m;
+  a.mu = mu;
+  a.nu = nu;
+  a.eps = eps;
+  a.a = 1.0 / mu;
+  a.b = 1.0 / (mu + nu * m) - 1.0 / mu;
+  a.c = 1.0 / (mu + 2 * nu * m) - 2.0 / (mu + nu * m) + 1.0 / mu;
+}
+
 }  // namespace
 
 extern "C" {
@@ -387,13 +399,8 @@ int vemb_create_problem(const vemb_hamiltonian* H, const vemb_lattice* lat, cons
   a.Ku = Ku;
   a.opset = o.opset;
   a.fermionic = o.fermionic;
-  a.mu = o.mu;
-  a.nu = o.nu;
-  a.eps = o.eps;
   a.sign = o.sign < 0 ? -1.0 : 1.0;
-  a.a = 1.0 / o.mu;
-  a.b = 1.0 / (o.mu + o.nu * m) - 1.0 / o.mu;
-  a.c = 1.0 / (o.mu + 2 * o.nu * m) - 2.0 / (o.mu + o.nu * m) + 1.0 / o.mu;
+  set_parameters(a, o.mu, o.nu, o.eps);
   auto cleanup = [&](int code) {
     vemb_destroy(p);
     return code;
@@ -501,6 +508,43 @@ int watchdog(vemb_problem* p) {
 
 // prec: VEMB_FP64, or the problem's MIXED / FP32 mode, whose eigensolves run in FP32 (sweeps, rebuild and
 // sign-function products; state and diagnostics stay FP64).
+// Adaptive parameters (vemb_options.adapt_every), after iteration t: the FP64 diagnostics (feasErr of eq.
+// feasErr and the relative primal-dual gap |E_p - LB| / |LB|), then one decision of the joint scale of
+// (mu, nu, eps): grown when both fell by more than a relative dead band, shrunk when either rose by more
+// (a quantity whose two values both lie at the rounding floor counts as neither).  Synchronises the stream.
+constexpr double kAdaptGrow = 1.25, kAdaptShrink = 0.5, kAdaptMax = 8.0, kAdaptDead = 1e-6, kAdaptFloor = 1e-12;
+
+int trend(double x, double x_prev) {
+  if (x <= kAdaptFloor && x_prev <= kAdaptFloor) return 0;
+  if (x < x_prev * (1.0 - kAdaptDead)) return -1;
+  if (x > x_prev * (1.0 + kAdaptDead)) return 1;
+  return 0;
+}
+
+double next_scale(double c, double f, double g, double f_prev, double g_prev) {
+  const int tf = trend(f, f_prev), tg = trend(g, g_prev);
+  if (tf > 0 || tg > 0)
+    c *= kAdaptShrink;
+  else if (tf < 0 && tg < 0)
+    c *= kAdaptGrow;
+  return std::min(std::max(c, 1.0), kAdaptMax);
+}
+
+int adapt_check(vemb_problem* p) {
+  double lb = 0.0, e = 0.0, f = 0.0;
+  VEMB_TRY(vemb_diagnostics(p, &lb, &e, &f));
+  const double g = std::fabs(e - lb) / std::fabs(lb);
+  if (!std::isfinite(g)) return fail(VEMB_E_NUMERIC, "non-finite gap at iteration " + std::to_string(p->t));
+  if (p->adapt_last >= 0.0) {
+    p->adapt_scale = next_scale(p->adapt_scale, f, g, p->adapt_last, p->adapt_last_gap);
+    const double c = p->adapt_scale;
+    set_parameters(p->a, c * p->opt.mu, c * p->opt.nu, c * p->opt.eps);
+  }
+  p->adapt_last = f;
+  p->adapt_last_gap = g;
+  return VEMB_OK;
+}
+
 int run_iterations(vemb_problem* p, int iters, int prec) {
   const StepArgs& a = p->a;
   hipStream_t s = p->stream;
@@ -526,6 +570,7 @@ int run_iterations(vemb_problem* p, int iters, int prec) {
       p->v_fp32 = sp != VEMB_FP64;
       ++p->t;
       if (p->opt.lb_every > 0 && p->t % p->opt.lb_every == 0) VEMB_TRY(watchdog(p));
+      if (p->opt.adapt_every > 0 && p->t % p->opt.adapt_every == 0) VEMB_TRY(adapt_check(p));
       continue;
     }
     // fork: pair projection on the side stream (reads rho, Lambda; writes rho_t,
@@ -553,6 +598,7 @@ int run_iterations(vemb_problem* p, int iters, int prec) {
     p->v_fp32 = sp != VEMB_FP64;
     ++p->t;
     if (p->opt.lb_every > 0 && p->t % p->opt.lb_every == 0) VEMB_TRY(watchdog(p));
+    if (p->opt.adapt_every > 0 && p->t % p->opt.adapt_every == 0) VEMB_TRY(adapt_check(p));
   }
   return VEMB_OK;
 }
@@ -876,6 +922,29 @@ int vemb_set_state(vemb_problem* p, const vemb_state* st) {
   p->v_valid = with_v;
   p->k_valid = false;
   p->t = st->t;
+  return VEMB_OK;
+}
+
+int vemb_penalties(const vemb_problem* p, double* mu, double* nu, double* eps, double* scale, double* last_feas,
+                   double* last_gap) {
+  if (!p) return fail(VEMB_E_INVALID, "NULL problem");
+  if (mu) *mu = p->a.mu;
+  if (nu) *nu = p->a.nu;
+  if (eps) *eps = p->a.eps;
+  if (scale) *scale = p->adapt_scale;
+  if (last_feas) *last_feas = p->adapt_last;
+  if (last_gap) *last_gap = p->adapt_last_gap;
+  return VEMB_OK;
+}
+
+int vemb_set_penalty_scale(vemb_problem* p, double scale, double last_feas, double last_gap) {
+  if (!p) return fail(VEMB_E_INVALID, "NULL problem");
+  if (!(scale >= 1.0 && scale <= kAdaptMax)) return fail(VEMB_E_INVALID, "penalty scale outside [1, 8]");
+  const bool have = last_feas >= 0.0 && last_gap >= 0.0;
+  p->adapt_scale = scale;
+  p->adapt_last = have ? last_feas : -1.0;
+  p->adapt_last_gap = have ? last_gap : -1.0;
+  set_parameters(p->a, scale * p->opt.mu, scale * p->opt.nu, scale * p->opt.eps);
   return VEMB_OK;
 }
 

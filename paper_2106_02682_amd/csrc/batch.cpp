@@ -206,6 +206,8 @@ int vemb_batch_create(vemb_problem* const* problems, int count, int use_graph, v
       return fail(VEMB_E_INVALID, "problems of a batch must share max_sweeps and warm_refresh");
     for (int j = 0; j < i; ++j)
       if (problems[j] == problems[i]) return fail(VEMB_E_INVALID, "a problem appears twice in the batch");
+    if (problems[i]->opt.adapt_every > 0)
+      return fail(VEMB_E_UNSUPPORTED, "adaptive parameters (adapt_every) run on single problems only");
   }
   auto* b = new vemb_batch();
   object_created();

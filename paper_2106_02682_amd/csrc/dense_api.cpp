@@ -118,6 +118,7 @@ int vemb_dense_create(const vemb_hamiltonian* H, const vemb_lattice* lat, const 
   // matrix cores above (storage padded with zeros to a multiple of 32)
   if (K > 1024) return fail(VEMB_E_UNSUPPORTED, "dense X above 1024 x 1024 (M n_op = " + std::to_string(K) + ")");
   if (n > 256) return fail(VEMB_E_UNSUPPORTED, "pair matrices above 256 x 256 are not supported");
+  if (o.adapt_every > 0) return fail(VEMB_E_UNSUPPORTED, "adaptive parameters run on translation-invariant problems");
   const int ld = K <= 64 ? K : (K + 31) / 32 * 32;
   HostModel host;
   rc = build_model(*H, g, host, err, o.fermionic != 0);

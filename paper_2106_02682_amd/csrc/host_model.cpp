@@ -90,6 +90,7 @@ int normalize_options(const vemb_options* in, vemb_options& o, std::string& err)
   if (o.precision < VEMB_FP64 || o.precision > VEMB_FP32) return err = "unknown precision", VEMB_E_INVALID;
   if (o.fermionic != 0 && o.fermionic != 1) return err = "fermionic must be 0 or 1", VEMB_E_INVALID;
   if (o.lb_every < 0) return err = "lb_every must be >= 0", VEMB_E_INVALID;
+  if (o.adapt_every < 0) return err = "adapt_every must be >= 0", VEMB_E_INVALID;
   if (o.fermionic && o.opset != VEMB_OPSET_COMPLETE)
     return err = "fermionic problems use the complete operator collection", VEMB_E_UNSUPPORTED;
   return VEMB_OK;

@@ -37,6 +37,9 @@ struct vemb_problem {
   double* diag_host = nullptr;
   hipEvent_t diag_ev = nullptr;
   bool diag_pending = false;
+  double adapt_scale = 1.0;   // joint scale of (mu, nu, eps) (vemb_options.adapt_every)
+  double adapt_last = -1.0;   // feasErr at the last adaptation check, < 0 before the first
+  double adapt_last_gap = -1.0;  // relative primal-dual gap at the last check
   std::vector<double> feas_hist;  // feasibility errors of the watchdog's checks (vemb_options.lb_every)
   struct Mark { int id; hipEvent_t start, stop; };
   std::vector<Mark> marks;

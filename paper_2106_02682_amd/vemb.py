@@ -39,6 +39,7 @@ EXPORTS = [
     "vemb_dense_set_state", "vemb_dense_last_sweeps", "vemb_dense_destroy", "vemb_psd_project_sign",
     "vemb_set_profiling_every", "vemb_psd_project_sign_noalloc", "vemb_batch_set_profiling",
     "vemb_batch_get_profile", "vemb_tile_map", "vemb_set_allocator", "vemb_divergence_check",
+    "vemb_penalties", "vemb_set_penalty_scale",
 ]
 BATCH_KERNELS = ["pair_update", "pair_xstep", "cluster_update", "dft_forward", "dft_inverse", "pair_jacobi",
                  "momentum_jacobi", "sign_gemm_real", "sign_gemm_complex"]
@@ -73,7 +74,7 @@ class vemb_options(ctypes.Structure):
     _fields_ = [("mu", ctypes.c_double), ("nu", ctypes.c_double), ("eps", ctypes.c_double),
                 ("opset", ctypes.c_int32), ("precision", ctypes.c_int32), ("max_sweeps", ctypes.c_int32),
                 ("sign", ctypes.c_int32), ("warm_refresh", ctypes.c_int32), ("tpb", ctypes.c_int32),
-                ("fermionic", ctypes.c_int32), ("lb_every", ctypes.c_int32)]
+                ("fermionic", ctypes.c_int32), ("lb_every", ctypes.c_int32), ("adapt_every", ctypes.c_int32)]
 
 
 class vemb_info(ctypes.Structure):
@@ -318,7 +319,7 @@ def default_options():
 
 
 def _marshal(terms, extent, cluster, opset, precision, mu, nu, eps, max_sweeps, sign, warm_refresh, tpb,
-             fermionic=False, lb_every=0):
+             fermionic=False, lb_every=0, adapt_every=0):
     """ctypes structs of a term list (``synth`` format: (coeff, ((pauli, (ox, oy)), ...))), lattice,
     clusters and options; the term array is returned too, to stay alive with the Hamiltonian."""
     arr = (vemb_term * max(1, len(terms)))()
@@ -343,15 +344,17 @@ def _marshal(terms, extent, cluster, opset, precision, mu, nu, eps, max_sweeps, 
     o.tpb = tpb
     o.fermionic = 1 if fermionic else 0
     o.lb_every = int(lb_every)
+    o.adapt_every = int(adapt_every)
     return H, lat, cl, o, arr
 
 
 def create_problem(terms, extent, cluster, opset="complete", precision="fp64", mu=10.0, nu=10.0, eps=2.0,
-                   max_sweeps=40, sign=-1, warm_refresh=64, tpb=0, stream=None, fermionic=False, lb_every=0):
+                   max_sweeps=40, sign=-1, warm_refresh=64, tpb=0, stream=None, fermionic=False, lb_every=0,
+                   adapt_every=0):
     """Terms in the ``synth`` format: (coeff, ((pauli, (ox, oy)), ...)); "F" letters are the ends of a
     fermionic hopping (fermionic problems)."""
     H, lat, cl, o, _keep = _marshal(terms, extent, cluster, opset, precision, mu, nu, eps, max_sweeps, sign,
-                                    warm_refresh, tpb, fermionic, lb_every)
+                                    warm_refresh, tpb, fermionic, lb_every, adapt_every)
     h = ctypes.c_void_p()
     _ensure_allocator()
     st = stream if stream is not None else current_stream()
@@ -368,6 +371,18 @@ def problem_info(h):
 
 def step(h, iters):
     _check(lib().vemb_step(h, int(iters)))
+
+
+def penalties(h):
+    """Parameters in force: dict mu, nu, eps, scale (joint scale of the adaptive mode), last_feas, last_gap."""
+    v = [ctypes.c_double() for _ in range(6)]
+    _check(lib().vemb_penalties(h, *[ctypes.byref(x) for x in v]))
+    return dict(zip(("mu", "nu", "eps", "scale", "last_feas", "last_gap"), (x.value for x in v)))
+
+
+def set_penalty_scale(h, scale, last_feas=-1.0, last_gap=-1.0):
+    _check(lib().vemb_set_penalty_scale(h, ctypes.c_double(scale), ctypes.c_double(last_feas),
+                                        ctypes.c_double(last_gap)))
 
 
 def refine(h, iters=1):
@@ -575,6 +590,12 @@ class Problem:
 
     def step(self, iters=1):
         step(self.h, iters)
+
+    def penalties(self):
+        return penalties(self.h)
+
+    def set_penalty_scale(self, scale, last_feas=-1.0, last_gap=-1.0):
+        set_penalty_scale(self.h, scale, last_feas, last_gap)
 
     def refine(self, iters=1):
         refine(self.h, iters)
@@ -826,9 +847,10 @@ class Dense:
     Pairs (i, j), i < j, in lexicographic order; state arrays are stacked in that order."""
 
     def __init__(self, terms, extent, cluster, fields=(), opset="complete", precision="fp64", mu=10.0, nu=10.0,
-                 eps=2.0, max_sweeps=40, sign=-1, warm_refresh=64, tpb=0, stream=None, fermionic=False):
+                 eps=2.0, max_sweeps=40, sign=-1, warm_refresh=64, tpb=0, stream=None, fermionic=False,
+                 adapt_every=0):
         H, lat, cl, o, keep = _marshal(terms, extent, cluster, opset, precision, mu, nu, eps, max_sweeps, sign,
-                                       warm_refresh, tpb, fermionic)
+                                       warm_refresh, tpb, fermionic, 0, adapt_every)
         fields = list(fields)
         farr = (vemb_site_field * max(1, len(fields)))()
         for f, (letter, (x, y), coeff) in enumerate(fields):
