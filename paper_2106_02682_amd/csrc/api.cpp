@@ -344,19 +344,6 @@ int vemb_set_allocator(vemb_alloc_fn alloc_fn, vemb_free_fn free_fn, void* ctx) 
   return VEMB_OK;
 }
 
-void vemb_default_options(vemb_options* o) {
-  if (!o) return;
-  std::memset(o, 0, sizeof(*o));
-  o->mu = 10.0;
-  o->nu = 10.0;
-  o->eps = 2.0;
-  o->opset = VEMB_OPSET_COMPLETE;
-  o->precision = VEMB_FP64;
-  o->max_sweeps = 40;
-  o->sign = -1;
-  o->warm_refresh = 64;
-}
-
 int vemb_create_problem(const vemb_hamiltonian* H, const vemb_lattice* lat, const vemb_clusters* cl,
                         const vemb_options* opts, void* hip_stream, vemb_problem** out) {
   if (!H || !lat || !cl || !out || (H->nterms > 0 && !H->terms)) return fail(VEMB_E_INVALID, "NULL argument");

@@ -96,7 +96,8 @@ template <> struct convert<cplx<double>, cplx<float>> {
 // order, carries the first cluster's parity string, which multiplies the unit E_ba of the
 // first cluster by (-1)^popcount(a).
 __device__ inline double jw_sign(int a, int c, int e) {
-  return (((__popc(c) + __popc(e)) & __popc(a)) & 1) ? -1.0 : 1.0;
+  const int pc = __builtin_popcount((unsigned)c), pe = __builtin_popcount((unsigned)e);
+  return (((pc + pe) & __builtin_popcount((unsigned)a)) & 1) ? -1.0 : 1.0;
 }
 
 constexpr int kMaxOps = 12;  // 3 L for L <= 4

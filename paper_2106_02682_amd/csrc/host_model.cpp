@@ -7,6 +7,7 @@
 
 #include <cmath>
 #include <complex>
+#include <cstring>
 #include <stdexcept>
 
 namespace vemb {
@@ -79,6 +80,24 @@ void add_hopping(std::vector<cd>& H, int nsites, int p, int q, double coeff) {
 
 }  // namespace
 
+}  // namespace vemb
+
+// The options' defaults live with their validation (host code only).
+extern "C" void vemb_default_options(vemb_options* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->mu = 10.0;
+  o->nu = 10.0;
+  o->eps = 2.0;
+  o->opset = VEMB_OPSET_COMPLETE;
+  o->precision = VEMB_FP64;
+  o->max_sweeps = 40;
+  o->sign = -1;
+  o->warm_refresh = 64;
+}
+
+namespace vemb {
+
 int normalize_options(const vemb_options* in, vemb_options& o, std::string& err) {
   vemb_default_options(&o);
   if (in) o = *in;
@@ -110,6 +129,8 @@ int parse_geometry(const vemb_lattice& lat, const vemb_clusters& cl, Geometry& g
   if (g.Nx % g.Lx || g.Ny % g.Ly) return err = "clusters do not tile the lattice", VEMB_E_INVALID;
   g.Mx = g.Nx / g.Lx;
   g.My = g.Ny / g.Ly;
+  // cluster counts beyond 2^20 would not fit the per-offset tables (and overflow int products)
+  if ((long long)g.Mx * g.My > (1LL << 20)) return err = "more than 2^20 clusters", VEMB_E_UNSUPPORTED;
   g.M = g.Mx * g.My;
   g.L = g.Lx * g.Ly;
   if (g.M < 2) return err = "at least two clusters are needed (M >= 2)", VEMB_E_UNSUPPORTED;
