@@ -382,10 +382,20 @@ int vemb_batch_create(vemb_problem* const* problems, int count, int use_graph, v
  * is ordered after them.  Asynchronous. */
 int vemb_batch_step(vemb_batch* b, int iters);
 /* Host arrays of length count: per-problem vemb_dual_bound results and status
- * codes (status may be NULL).  Synchronises; returns the last failing status. */
+ * codes (status may be NULL).  Synchronises; returns the last failing status.  An instance whose
+ * bound is not finite (VEMB_E_NUMERIC) is masked (vemb_batch_set_active): later steps skip it. */
 int vemb_batch_dual_bounds(vemb_batch* b, double* lb_per_site, int* status);
-/* Host arrays of length count (either may be NULL): vemb_primal_energy per problem. */
+/* Host arrays of length count (either may be NULL): vemb_primal_energy per problem.  An instance whose
+ * energy or feasibility error is not finite is masked, as above. */
 int vemb_batch_primal_energies(vemb_batch* b, double* e_per_site, double* feas_err);
+/* Failure masking.  A masked instance (active = 0) is skipped by every launch of later steps -- its
+ * workgroups return at once, inside graph replays too -- so its state and iteration count stay as they
+ * were (for inspection, or vemb_set_state and unmasking) and a diverged instance no longer costs its
+ * eigensolves' sweep cap in every class launch; the other instances step exactly as before.  index in
+ * [0, count); synchronises the batch stream.  Errors: VEMB_E_INVALID. */
+int vemb_batch_set_active(vemb_batch* b, int index, int active);
+/* Host array of length count: 1 for stepped instances, 0 for masked ones. */
+int vemb_batch_get_active(const vemb_batch* b, int* active);
 /* Number of eigensolver size classes and kernel launches per iteration. */
 int vemb_batch_info(const vemb_batch* b, int* classes, int* launches_per_iteration);
 /* Sampled kernel timing of a batch.  every >= 1: the iterations whose batch iteration index (counted

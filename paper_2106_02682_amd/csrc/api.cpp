@@ -387,6 +387,7 @@ int vemb_create_problem(const vemb_hamiltonian* H, const vemb_lattice* lat, cons
   a.opset = o.opset;
   a.fermionic = o.fermionic;
   a.sign = o.sign < 0 ? -1.0 : 1.0;
+  a.active = 1;
   set_parameters(a, o.mu, o.nu, o.eps);
   auto cleanup = [&](int code) {
     vemb_destroy(p);

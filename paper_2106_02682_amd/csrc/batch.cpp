@@ -11,6 +11,7 @@
 // replayed.  Each instance keeps its own state and kept eigenvectors, so a
 // problem can be stepped alone or in a batch interchangeably.
 #include <algorithm>
+#include <cstddef>
 #include <map>
 #include <tuple>
 #include <vector>
@@ -31,6 +32,7 @@ struct vemb_batch {
   int nwork[5] = {};
   PairPtrs* d_pair = nullptr;
   MomPtrs* d_mom = nullptr;
+  std::vector<int> active;  // host copy of the instances' mask (1 stepped, 0 masked)
   struct Group {
     int kind, n, precision, count, tpb;
     int2* d_item;
@@ -61,6 +63,22 @@ int balloc(vemb_batch* b, T** p, size_t count) {
   void* raw = b->mem.get(std::max<size_t>(count, 1) * sizeof(T));
   if (!raw) return fail(VEMB_E_NOMEM, "batch allocation");
   *p = static_cast<T*>(raw);
+  return VEMB_OK;
+}
+
+// Mask (0) or unmask (1) instance i: the flags inside its device step arguments and projection pointers,
+// written on the batch stream, so that later launches and graph replays see them.
+int set_active(vemb_batch* b, int i, int active) {
+  hipStream_t s = b->stream;
+  const int v = active;
+  char* a = reinterpret_cast<char*>(b->d_args + i) + offsetof(StepArgs, active);
+  char* pp = reinterpret_cast<char*>(b->d_pair + i) + offsetof(PairPtrs, active);
+  char* mp = reinterpret_cast<char*>(b->d_mom + i) + offsetof(MomPtrs, active);
+  VEMB_TRY(hip_rc(hipMemcpyAsync(a, &v, sizeof(int), hipMemcpyHostToDevice, s), "mask"));
+  VEMB_TRY(hip_rc(hipMemcpyAsync(pp, &v, sizeof(int), hipMemcpyHostToDevice, s), "mask"));
+  VEMB_TRY(hip_rc(hipMemcpyAsync(mp, &v, sizeof(int), hipMemcpyHostToDevice, s), "mask"));
+  VEMB_TRY(hip_rc(hipStreamSynchronize(s), "mask sync"));
+  b->active[i] = active;
   return VEMB_OK;
 }
 
@@ -212,6 +230,7 @@ int vemb_batch_create(vemb_problem* const* problems, int count, int use_graph, v
   auto* b = new vemb_batch();
   object_created();
   b->probs.assign(problems, problems + count);
+  b->active.assign(count, 1);
   b->use_graph = use_graph != 0;
   b->refresh = problems[0]->opt.warm_refresh;
   auto cleanup = [&](int rc) {
@@ -234,8 +253,9 @@ int vemb_batch_create(vemb_problem* const* problems, int count, int use_graph, v
   for (int i = 0; i < count; ++i) {
     vemb_problem* p = problems[i];
     args[i] = p->a;
-    pp[i] = {p->a.rho, p->a.Lam, p->a.rho_t, p->a.feas, p->a.sweeps, p->a.Vpair, p->a.mu};
-    mp[i] = {p->a.Xh, p->a.sweeps + p->P, p->a.Vmom};
+    args[i].active = 1;
+    pp[i] = {p->a.rho, p->a.Lam, p->a.rho_t, p->a.feas, p->a.sweeps, p->a.Vpair, p->a.mu, 1};
+    mp[i] = {p->a.Xh, p->a.sweeps + p->P, p->a.Vmom, 1};
     int grid[5][2];
     local_grids(p->a, grid);
     for (int w = 0; w < 5; ++w) {
@@ -313,14 +333,19 @@ int vemb_batch_step(vemb_batch* b, int iters) {
   for (int it = 0; it < iters; ++it) {
     // one graph serves all instances: start cold if any instance would alone
     bool cold = b->refresh < 0;
-    for (vemb_problem* p : b->probs) cold = cold || !p->v_valid || (b->refresh > 0 && p->t % b->refresh == 0);
+    for (size_t i = 0; i < b->probs.size(); ++i) {
+      const vemb_problem* p = b->probs[i];
+      if (b->active[i]) cold = cold || !p->v_valid || (b->refresh > 0 && p->t % b->refresh == 0);
+    }
     const bool timed = b->prof_every > 0 && b->iter % b->prof_every == 0;
     if (b->use_graph && !timed)
       VEMB_TRY(hip_rc(hipGraphLaunch(b->exec[cold ? 1 : 0], b->stream), "graph launch"));
     else
       VEMB_TRY(enqueue_iteration(b, cold ? 1 : 0, timed));
     ++b->iter;
-    for (vemb_problem* p : b->probs) {
+    for (size_t i = 0; i < b->probs.size(); ++i) {
+      if (!b->active[i]) continue;  // a masked instance keeps its state and its iteration count
+      vemb_problem* p = b->probs[i];
       p->v_valid = true;
       p->v_fp32 = solve_precision(p->opt.precision) != VEMB_FP64;
       ++p->t;
@@ -340,6 +365,7 @@ int vemb_batch_dual_bounds(vemb_batch* b, double* lb, int* status) {
     const int rc = vemb_dual_bound(b->probs[i], &lb[i]);
     if (status) status[i] = rc;
     if (rc != VEMB_OK) worst = rc;
+    if (rc == VEMB_E_NUMERIC && b->active[i]) VEMB_TRY(set_active(b, (int)i, 0));
   }
   return worst;
 }
@@ -351,8 +377,21 @@ int vemb_batch_primal_energies(vemb_batch* b, double* e, double* feas) {
   for (size_t i = 0; i < b->probs.size(); ++i) {
     const int rc = vemb_primal_energy(b->probs[i], e ? &e[i] : nullptr, feas ? &feas[i] : nullptr);
     if (rc != VEMB_OK) worst = rc;
+    if (rc == VEMB_E_NUMERIC && b->active[i]) VEMB_TRY(set_active(b, (int)i, 0));
   }
   return worst;
+}
+
+int vemb_batch_set_active(vemb_batch* b, int index, int active) {
+  if (!b || index < 0 || index >= (int)b->probs.size())
+    return fail(VEMB_E_INVALID, "bad arguments to vemb_batch_set_active");
+  return set_active(b, index, active ? 1 : 0);
+}
+
+int vemb_batch_get_active(const vemb_batch* b, int* active) {
+  if (!b || !active) return fail(VEMB_E_INVALID, "NULL argument");
+  for (size_t i = 0; i < b->probs.size(); ++i) active[i] = b->active[i];
+  return VEMB_OK;
 }
 
 int vemb_batch_info(const vemb_batch* b, int* groups, int* launches_per_iteration) {

@@ -484,6 +484,7 @@ __device__ __attribute__((always_inline)) void jacobi_body(Policy pol, int n, in
 template <typename S, int NMAX, int MODE, bool WARM, int NT, typename Policy, bool REG = false>
 __global__ void __launch_bounds__(NT) jacobi_kernel(Policy pol, int n, int max_sweeps, void* vstore_raw, int cold) {
   __shared__ __attribute__((aligned(16))) unsigned char smem[JacobiLds<S, NMAX, WARM, NT>::bytes];
+  if (!policy_active(pol, blockIdx.x)) return;  // a masked batch instance: the whole workgroup
   jacobi_body<S, NMAX, MODE, WARM, NT, Policy, REG>(pol, n, max_sweeps, vstore_raw, cold, blockIdx.x, smem);
 }
 

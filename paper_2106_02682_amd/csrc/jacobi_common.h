@@ -363,6 +363,11 @@ struct BatchedPairPolicy {
   }
 };
 
+// Whether a solve's matrix belongs to an instance that is being stepped: always for single problems; a
+// batch skips the blocks of a masked instance (their workgroups return before any work).
+template <typename Policy> __device__ inline bool policy_active(const Policy&, int) { return true; }
+__device__ inline bool policy_active(const BatchedPairPolicy& p, int mat) { return p.inst[p.item[mat].x].active != 0; }
+
 struct BatchedMomentumPolicy {
   const int2* item;
   const MomPtrs* inst;
@@ -394,6 +399,9 @@ struct BatchedMomentumPolicy {
     return reinterpret_cast<D*>(inst[w.x].vstore) + (size_t)w.y * nn;
   }
 };
+__device__ inline bool policy_active(const BatchedMomentumPolicy& p, int mat) {
+  return p.inst[p.item[mat].x].active != 0;
+}
 
 
 }  // namespace

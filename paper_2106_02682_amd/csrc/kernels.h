@@ -15,11 +15,13 @@ struct PairPtrs {
   int* sweeps;
   double* vstore;
   double mu;
+  int active;  // 0: the instance is masked in its batch (its blocks are skipped)
 };
 struct MomPtrs {
   double* Xh;
   int* sweeps;
   double* vstore;
+  int active;
 };
 // kind 0: pair projections (PairPtrs), kind 1: momentum projections (MomPtrs).
 // item: device array count x int2 (instance, local index); ptrs: device array of
@@ -122,6 +124,7 @@ struct StepArgs {
   void* tscr_pair;
   void* wscr_mom;   // (n_op > 64): Ku x n_op x n_op complex doubles each
   void* tscr_mom;
+  int active;  // batches: 0 masks the instance (every batched kernel skips its blocks); 1 otherwise
 };
 
 // Batched step kernels: work[b] = {instance, local block x, local block y}.

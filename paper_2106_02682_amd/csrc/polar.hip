@@ -52,7 +52,9 @@ __global__ void __launch_bounds__(256) ns_init_kernel(const double* in, double* 
   const int i = (int)(e / ld), j = (int)(e % ld);
   double s2 = 0.0;
   for (int b = 0; b < kNormBlocks; ++b) s2 += partial[b];
-  const double inv = s2 > 0.0 ? 1.0 / (1.01 * sqrt(s2)) : 1.0;
+  // a squared norm that overflows (entries beyond ~1e150: a diverged iterate) scales by NaN, so the
+  // failure shows in every result instead of a silently wrong projection (a zero scale)
+  const double inv = s2 > 0.0 ? (s2 < INFINITY ? 1.0 / (1.01 * sqrt(s2)) : NAN) : 1.0;
   const double a = 0.5 * (in[e] + in[(long)j * ld + i]);
   A[e] = a;
   X[e] = a * inv;

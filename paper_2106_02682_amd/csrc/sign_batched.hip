@@ -40,6 +40,7 @@ template <typename S, typename Policy>
 __global__ void __launch_bounds__(kSignThreads) sign_load_kernel(Policy pol, int n, S* work) {
   constexpr int TB = 32, LDT = TB + 1, TT = TB * TB;
   const int mat = blockIdx.x, tid = threadIdx.x;
+  if (!policy_active(pol, mat)) return;  // a masked batch instance: its products run on stale data, unused
   const size_t nn = (size_t)n * n;
   S* A = work + (size_t)mat * 4 * nn;
   S* X = A + nn;
@@ -71,7 +72,9 @@ __global__ void __launch_bounds__(kSignThreads) sign_load_kernel(Policy pol, int
     __syncthreads();
   }
   const double s2 = block_sum(acc, red);
-  const double inv = s2 > 0.0 ? 1.0 / (1.01 * sqrt(s2)) : 1.0;
+  // a squared norm that overflows (entries beyond ~1e150: a diverged iterate) scales by NaN, so the
+  // failure shows in every result instead of a silently wrong projection (a zero scale)
+  const double inv = s2 > 0.0 ? (s2 < INFINITY ? 1.0 / (1.01 * sqrt(s2)) : NAN) : 1.0;
   for (int idx = 0; idx < pairs; ++idx) {
     int ti = 0, tj = 0;
     upper_tile(idx, tiles, &ti, &tj);
@@ -211,6 +214,7 @@ template <typename S, typename Policy>
 __global__ void __launch_bounds__(kSignThreads) sign_store_kernel(Policy pol, int n, const S* work, int pi_off,
                                                                   int steps) {
   const int mat = blockIdx.x;
+  if (!policy_active(pol, mat)) return;
   const size_t nn = (size_t)n * n;
   const S* Pi = work + (size_t)mat * 4 * nn + pi_off;
   __shared__ double red[kSignThreads];

@@ -365,23 +365,29 @@ __global__ void __launch_bounds__(kPairThreads) pair_update_kernel(StepArgs A) {
 __global__ void __launch_bounds__(kBlock) pair_xstep_kernel(StepArgs A) { pair_xstep_body(A, blockIdx.x, blockIdx.y); }
 __global__ void __launch_bounds__(kClusterBlock) cluster_update_kernel(StepArgs A) { cluster_update_body(A); }
 
+// A masked instance (args[i].active == 0) keeps its state: its workgroups return at once.
 __global__ void __launch_bounds__(kPairThreads) pair_update_batched(const StepArgs* args, const WorkItem* work) {
   const WorkItem w = work[blockIdx.x];
+  if (!args[w.inst].active) return;
   pair_update_body(args[w.inst], w.bx);
 }
 __global__ void __launch_bounds__(kBlock) pair_xstep_batched(const StepArgs* args, const WorkItem* work) {
   const WorkItem w = work[blockIdx.x];
+  if (!args[w.inst].active) return;
   pair_xstep_body(args[w.inst], w.bx, w.by);
 }
 __global__ void __launch_bounds__(kClusterBlock) cluster_update_batched(const StepArgs* args) {
+  if (!args[blockIdx.x].active) return;
   cluster_update_body(args[blockIdx.x]);
 }
 __global__ void __launch_bounds__(kBlock) dft_forward_batched(const StepArgs* args, const WorkItem* work) {
   const WorkItem w = work[blockIdx.x];
+  if (!args[w.inst].active) return;
   dft_mfma_body<true>(args[w.inst], w.bx, w.by);
 }
 __global__ void __launch_bounds__(kBlock) dft_inverse_batched(const StepArgs* args, const WorkItem* work) {
   const WorkItem w = work[blockIdx.x];
+  if (!args[w.inst].active) return;
   dft_mfma_body<false>(args[w.inst], w.bx, w.by);
 }
 

@@ -39,7 +39,7 @@ EXPORTS = [
     "vemb_dense_set_state", "vemb_dense_last_sweeps", "vemb_dense_destroy", "vemb_psd_project_sign",
     "vemb_set_profiling_every", "vemb_psd_project_sign_noalloc", "vemb_batch_set_profiling",
     "vemb_batch_get_profile", "vemb_tile_map", "vemb_set_allocator", "vemb_divergence_check",
-    "vemb_penalties", "vemb_set_penalty_scale",
+    "vemb_penalties", "vemb_set_penalty_scale", "vemb_batch_set_active", "vemb_batch_get_active",
 ]
 BATCH_KERNELS = ["pair_update", "pair_xstep", "cluster_update", "dft_forward", "dft_inverse", "pair_jacobi",
                  "momentum_jacobi", "sign_gemm_real", "sign_gemm_complex"]
@@ -686,11 +686,22 @@ class Batch:
             _check(rc)
         return lb
 
-    def primal_energies(self):
+    def primal_energies(self, check=True):
         e = np.zeros(len(self.problems))
         f = np.zeros(len(self.problems))
-        _check(lib().vemb_batch_primal_energies(self.h, _ptr(e), _ptr(f)))
+        rc = lib().vemb_batch_primal_energies(self.h, _ptr(e), _ptr(f))
+        if check:
+            _check(rc)
         return e, f
+
+    def set_active(self, index, active=True):
+        """Mask (False) or unmask (True) one instance: a masked instance is skipped by later steps."""
+        _check(lib().vemb_batch_set_active(self.h, int(index), int(bool(active))))
+
+    def active(self):
+        a = (ctypes.c_int * len(self.problems))()
+        _check(lib().vemb_batch_get_active(self.h, a))
+        return [bool(x) for x in a]
 
     def set_profiling(self, every):
         """Time the kernels of every ``every``-th iteration (0 = off); resets the accumulated times."""
