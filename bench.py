@@ -235,13 +235,29 @@ def warm_start_leg(args):
     import synth
     from paper_2106_02682_amd import warmstart as ws
 
-    N, L = 64, 2
-    near = N // L // 2
-    train = synth.family_draws(args.warm_train, N, L, split=0)
-    held = synth.family_draws(args.warm_heldout, N, L, split=1)
+    from paper_2106_02682_amd import vemb
+
+    if args.warm_family == "cross":
+        # one network for rings of 32..512 sites and clusters of the sizes in --warm-ls (k = 2L an input);
+        # encodings of the `near` nearest distances exact and the rest averaged, so their size does not
+        # depend on N
+        near = args.warm_near
+        Ls = tuple(int(x) for x in args.warm_ls.split(","))
+        train = synth.cross_draws(args.warm_train, split=0, Ls=Ls)
+        held = synth.cross_draws(args.warm_heldout, split=1, Ls=Ls)
+        family = (f"TFI/XXZ rings, N ~ U{{32..512}}, clusters of {Ls} sites alternating, model, h, Jz from the "
+                  f"seeded draws; one network, encodings with {near} exact distances"
+                  + (", shorter targets zero-padded to the longest" if len(Ls) > 1 else ""))
+    else:
+        N, L = 64, 2
+        near = N // L // 2
+        train = synth.family_draws(args.warm_train, N, L, split=0)
+        held = synth.family_draws(args.warm_heldout, N, L, split=1)
+        family = f"TFI/XXZ ring N={N}, {L}-site clusters (M={N // L}); model, h, Jz from the seeded draws"
     t0 = time.perf_counter()
-    log(f"warm start: solving {len(train)} training draws for {args.warm_train_iters} iterations")
-    X, T = ws.converged_targets(train, args.warm_train_iters, near, log=log)
+    log(f"warm start: solving {len(train)} training draws for {args.warm_train_iters} iterations "
+        f"({args.warm_data_precision})")
+    X, T = ws.converged_targets(train, args.warm_train_iters, near, log=log, precision=args.warm_data_precision)
     t_data = time.perf_counter() - t0
     net = ws.make_network(T.shape[1], max_batch=max(64, args.warm_heldout))
     torch.cuda.synchronize()
@@ -254,7 +270,7 @@ def warm_start_leg(args):
     res = ws.compare(held, net, near, iters=args.warm_horizon, ref_iters=args.warm_ref, every=50, tol=1e-6, log=log)
     net.close()
     out = {
-        "family": f"TFI/XXZ ring N={N}, {L}-site clusters (M={N // L}); model, h, Jz from the seeded draws",
+        "family": family, "outputs": int(T.shape[1]), "train_data_precision": args.warm_data_precision,
         "train_instances": args.warm_train, "train_solver_iters": args.warm_train_iters,
         "train_steps": args.warm_steps, "final_train_loss": losses[-1][1], "data_seconds": t_data,
         "train_seconds": t_train, "heldout": args.warm_heldout, "horizon_iters": args.warm_horizon,
@@ -692,10 +708,10 @@ def main():
     ap.add_argument("--c2b-steps", type=int, default=500, help="timed steps of the c2b object")
     ap.add_argument("--h", type=float, default=1.0)
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
-    ap.add_argument("--workload", choices=["c4", "c2b", "dense", "tune", "profile"], default="c4",
+    ap.add_argument("--workload", choices=["c4", "c2b", "dense", "tune", "profile", "warm"], default="c4",
                     help="c4: the 64-instance batched sweep (default, with the c2b object); c2b: the N=384 ring alone; "
                          "dense: Algorithm 5 on a disordered ring; tune: the per-family parameter race; profile: a "
-                         "fixed run for rocprofv3")
+                         "fixed run for rocprofv3; warm: the learned warm-start leg alone")
     ap.add_argument("--profile-workload", choices=["c4", "c2b", "c3a", "c3b"], default="c4")
     ap.add_argument("--summarize-traffic", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
     ap.add_argument("--summarize-stats", nargs=4, metavar=("STATS_DIR", "TITLE", "COMMAND", "OUT_NAME"),
@@ -714,6 +730,12 @@ def main():
     ap.add_argument("--warm-heldout", type=int, default=16)
     ap.add_argument("--warm-horizon", type=int, default=30000)
     ap.add_argument("--warm-ref", type=int, default=60000)
+    ap.add_argument("--warm-family", choices=("ring64", "cross"), default="ring64",
+                    help="ring64: the N=64, 2-site family; cross: rings of 32..512 sites, 2- and 3-site clusters")
+    ap.add_argument("--warm-data-precision", choices=("fp64", "mixed"), default="fp64",
+                    help="precision of the solves that produce the training states")
+    ap.add_argument("--warm-ls", default="2,3", help="cluster sizes of the cross family")
+    ap.add_argument("--warm-near", type=int, default=3, help="exact distances of the cross family's encoding")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (this build has no multi-GPU path); got --gpus {args.gpus}",
@@ -750,6 +772,9 @@ def main():
         return
     if args.workload == "tune":
         print(json.dumps(tune_leg(args)), flush=True)
+        return
+    if args.workload == "warm":
+        print(json.dumps({"warm_start": warm_start_leg(args)}), flush=True)
         return
     if args.workload == "c4":
         out, _ = c4_leg(args)

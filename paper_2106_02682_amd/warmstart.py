@@ -42,15 +42,24 @@ def features(draws) -> np.ndarray:
     return np.stack([synth.mlp_features(d) for d in draws]).astype(np.float32)
 
 
-def converged_targets(draws, iters, near, chunk=64, log=None):
+def encoding_size(L, near):
+    """Warm-start encoding length of a ring with clusters of L sites (independent of the ring's size once
+    M > 2 near + 1), read from the library on a small ring."""
+    with vemb.Problem.from_workload(synth.tfi_ring((2 * near + 2) * L, L, 1.0)) as p:
+        return vemb.warm_size(p.h, near)
+
+
+def converged_targets(draws, iters, near, chunk=64, log=None, precision="fp64"):
     """Solve every draw for `iters` iterations (batched, graph-replayed) and encode its state
-    (`near` distances exact).  Returns (features, targets), targets a device float32 tensor."""
+    (`near` distances exact).  Returns (features, targets), targets a device float32 tensor whose rows
+    are the encodings, zero-padded to the longest one when the draws mix cluster sizes (each problem
+    decodes its own prefix)."""
     torch = _torch()
-    size = None
+    size = max(encoding_size(L, near) for L in sorted({d["L"] for d in draws}))
     rows = []
     for c0 in range(0, len(draws), chunk):
         part = draws[c0:c0 + chunk]
-        probs = open_problems(part)
+        probs = open_problems(part, precision)
         try:
             with vemb.Batch(probs) as b:
                 done = 0
@@ -62,13 +71,8 @@ def converged_targets(draws, iters, near, chunk=64, log=None):
                     if log:
                         log(f"training data: instances {c0}..{c0 + len(part) - 1}: {done}/{iters} iterations")
             for p in probs:
-                s = vemb.warm_size(p.h, near)
-                if size is None:
-                    size = s
-                if s != size:
-                    raise ValueError("all instances of a training set must share the cluster size")
-                v = torch.empty(s, dtype=torch.float32, device="cuda")
-                vemb.warm_encode(p.h, v, near)
+                v = torch.zeros(size, dtype=torch.float32, device="cuda")
+                vemb.warm_encode(p.h, v[:vemb.warm_size(p.h, near)], near)
                 rows.append(v)
             torch.cuda.synchronize()
         finally:
@@ -184,8 +188,8 @@ def compare(draws, net, near, iters, ref_iters, every=20, tol=1e-6, log=None):
         V = predict(net, Xh)
         torch.cuda.synchronize()
         t_pred = time.perf_counter() - t0
-        w_its, w_lbs, w_secs, w_es, w_fs = bound_trajectory(probs, iters, every,
-                                                            warm_vecs=[V[i] for i in range(len(probs))], near=near,
+        vecs = [V[i, :vemb.warm_size(p.h, near)] for i, p in enumerate(probs)]
+        w_its, w_lbs, w_secs, w_es, w_fs = bound_trajectory(probs, iters, every, warm_vecs=vecs, near=near,
                                                             log=log, tag="warm")
         w_secs = w_secs + t_pred
     finally:

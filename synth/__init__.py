@@ -249,6 +249,18 @@ def family_draws(count: int, N: int, L: int, split: int = 0) -> list:
     return out
 
 
+def cross_draws(count: int, split: int = 0, Ls=(2, 3)) -> list:
+    """Draws of the learned start's cross-size family: model, N ~ U{32..512}, h, J_z from the training
+    (split 0) / held-out (split 1) streams as in the batched sweep, clusters of L sites alternating over
+    Ls (one network for every ring size and cluster size, k = 2L an input)."""
+    out = []
+    for i in range(count):
+        d = draw_instance(np.random.default_rng([BASE_SEED, 5, split, i]))
+        d["L"] = Ls[i % len(Ls)]
+        out.append(d)
+    return out
+
+
 def mlp_init(dims, tag: int = 0) -> np.ndarray:
     """Initial parameters, flat FP32 in the layout W_0 (out x in, row-major), b_0, W_1, b_1, ...
     drawn uniform in +-1/sqrt(fan_in) from a seeded stream."""
