@@ -2,6 +2,8 @@
 
 * the printed "+ eps G" step diverges; with lb_every the watchdog stops vemb_step with
   VEMB_E_DIVERGED or VEMB_E_NUMERIC, while the ordinary iteration with the same setting runs on;
+* with a 3-sweep cap, warm-started iterations follow cold-started ones to 1e-10 on the 384-ring, and every
+  kept basis is orthonormal or the identity on the AFH 48-ring;
 * an eigensolve stopped by a (deliberately small) sweep cap is reported as VEMB_E_NOCONV and its kept
   eigenvectors are reset to the identity, so the next solve starts cold;
 * with torch's caching allocator installed (the binding's default on a GPU), every device allocation
@@ -58,6 +60,49 @@ def test_unconverged_solves_reset_their_eigenvectors(vemb):
         assert np.array_equal(V, np.broadcast_to(np.eye(n), V.shape))
         with pytest.raises(vemb.VembError):
             g.last_sweeps()
+
+
+def test_capped_warm_solves_match_cold_solves(vemb):
+    """A sweep cap of 3 stops every solve of the 384-ring's dense 64 x 64 blocks unconverged; they keep
+    the identity instead of a non-orthonormal basis, so the warm-started iterations follow the always-cold
+    ones (warm_refresh < 0) to 1e-10 instead of drifting with an unconverged basis."""
+    w = synth.tfi_ring(384, 3, 1.0)
+    out = {}
+    for refresh in (64, -1):
+        with vemb.Problem.from_workload(w, max_sweeps=3, warm_refresh=refresh) as g:
+            g.step(20)
+            out[refresh] = g.get_state()
+    keys = ("X", "rho0", "rho", "rho_t", "Lam", "Lam1", "Lam2")
+    errs = {k: float(np.abs(out[64][k] - out[-1][k]).max() / max(1.0, np.abs(out[-1][k]).max())) for k in keys}
+    print(f"warm vs cold with a 3-sweep cap {errs}")
+    assert max(errs.values()) <= 1e-10
+
+
+def test_capped_solves_keep_orthonormal_bases(vemb):
+    """Where some solves do converge within a 3-sweep cap from a warm start (the degenerate spectra of the
+    AFH 48-ring with 3-site clusters), warm and cold runs differ by the cold run's truncation (4e-3 after
+    20 iterations), so the property checked is the kept bases themselves: after every iteration each
+    kept pair and momentum basis is orthonormal (a converged solve) or exactly the identity (an
+    unconverged one)."""
+    w = synth.xxz_ring(48, 3, 1.0)
+    with vemb.Problem.from_workload(w, max_sweeps=3) as g:
+        n, k = g.info["n"], g.info["n_op"]
+        ident = converged = 0
+        for _ in range(20):
+            g.step(1)
+            st = g.get_state(with_eigvecs=True)
+            Vp = st["Vpair"].reshape(-1, n, n)
+            Vm = st["Vmom"].reshape(-1, k, k, 2)
+            Vm = Vm[..., 0] + 1j * Vm[..., 1]
+            for V in list(Vp) + list(Vm):
+                if np.array_equal(V, np.eye(V.shape[0])):
+                    ident += 1
+                    continue
+                converged += 1
+                err = np.abs(V.conj().T @ V - np.eye(V.shape[0])).max()
+                assert err <= 1e-9, err
+    print(f"kept bases: {ident} identities, {converged} orthonormal")
+    assert ident > 0 and converged > 0
 
 
 def _run_all(vemb):
