@@ -267,10 +267,12 @@ def warm_start_leg(args):
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
     log(f"warm start: {len(held)} held-out draws, cold {args.warm_ref} / warm {args.warm_horizon} iterations")
-    res = ws.compare(held, net, near, iters=args.warm_horizon, ref_iters=args.warm_ref, every=50, tol=1e-6, log=log)
+    res = ws.compare(held, net, near, iters=args.warm_horizon, ref_iters=args.warm_ref, every=50, tol=1e-6, log=log,
+                     far_cold=bool(args.warm_far_cold))
     net.close()
     out = {
         "family": family, "outputs": int(T.shape[1]), "train_data_precision": args.warm_data_precision,
+        "far_offsets": "cold" if args.warm_far_cold else "far slot",
         "train_instances": args.warm_train, "train_solver_iters": args.warm_train_iters,
         "train_steps": args.warm_steps, "final_train_loss": losses[-1][1], "data_seconds": t_data,
         "train_seconds": t_train, "heldout": args.warm_heldout, "horizon_iters": args.warm_horizon,
@@ -736,6 +738,8 @@ def main():
                     help="precision of the solves that produce the training states")
     ap.add_argument("--warm-ls", default="2,3", help="cluster sizes of the cross family")
     ap.add_argument("--warm-near", type=int, default=3, help="exact distances of the cross family's encoding")
+    ap.add_argument("--warm-far-cold", type=int, default=0,
+                    help="1: the warm start's offsets beyond the exact distances start cold (else the far slot)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (this build has no multi-GPU path); got --gpus {args.gpus}",

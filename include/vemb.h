@@ -533,6 +533,9 @@ int vemb_warm_encode(vemb_problem* p, int near, float* vec);
  * blocks (FP64).  Resets the iteration count (eigensolves restart cold).
  * Asynchronous. */
 int vemb_warm_start(vemb_problem* p, int near, const float* vec);
+/* As vemb_warm_start; far_cold = 1 starts the offsets at distances above `near` cold instead of from the
+ * far slot (X_0d = 0, multipliers 0, rho~_d = rho_d = I/n: Section 4's start), the far slot unused. */
+int vemb_warm_start_ex(vemb_problem* p, int near, const float* vec, int far_cold);
 
 /* Network: dims[0] inputs, dims[1..n_dims-2] silu hidden layers, dims[n_dims-1]
  * outputs.  Parameters flat FP32 in the order W_0 (dims[1] x dims[0], row-major),

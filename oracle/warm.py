@@ -107,7 +107,10 @@ def _unit_trace(a):
     return a + (1.0 - np.trace(a)) / k * np.eye(k)
 
 
-def decode(p: Problem, vec, near: int = NEAR) -> State:
+def decode(p: Problem, vec, near: int = NEAR, far_cold: bool = False) -> State:
+    """State from a vector (the inverse of encode for near >= M/2).  far_cold: the offsets at distances
+    above `near` take the cold start of Section 4 (X_0d = 0, multipliers 0, rho~_d = I/n) instead of
+    the far slot."""
     if p.My != 1:
         raise ValueError("the warm-start encoding covers rings (one-dimensional cluster lattices)")
     if near < 1:
@@ -116,9 +119,11 @@ def decode(p: Problem, vec, near: int = NEAR) -> State:
     X00, rho0, blocks = _block_views(p, vec, near)
     M, P = p.M, p.P
     raw = {}
+    cold = (np.zeros((p.n_op, p.n_op)), np.zeros((p.n, p.n)), np.zeros((p.m, p.m)), np.zeros((p.m, p.m)),
+            np.eye(p.n) / p.n)
     for d in range(1, M):
         direction, slot = slot_of(d, M, near)
-        raw[d] = blocks[direction * (near + 1) + slot]
+        raw[d] = cold if (far_cold and slot == near) else blocks[direction * (near + 1) + slot]
     Xp = np.zeros((M, p.n_op, p.n_op))
     Xp[0] = _sym(X00)
     for d in range(1, M):

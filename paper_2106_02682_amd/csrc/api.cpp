@@ -633,10 +633,12 @@ int vemb_warm_encode(vemb_problem* p, int near, float* vec) {
   return hip_rc(launch_warm_encode(p->a, near, vec, p->stream), "warm-start encode");
 }
 
-int vemb_warm_start(vemb_problem* p, int near, const float* vec) {
+int vemb_warm_start(vemb_problem* p, int near, const float* vec) { return vemb_warm_start_ex(p, near, vec, 0); }
+
+int vemb_warm_start_ex(vemb_problem* p, int near, const float* vec, int far_cold) {
   if (!p || !vec || near < 1) return fail(VEMB_E_INVALID, "bad arguments to vemb_warm_start");
   VEMB_TRY(check_ring(p));
-  VEMB_TRY(hip_rc(launch_warm_decode(p->a, near, vec, p->stream), "warm-start decode"));
+  VEMB_TRY(hip_rc(launch_warm_decode(p->a, near, vec, p->stream, far_cold), "warm-start decode"));
   VEMB_TRY(project_x(p));
   p->t = 0;
   p->v_valid = false;

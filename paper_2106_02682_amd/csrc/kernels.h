@@ -150,6 +150,7 @@ hipError_t launch_bound_build(const StepArgs& a, hipStream_t st);
 // `near` distances have blocks of their own, larger distances share a 'far' block.
 struct WarmLayout {
   int near;
+  int far_cold;  // decode: offsets beyond `near` take the cold start instead of the far slot
   long x00, rho0, block0, bsz, total;  // offsets / sizes in floats
   long oX, oL, oL1, oL2, oR;           // parts of a block
 };
@@ -157,6 +158,7 @@ WarmLayout warm_layout(const StepArgs& a, int near);
 // vec (device, warm_layout(a, near).total floats) <- state; needs M >= near + 1.
 hipError_t launch_warm_encode(const StepArgs& a, int near, float* vec, hipStream_t st);
 // State <- vec: X' (in Xp, to be projected), rho0, rho~ = rho, Lambda, Lambda1, Lambda2.
-hipError_t launch_warm_decode(const StepArgs& a, int near, const float* vec, hipStream_t st);
+// far_cold: offsets at distances above `near` start cold (X_0d = 0, multipliers 0, rho~ = I/n).
+hipError_t launch_warm_decode(const StepArgs& a, int near, const float* vec, hipStream_t st, int far_cold = 0);
 
 }  // namespace vemb

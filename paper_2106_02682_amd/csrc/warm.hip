@@ -12,7 +12,8 @@
 // every offset from its slot, symmetrises (X_0,M-d = X_0d^T, so X is symmetric),
 // fixes Tr rho_0 = 1 and leaves X' in the X-step buffer; the caller then projects
 // X onto the PSD cone through its momentum blocks, so the Lagrangian bound at the
-// decoded point is valid.
+// decoded point is valid.  With far_cold the offsets beyond `near` take Section 4's cold start instead
+// (X_0d = 0, multipliers 0, rho~_d = rho_d = I/n), the far slot unused.
 #include "kernels.h"
 
 namespace vemb {
@@ -98,6 +99,21 @@ __global__ void __launch_bounds__(256) warm_decode_kernel(StepArgs A, WarmLayout
   int dir, slot, dir2, slot2;
   slot_of(d, M, w.near, dir, slot);
   slot_of(M - d, M, w.near, dir2, slot2);
+  if (w.far_cold && slot == w.near) {  // a far offset (d and M - d lie at the same distance)
+    for (long e = threadIdx.x; e < nop2; e += 256) A.Xp[d * nop2 + e] = 0.0;
+    for (long e = threadIdx.x; e < n2; e += 256) {
+      const long i = e / n, j = e - i * n;
+      const double rt = i == j ? 1.0 / n : 0.0;
+      A.Lam[(d - 1) * n2 + e] = 0.0;
+      A.rho_t[(d - 1) * n2 + e] = rt;
+      A.rho[(d - 1) * n2 + e] = rt;
+    }
+    for (long e = threadIdx.x; e < m2; e += 256) {
+      A.Lam1[(d - 1) * m2 + e] = 0.0;
+      A.Lam2[(d - 1) * m2 + e] = 0.0;
+    }
+    return;
+  }
   const float* P = vec + block_base(w, dir, slot);
   const float* Q = vec + block_base(w, dir2, slot2);
   for (long e = threadIdx.x; e < nop2; e += 256) {  // X_0d = (P_d + P_{M-d}^T) / 2
@@ -143,8 +159,10 @@ hipError_t launch_warm_encode(const StepArgs& a, int near, float* vec, hipStream
   return hipGetLastError();
 }
 
-hipError_t launch_warm_decode(const StepArgs& a, int near, const float* vec, hipStream_t st) {
-  hipLaunchKernelGGL(warm_decode_kernel, dim3(a.M), dim3(256), 0, st, a, warm_layout(a, near), vec);
+hipError_t launch_warm_decode(const StepArgs& a, int near, const float* vec, hipStream_t st, int far_cold) {
+  WarmLayout w = warm_layout(a, near);
+  w.far_cold = far_cold ? 1 : 0;
+  hipLaunchKernelGGL(warm_decode_kernel, dim3(a.M), dim3(256), 0, st, a, w, vec);
   return hipGetLastError();
 }
 

@@ -40,6 +40,7 @@ EXPORTS = [
     "vemb_set_profiling_every", "vemb_psd_project_sign_noalloc", "vemb_batch_set_profiling",
     "vemb_batch_get_profile", "vemb_tile_map", "vemb_set_allocator", "vemb_divergence_check",
     "vemb_penalties", "vemb_set_penalty_scale", "vemb_batch_set_active", "vemb_batch_get_active",
+    "vemb_warm_start_ex",
 ]
 BATCH_KERNELS = ["pair_update", "pair_xstep", "cluster_update", "dft_forward", "dft_inverse", "pair_jacobi",
                  "momentum_jacobi", "sign_gemm_real", "sign_gemm_complex"]
@@ -762,8 +763,12 @@ def warm_encode(h, out, near=WARM_NEAR):
     _check(lib().vemb_warm_encode(h, int(near), _dev(out)))
 
 
-def warm_start(h, vec, near=WARM_NEAR):
-    """vec: device float32 tensor of warm_size(h, near) elements."""
+def warm_start(h, vec, near=WARM_NEAR, far_cold=False):
+    """vec: device float32 tensor of warm_size(h, near) elements; far_cold starts the offsets beyond
+    `near` cold instead of from the far slot."""
+    if far_cold:
+        _check(lib().vemb_warm_start_ex(h, int(near), _dev(vec), 1))
+        return
     _check(lib().vemb_warm_start(h, int(near), _dev(vec)))
 
 

@@ -116,7 +116,7 @@ def predict(net, X):
     return Y
 
 
-def bound_trajectory(probs, iters, every, warm_vecs=None, near=None, log=None, tag=""):
+def bound_trajectory(probs, iters, every, warm_vecs=None, near=None, log=None, tag="", far_cold=False):
     """Step a batch of problems `iters` iterations, reading the bounds, energies and feasibility errors
     every `every`.  Returns (its, lbs[len(its), count], secs[len(its)], es, fs) with wall-clock seconds
     since the start (the start includes decoding the warm vectors, if given; the energies are read after
@@ -126,7 +126,7 @@ def bound_trajectory(probs, iters, every, warm_vecs=None, near=None, log=None, t
     t0 = time.perf_counter()
     if warm_vecs is not None:
         for p, v in zip(probs, warm_vecs):
-            vemb.warm_start(p.h, v, near)
+            vemb.warm_start(p.h, v, near, far_cold=far_cold)
     its, lbs, secs, es, fs = [], [], [], [], []
     with vemb.Batch(probs) as b:
         done = 0
@@ -171,8 +171,9 @@ def first_converged(its, lbs, secs, lb_ref, tol):
     return out
 
 
-def compare(draws, net, near, iters, ref_iters, every=20, tol=1e-6, log=None):
-    """Cold reference run (ref_iters) and warm run (iters) on the same instances."""
+def compare(draws, net, near, iters, ref_iters, every=20, tol=1e-6, log=None, far_cold=False):
+    """Cold reference run (ref_iters) and warm run (iters) on the same instances; far_cold starts the
+    warm run's offsets beyond `near` cold."""
     torch = _torch()
     probs = open_problems(draws)
     try:
@@ -190,7 +191,7 @@ def compare(draws, net, near, iters, ref_iters, every=20, tol=1e-6, log=None):
         t_pred = time.perf_counter() - t0
         vecs = [V[i, :vemb.warm_size(p.h, near)] for i, p in enumerate(probs)]
         w_its, w_lbs, w_secs, w_es, w_fs = bound_trajectory(probs, iters, every, warm_vecs=vecs, near=near,
-                                                            log=log, tag="warm")
+                                                            log=log, tag="warm", far_cold=far_cold)
         w_secs = w_secs + t_pred
     finally:
         for p in probs:

@@ -138,17 +138,19 @@ def test_encode_matches_oracle(vemb, N, near):
     assert np.abs(got - want).max() <= 1e-6 * np.abs(want).max()
 
 
-@pytest.mark.parametrize("N,L,near", [(16, 2, 3), (22, 2, 3), (32, 2, 3), (24, 3, 3), (22, 2, 5), (32, 2, 8)])
-def test_decode_matches_oracle(vemb, N, L, near):
+@pytest.mark.parametrize("N,L,near,far_cold", [(16, 2, 3, False), (22, 2, 3, False), (32, 2, 3, False),
+                                                (24, 3, 3, False), (22, 2, 5, False), (32, 2, 8, False),
+                                                (32, 2, 3, True), (24, 3, 2, True), (22, 2, 5, True)])
+def test_decode_matches_oracle(vemb, N, L, near, far_cold):
     w = synth.tfi_ring(N, L, 1.0)
     p = alg6.Problem.from_workload(w)
     vec = (np.random.default_rng([synth.BASE_SEED, 16, N, L]).standard_normal(warm.sizes(p, near)[0]) * 0.2)
     vec = vec.astype(np.float32)
     with vemb.Problem.from_workload(w) as g:
-        vemb.warm_start(g.h, torch.from_numpy(vec).cuda(), near)
+        vemb.warm_start(g.h, torch.from_numpy(vec).cuda(), near, far_cold=far_cold)
         st = g.get_state()
         lb = g.dual_bound()
-    s = warm.decode(p, vec.astype(np.float64), near)
+    s = warm.decode(p, vec.astype(np.float64), near, far_cold=far_cold)
     for k in ("X", "rho0", "rho_t", "rho", "Lam", "Lam1", "Lam2"):
         err = np.abs(st[k] - getattr(s, k)).max() / max(np.abs(getattr(s, k)).max(), 1e-30)
         assert err < 1e-10, (k, err)

@@ -81,3 +81,32 @@ def test_bound_at_decoded_random_point_is_below_ground_energy():
     for seed in range(3):
         s = warm.decode(p, _random_vec(p, 100 + seed))
         assert alg6.lower_bound(p, s) <= e0 + 1e-12
+
+
+def test_far_offsets_start_cold():
+    """decode(far_cold=True): offsets at distances up to `near` keep their slots exactly as the plain decode
+    gives them, every farther offset is Section 4's cold start (multipliers 0, rho~ = I/n, X' block 0 before
+    the projection), the projected X is PSD, and with no far offsets (near >= M/2) nothing changes."""
+    w = synth.tfi_ring(32, 2, 1.1)  # M = 16 clusters
+    p = alg6.Problem.from_workload(w)
+    s, _ = alg6.solve(p, 40)
+    near = 3
+    vec = warm.encode(p, s, near)
+    plain = warm.decode(p, vec, near)
+    cold = warm.decode(p, vec, near, far_cold=True)
+    cold0 = alg6.initial_state(p)
+    M = p.M
+    for d in range(1, M):
+        r = min(d, M - d)
+        if r <= near:
+            for k in ("Lam", "Lam1", "Lam2", "rho_t"):
+                assert np.array_equal(getattr(cold, k)[d - 1], getattr(plain, k)[d - 1]), (d, k)
+        else:
+            for k in ("Lam", "Lam1", "Lam2", "rho_t", "rho"):
+                assert np.array_equal(getattr(cold, k)[d - 1], getattr(cold0, k)[d - 1]), (d, k)
+    assert alg6.min_momentum_eig(p, cold) >= -1e-12
+    full = M // 2
+    vec_full = warm.encode(p, s, full)
+    a, b = warm.decode(p, vec_full, full), warm.decode(p, vec_full, full, far_cold=True)
+    for k in ("X", "rho0", "rho_t", "Lam", "Lam1", "Lam2"):
+        assert np.array_equal(getattr(a, k), getattr(b, k)), k
