@@ -20,6 +20,10 @@ Contents
              pin the translation-invariant reduction.
 ``exact``    exact diagonalisation and the Jordan-Wigner closed form.
 ``mlp``      FP64 forward/backward of the warm-start network (gradient pin).
+``warm``     the warm-start state encoding and decoding.
+``adapt``    Algorithm 6 with the joint scale of (mu, nu, eps) adapted during
+             the run (Section 4's remark on tuning them).
+``fermion``  Jordan-Wigner operators and Hamiltonians of spinless fermions.
 
 Readings of the paper that the oracle fixes are listed in the header of
 ``alg6``; every function cites the passage it follows.
