@@ -44,7 +44,7 @@ constexpr int kSliceCols = 16;
 hipError_t launch_lambda_min_slice(const double* K, double* x, double* sigma, double* lmin, int* flags, int* nflag,
                                    int n, int count, void* work, hipStream_t st, int precision);
 
-// Kernel launches of one sign-function projection (load, the products, store) in a precision.
+// Kernel launches of one sign-function projection (load, scale, the products, store, finish) in a precision.
 int sign_launches(int precision);
 
 // Real flops of one product launch over `count` blocks of size n: the upper-triangle 64 x 64 tiles

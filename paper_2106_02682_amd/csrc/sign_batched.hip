@@ -12,6 +12,8 @@
 // these kernels.  Products of Hermitian polynomials in A are Hermitian; each is written exactly
 // Hermitian (tile and conjugate mirror, symmetrised diagonal tiles), because the products read
 // P(i, k) as conj(P(k, i)).
+#include <algorithm>
+
 #include "jacobi_common.h"
 #include "mfma_tile.h"
 #include "polar.h"
@@ -30,25 +32,29 @@ template <typename R> __device__ inline cplx<R> herm_part(cplx<R> a, cplx<R> at)
 template <typename R> __device__ inline R scale_s(double s, R a) { return R(s) * a; }
 template <typename R> __device__ inline cplx<R> scale_s(double s, cplx<R> a) { return {R(s) * a.re, R(s) * a.im}; }
 
-// Per block: A = Hermitian part of the policy's input, X = A / (1.01 ||A||_F).  One workgroup per block.
-// The input is read as pairs of 32 x 32 tiles, (i-range, j-range) and its transpose position, each with
-// row-wise (coalesced) reads staged in LDS, so the transposed entry that the Hermitian part needs costs
-// no cache line of its own (entry-wise column reads fetched 17x the block's bytes from HBM); A's tile and
-// its conjugate mirror are written row by row.  The scaling pass visits the entries in the same
-// thread-to-entry order, so each thread reads back only its own stores.
+// A = Hermitian part of the policy's input, X = A / (1.01 ||A||_F), over `parts` workgroups per block
+// (blockIdx.y; one for batches of many blocks, more for a single problem's few blocks, so that the
+// chip is filled).  The input is read as pairs of 32 x 32 tiles, (i-range, j-range) and its transpose
+// position, each with row-wise (coalesced) reads staged in LDS, so the transposed entry that the
+// Hermitian part needs costs no cache line of its own (entry-wise column reads fetched 17x the block's
+// bytes from HBM); A's tile and its conjugate mirror are written row by row.  Workgroup g of a block
+// takes the tile pairs g, g + parts, ... and leaves its share of ||A||_F^2 in the block's T slot (free
+// until the products); sign_scale_kernel then sums the shares in order and writes X.
+constexpr int kLoadTile = 32;
+
 template <typename S, typename Policy>
 __global__ void __launch_bounds__(kSignThreads) sign_load_kernel(Policy pol, int n, S* work) {
-  constexpr int TB = 32, LDT = TB + 1, TT = TB * TB;
-  const int mat = blockIdx.x, tid = threadIdx.x;
+  constexpr int TB = kLoadTile, LDT = TB + 1, TT = TB * TB;
+  const int mat = blockIdx.x, part = blockIdx.y, parts = gridDim.y, tid = threadIdx.x;
   if (!policy_active(pol, mat)) return;  // a masked batch instance: its products run on stale data, unused
   const size_t nn = (size_t)n * n;
   S* A = work + (size_t)mat * 4 * nn;
-  S* X = A + nn;
+  double* share = reinterpret_cast<double*>(A + 3 * nn);  // the T slot
   __shared__ S t1[TB * LDT], t2[TB * LDT];
   __shared__ double red[kSignThreads];
   const int tiles = n / TB, pairs = upper_tile_count(tiles);
   double acc = 0.0;
-  for (int idx = 0; idx < pairs; ++idx) {
+  for (int idx = part; idx < pairs; idx += parts) {
     int ti = 0, tj = 0;
     upper_tile(idx, tiles, &ti, &tj);
     const int i0 = ti * TB, j0 = tj * TB;
@@ -72,10 +78,26 @@ __global__ void __launch_bounds__(kSignThreads) sign_load_kernel(Policy pol, int
     __syncthreads();
   }
   const double s2 = block_sum(acc, red);
-  // a squared norm that overflows (entries beyond ~1e150: a diverged iterate) scales by NaN, so the
-  // failure shows in every result instead of a silently wrong projection (a zero scale)
+  if (tid == 0) share[part] = s2;
+}
+
+// X = A / (1.01 ||A||_F) over the same workgroups and tile pairs as sign_load_kernel, the norm from its
+// shares summed in workgroup order.  A squared norm that overflows (entries beyond ~1e150: a diverged
+// iterate) scales by NaN, so the failure shows in every result instead of a silently wrong projection.
+template <typename S, typename Policy>
+__global__ void __launch_bounds__(kSignThreads) sign_scale_kernel(Policy pol, int n, S* work) {
+  constexpr int TB = kLoadTile, TT = TB * TB;
+  const int mat = blockIdx.x, part = blockIdx.y, parts = gridDim.y, tid = threadIdx.x;
+  if (!policy_active(pol, mat)) return;
+  const size_t nn = (size_t)n * n;
+  S* A = work + (size_t)mat * 4 * nn;
+  S* X = A + nn;
+  const double* share = reinterpret_cast<const double*>(A + 3 * nn);
+  double s2 = 0.0;
+  for (int g = 0; g < parts; ++g) s2 += share[g];
   const double inv = s2 > 0.0 ? (s2 < INFINITY ? 1.0 / (1.01 * sqrt(s2)) : NAN) : 1.0;
-  for (int idx = 0; idx < pairs; ++idx) {
+  const int tiles = n / TB, pairs = upper_tile_count(tiles);
+  for (int idx = part; idx < pairs; idx += parts) {
     int ti = 0, tj = 0;
     upper_tile(idx, tiles, &ti, &tj);
     const int i0 = ti * TB, j0 = tj * TB;
@@ -208,24 +230,40 @@ __global__ void __launch_bounds__(GemmShape<S>::NT) sign_gemm_kernel(S* work, in
   }
 }
 
-// Per block: Pi(A) (at offset pi_off of the block's work area) through the policy's store;
-// feasibility and the step count recorded.
+// Pi(A) (at offset pi_off of the block's work area) through the policy's store, over `parts` workgroups
+// per block (blockIdx.y, contiguous ranges of rows); each leaves its share of ||rho - rho~||^2 in the
+// block's X slot (free after the last product), and sign_finish_kernel sums the shares in order.
 template <typename S, typename Policy>
-__global__ void __launch_bounds__(kSignThreads) sign_store_kernel(Policy pol, int n, const S* work, int pi_off,
-                                                                  int steps) {
-  const int mat = blockIdx.x;
+__global__ void __launch_bounds__(kSignThreads) sign_store_kernel(Policy pol, int n, S* work, int pi_off) {
+  const int mat = blockIdx.x, part = blockIdx.y, parts = gridDim.y;
   if (!policy_active(pol, mat)) return;
   const size_t nn = (size_t)n * n;
-  const S* Pi = work + (size_t)mat * 4 * nn + pi_off;
+  S* base = work + (size_t)mat * 4 * nn;
+  const S* Pi = base + pi_off;
+  double* share = reinterpret_cast<double*>(base + nn);  // the X slot
   __shared__ double red[kSignThreads];
-  double part = 0.0;
-  for (size_t e = threadIdx.x; e < nn; e += kSignThreads) part += pol.store(mat, (int)(e / n), (int)(e % n), Pi[e]);
-  const double tot = block_sum(part, red);
-  if (threadIdx.x == 0) {
-    pol.finish(mat, tot);
-    pol.record_sweeps(mat, steps);
-  }
+  const size_t e0 = nn * part / parts, e1 = nn * (part + 1) / parts;
+  double acc = 0.0;
+  for (size_t e = e0 + threadIdx.x; e < e1; e += kSignThreads) acc += pol.store(mat, (int)(e / n), (int)(e % n), Pi[e]);
+  const double tot = block_sum(acc, red);
+  if (threadIdx.x == 0) share[part] = tot;
 }
+
+template <typename S, typename Policy>
+__global__ void __launch_bounds__(64) sign_finish_kernel(Policy pol, int n, const S* work, int parts, int steps,
+                                                         int count) {
+  const int mat = blockIdx.x * 64 + threadIdx.x;
+  if (mat >= count || !policy_active(pol, mat)) return;
+  const size_t nn = (size_t)n * n;
+  const double* share = reinterpret_cast<const double*>(work + (size_t)mat * 4 * nn + nn);
+  double tot = 0.0;
+  for (int g = 0; g < parts; ++g) tot += share[g];
+  pol.finish(mat, tot);
+  pol.record_sweeps(mat, steps);
+}
+
+// Workgroups per block of the load, scale and store passes: enough to give the chip ~512 workgroups.
+inline int pass_parts(int count) { return std::max(1, std::min(8, (512 + count - 1) / count)); }
 
 template <typename S>
 void gemm(S* work, int n, int count, int p, int q, int e, int o, double c0, double c1, hipStream_t st,
@@ -250,7 +288,9 @@ hipError_t sign_function(const Policy& pol, int n, int count, S* work, hipStream
   const int nn = n * n;
   const int Y = 2 * nn;
   int X = nn, T = 3 * nn;
-  hipLaunchKernelGGL((sign_load_kernel<S, Policy>), dim3(count), dim3(kSignThreads), 0, st, pol, n, work);
+  const int parts = pass_parts(count);
+  hipLaunchKernelGGL((sign_load_kernel<S, Policy>), dim3(count, parts), dim3(kSignThreads), 0, st, pol, n, work);
+  hipLaunchKernelGGL((sign_scale_kernel<S, Policy>), dim3(count, parts), dim3(kSignThreads), 0, st, pol, n, work);
   for (double a : sched) {
     gemm<S>(work, n, count, X, X, -1, Y, 0.0, 1.0, st, hook);
     gemm<S>(work, n, count, X, Y, X, T, 1.5 * a, -0.5 * a * a * a, st, hook);
@@ -272,7 +312,10 @@ hipError_t sign_project(const Policy& pol, int n, int count, void* work_raw, hip
   const int A = 0, Y = 2 * n * n;
   // Pi(A) = (A + A S) / 2 into the slot of X^2, free after the last step
   gemm<S>(work, n, count, A, X, A, Y, 0.5, 0.5, st, hook);
-  hipLaunchKernelGGL((sign_store_kernel<S, Policy>), dim3(count), dim3(kSignThreads), 0, st, pol, n, work, Y, steps);
+  const int parts = pass_parts(count);
+  hipLaunchKernelGGL((sign_store_kernel<S, Policy>), dim3(count, parts), dim3(kSignThreads), 0, st, pol, n, work, Y);
+  hipLaunchKernelGGL((sign_finish_kernel<S, Policy>), dim3((count + 63) / 64), dim3(64), 0, st, pol, n, work, parts,
+                     steps, count);
   return hipGetLastError();
 }
 
@@ -571,7 +614,7 @@ hipError_t slice_pass(const double* K, double* x, double* sigma, double* lmin, i
 int sign_launches(int precision) {
   const double l0 = precision == VEMB_FP64 ? kNsResolved : kNsResolved32;
   const double stop = precision == VEMB_FP64 ? kNsStop : kNsStop32;
-  return 2 * (int)ns_schedule(l0, stop).size() + 3;
+  return 2 * (int)ns_schedule(l0, stop).size() + 5;  // load, scale, the products, Pi, store, finish
 }
 
 hipError_t launch_pair_projection_sign(const double* rho, double* Lam, double* rho_t, double* feas, int n, int P,
