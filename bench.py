@@ -46,6 +46,7 @@ KERNEL_SOURCES = {
     "momentum_jacobi": ("jacobi.hip", "jacobi_common.h"),
     "sign_gemm_real": ("sign_batched.hip", "mfma_tile.h"), "sign_gemm_complex": ("sign_batched.hip", "mfma_tile.h"),
     "sign_load_real": ("sign_batched.hip",), "sign_load_complex": ("sign_batched.hip",),
+    "sign_scale_real": ("sign_batched.hip",), "sign_scale_complex": ("sign_batched.hip",),
     "sign_store_real": ("sign_batched.hip",), "sign_store_complex": ("sign_batched.hip",),
     "pair_update": ("step_kernels.hip",), "pair_xstep": ("step_kernels.hip",), "cluster_update": ("step_kernels.hip",),
     "dft_forward": ("step_kernels.hip", "mfma_tile.h"), "dft_inverse": ("step_kernels.hip", "mfma_tile.h"),
@@ -504,6 +505,7 @@ TRAFFIC_KERNELS = [
     ("dft_inverse", r"dft_mfma_kernel<false>|dft_inverse_batched"),
     ("sign_gemm_real", r"sign_gemm_kernel<double>"), ("sign_gemm_complex", r"sign_gemm_kernel<vemb::cplx<double> >"),
     ("sign_load_real", r"sign_load_kernel<double,"), ("sign_load_complex", r"sign_load_kernel<vemb::cplx<double>,"),
+    ("sign_scale_real", r"sign_scale_kernel<double,"), ("sign_scale_complex", r"sign_scale_kernel<vemb::cplx<double>,"),
     ("sign_store_real", r"sign_store_kernel<double,"), ("sign_store_complex", r"sign_store_kernel<vemb::cplx<double>,"),
     ("pair_jacobi", r"jacobi_kernel<double, \d+, 0, true, \d+, vemb::\(anonymous namespace\)::BatchedPairPolicy"),
     ("momentum_jacobi", r"jacobi_kernel<vemb::cplx<double>, \d+, 0, true, \d+, vemb::\(anonymous namespace\)::BatchedMomentumPolicy"),
