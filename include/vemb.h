@@ -540,7 +540,9 @@ int vemb_warm_start_ex(vemb_problem* p, int near, const float* vec, int far_cold
 /* Network: dims[0] inputs, dims[1..n_dims-2] silu hidden layers, dims[n_dims-1]
  * outputs.  Parameters flat FP32 in the order W_0 (dims[1] x dims[0], row-major),
  * b_0, W_1, b_1, ...; the passes read the weights rounded to bfloat16 (nearest
- * even) and compute in FP32.  Targets are learned normalised per output,
+ * even) and multiply on the BF16 matrix cores with FP32 accumulation, FP32
+ * activations and gradients entering as exact sums of three bfloat16 terms (the
+ * accuracy of an FP32 product).  Targets are learned normalised per output,
  * t_hat = (t - mean) / std; the loss is the mean of (y - t_hat)^2 over batch and
  * outputs; Adam (b1 0.9, b2 0.999, eps 1e-8) updates the FP32 parameters.
  * All x / y / target / row arrays below are DEVICE pointers, row-major. */

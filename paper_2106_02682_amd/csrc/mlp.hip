@@ -2,12 +2,16 @@
 // hidden layers, trained by Adam on normalised targets.
 //
 // Weights live in FP32 (master copy, Adam moments) and are read by the passes as
-// bfloat16 (round to nearest even), halving their footprint; activations,
-// products and accumulation are FP32.  Every product is one tiled matrix-core
-// GEMM (v_mfma_f32_16x16x4_f32: a bf16 operand widens exactly to FP32), with the
-// bias, silu and silu' factors fused into the epilogue:
-//   forward   Z_l = A_{l-1} W_l^T + b_l,  A_l = silu(Z_l)
-//   backward  dW_l = dZ_l^T A_{l-1},  dZ_{l-1} = (dZ_l W_l) * silu'(Z_{l-1})
+// bfloat16 (round to nearest even), halving their footprint; activations and
+// gradients are FP32 and every product accumulates in FP32.  Every product is one
+// tiled GEMM on the BF16 matrix cores (v_mfma_f32_16x16x16_bf16): an FP32 operand
+// enters as the exact sum of three bfloat16 terms (x = h + m + l; each remainder
+// after rounding to the nearest bfloat16 is exact in FP32 and has at most 16, then
+// 8, significant bits), a bfloat16 weight as itself.  Each term product is exact in
+// FP32; against bfloat16 weights the three term products give the FP32 operand's
+// product exactly, and between two FP32 operands the six term products of order
+// up to 2^-16 are taken (the three dropped ones are below 2^-23 of the product).
+// The bias, silu and silu' factors are fused into the epilogue:
 #include <algorithm>
 
 #include "mlp.h"
@@ -17,6 +21,7 @@ namespace {
 
 constexpr int BM = 64, BN = 64, BK = 16, GT = 256;
 typedef float f4 __attribute__((ext_vector_type(4)));
+typedef short s4 __attribute__((ext_vector_type(4)));
 
 __device__ inline float bf16_to_f32(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
@@ -30,6 +35,22 @@ __device__ inline uint16_t f32_to_bf16(float f) {
 __device__ inline float load_b(const float* p, long i) { return p[i]; }
 __device__ inline float load_b(const uint16_t* p, long i) { return bf16_to_f32(p[i]); }
 
+// x = t[0] + t[1] + t[2] exactly (finite x whose rounding stays finite); a non-finite
+// leading term carries x alone.
+__device__ inline void split3(float x, short t[3]) {
+  const uint16_t h = f32_to_bf16(x);
+  const float fh = bf16_to_f32(h);
+  t[0] = (short)h;
+  if (!isfinite(fh)) {
+    t[1] = t[2] = 0;
+    return;
+  }
+  const float r1 = x - fh;
+  const uint16_t m = f32_to_bf16(r1);
+  t[1] = (short)m;
+  t[2] = (short)f32_to_bf16(r1 - bf16_to_f32(m));
+}
+
 __device__ inline float sigm(float z) { return 1.0f / (1.0f + expf(-z)); }
 __device__ inline float silu(float z) { return z * sigm(z); }
 __device__ inline float silu_grad(float z) {
@@ -38,9 +59,10 @@ __device__ inline float silu_grad(float z) {
 }
 
 // 64 x 64 output tile per workgroup, four wavefronts of 32 x 32 (2 x 2 MFMA tiles
-// of 16 x 16), K staged through LDS in steps of 16.  MFMA 16x16x4 lane layout:
-// operand A(i, k) from lane i + 16 k, B(k, j) from lane j + 16 k; result D(i, j)
-// in lane j + 16 (i / 4), register i % 4.
+// of 16 x 16), K staged through LDS (FP32) in steps of 16, one 16x16x16 product per
+// term pair and step.  Lane layout of v_mfma_f32_16x16x16_bf16: lane l supplies
+// A(l % 16, 4 (l / 16) + v) and B(4 (l / 16) + v, l % 16) as element v of its four;
+// result D(i, j) in lane j + 16 (i / 4), register i % 4.
 __device__ inline void epilogue(const GemmArgs& g, int i, int j, float v) {
   if (g.bias) v += g.bias[j];
   const long o = (long)i * g.ldc + j;
@@ -56,6 +78,7 @@ __device__ inline void epilogue(const GemmArgs& g, int i, int j, float v) {
 
 template <typename TB>
 __global__ void __launch_bounds__(GT) gemm_kernel(GemmArgs g) {
+  constexpr bool kBf16B = sizeof(TB) == 2;
   __shared__ float As[BK][BM + 4];
   __shared__ float Bs[BK][BN + 4];
   const TB* B = static_cast<const TB*>(g.B);
@@ -101,19 +124,41 @@ __global__ void __launch_bounds__(GT) gemm_kernel(GemmArgs g) {
       Bs[k][j] = (gj < g.N && gk < kend) ? load_b(B, (long)gk * g.sbk + (long)gj * g.sbj) : 0.f;
     }
     __syncthreads();
+    // bfloat16 terms of this lane's four A and four B entries per 16-column tile
+    constexpr int SB = kBf16B ? 1 : 3;
+    s4 at[2][3], bt[2][SB];
+    const int kq = 4 * (lane >> 4);
 #pragma unroll
-    for (int kk = 0; kk < BK; kk += 4) {
-      float av[2], bv[2];
+    for (int t = 0; t < 2; ++t)
 #pragma unroll
-      for (int t = 0; t < 2; ++t) {
-        av[t] = As[kk + (lane >> 4)][wm + t * 16 + (lane & 15)];
-        bv[t] = Bs[kk + (lane >> 4)][wn + t * 16 + (lane & 15)];
+      for (int v = 0; v < 4; ++v) {
+        short ta[3];
+        split3(As[kq + v][wm + t * 16 + (lane & 15)], ta);
+#pragma unroll
+        for (int q = 0; q < 3; ++q) at[t][q][v] = ta[q];
+        const float b = Bs[kq + v][wn + t * 16 + (lane & 15)];
+        if constexpr (kBf16B) {
+          bt[t][0][v] = (short)(__float_as_uint(b) >> 16);  // a widened bfloat16: exact
+        } else {
+          short tb[3];
+          split3(b, tb);
+#pragma unroll
+          for (int q = 0; q < 3; ++q) bt[t][q][v] = tb[q];
+        }
       }
+    // term pairs of order <= 2^-16, smallest first
 #pragma unroll
-      for (int a = 0; a < 2; ++a)
+    for (int ord = 2; ord >= 0; --ord)
 #pragma unroll
-        for (int b = 0; b < 2; ++b) acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a], bv[b], acc[a][b], 0, 0, 0);
-    }
+      for (int qa = 0; qa <= ord; ++qa) {
+        const int qb = ord - qa;
+        if (qb >= SB) continue;
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+          for (int b = 0; b < 2; ++b)
+            acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(at[a][qa], bt[b][qb], acc[a][b], 0, 0, 0);
+      }
     __syncthreads();
   }
 #pragma unroll
