@@ -163,13 +163,45 @@ __global__ void __launch_bounds__(GemmShape<S>::NT) sign_gemm_kernel(S* work, in
     for (int a = 0; a < SUB; ++a)
 #pragma unroll
       for (int b = 0; b < SUB; ++b) acc[q][a][b] = Acc{R(0), R(0), R(0), R(0)};
+  // Real blocks: each chunk's operand slices are loaded into registers while the previous chunk's
+  // products run.  Complex blocks stage after the products as before: their copies would take the
+  // registers that let two workgroups share a CU.
+  constexpr int PER = CPLX ? 1 : KC * TB / NT;
+  static_assert(CPLX || PER * NT == KC * TB, "whole staging rounds");
+  S pre_p[PER], pre_q[PER];
+  if constexpr (!CPLX) {
+#pragma unroll
+    for (int x = 0; x < PER; ++x) {
+      const int e = tid + x * NT, k = e / TB, c = e % TB;
+      pre_p[x] = P[(size_t)k * n + ti * TB + c];
+      pre_q[x] = Q[(size_t)k * n + tj * TB + c];
+    }
+  }
   for (int k0 = 0; k0 < n; k0 += KC) {
-    for (int e = tid; e < KC * TB; e += NT) {
-      const int k = e / TB, c = e % TB;
-      Ps[e] = P[(size_t)(k0 + k) * n + ti * TB + c];
-      Qs[e] = Q[(size_t)(k0 + k) * n + tj * TB + c];
+    if constexpr (!CPLX) {
+#pragma unroll
+      for (int x = 0; x < PER; ++x) {
+        Ps[tid + x * NT] = pre_p[x];
+        Qs[tid + x * NT] = pre_q[x];
+      }
+    } else {
+      for (int e = tid; e < KC * TB; e += NT) {
+        const int k = e / TB, c = e % TB;
+        Ps[e] = P[(size_t)(k0 + k) * n + ti * TB + c];
+        Qs[e] = Q[(size_t)(k0 + k) * n + tj * TB + c];
+      }
     }
     __syncthreads();
+    if constexpr (!CPLX) {
+      if (k0 + KC < n) {
+#pragma unroll
+        for (int x = 0; x < PER; ++x) {
+          const int e = tid + x * NT, k = e / TB, c = e % TB;
+          pre_p[x] = P[(size_t)(k0 + KC + k) * n + ti * TB + c];
+          pre_q[x] = Q[(size_t)(k0 + KC + k) * n + tj * TB + c];
+        }
+      }
+    }
 #pragma unroll
     for (int u = 0; u < KC / 4; ++u) {
       S av[SUB], bv[SUB];
