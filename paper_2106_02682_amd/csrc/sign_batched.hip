@@ -117,7 +117,8 @@ __global__ void __launch_bounds__(kSignThreads) sign_scale_kernel(Policy pol, in
 // of block blockIdx.y; P, Q, E, out are offsets (in scalars) inside the block's 4 n^2 work area.  The
 // reduction runs in chunks of KC: the KC x 64 slices P(k0.., i-range) and Q(k0.., j-range) are staged in
 // LDS with coalesced row reads (P(i, k) = conj(P(k, i)) read as rows of P).  Sixteen wavefronts, one
-// 16 x 16 matrix-core sub-tile each; a complex product takes four real ones.  (Measured on the batched
+// 16 x 16 matrix-core sub-tile each; a complex product takes four real ones; the next chunk's slices are
+// loaded into registers while the current chunk's products run.  (Measured on the batched
 // sweep, where the real pair blocks and the complex momentum blocks run concurrently on two streams:
 // 2 x 2 sub-tiles per wavefront on four wavefronts make the real products alone 30 % faster but the
 // step 10 % slower; three-product (Gauss) complex products are no faster; giving all tiles of a block to
@@ -163,43 +164,42 @@ __global__ void __launch_bounds__(GemmShape<S>::NT) sign_gemm_kernel(S* work, in
     for (int a = 0; a < SUB; ++a)
 #pragma unroll
       for (int b = 0; b < SUB; ++b) acc[q][a][b] = Acc{R(0), R(0), R(0), R(0)};
-  // Real blocks: each chunk's operand slices are loaded into registers while the previous chunk's
-  // products run.  Complex blocks stage after the products as before: their copies would take the
-  // registers that let two workgroups share a CU.
-  constexpr int PER = CPLX ? 1 : KC * TB / NT;
-  static_assert(CPLX || PER * NT == KC * TB, "whole staging rounds");
-  S pre_p[PER], pre_q[PER];
-  if constexpr (!CPLX) {
+  // prefetch of the next chunk into registers (as real words: a complex entry is two); complex blocks
+  // prefetch the Q slice only
+  constexpr int NC = CPLX ? 2 : 1;
+  constexpr int ROWW = TB * NC, PERW = KC * ROWW / NT, PER = KC * TB / NT;
+  const R* Pw = reinterpret_cast<const R*>(P);
+  const R* Qw = reinterpret_cast<const R*>(Q);
+  R* Psw = reinterpret_cast<R*>(Ps);
+  R* Qsw = reinterpret_cast<R*>(Qs);
+  const size_t ldw = (size_t)n * NC;
+  R pre_p[CPLX ? 1 : PERW], pre_q[PERW];
 #pragma unroll
-    for (int x = 0; x < PER; ++x) {
-      const int e = tid + x * NT, k = e / TB, c = e % TB;
-      pre_p[x] = P[(size_t)k * n + ti * TB + c];
-      pre_q[x] = Q[(size_t)k * n + tj * TB + c];
-    }
+  for (int x = 0; x < PERW; ++x) {
+    const int e = tid + x * NT, k = e / ROWW, c = e % ROWW;
+    if constexpr (!CPLX) pre_p[x] = Pw[(size_t)k * ldw + ti * ROWW + c];
+    pre_q[x] = Qw[(size_t)k * ldw + tj * ROWW + c];
   }
   for (int k0 = 0; k0 < n; k0 += KC) {
-    if constexpr (!CPLX) {
+    if constexpr (CPLX) {
 #pragma unroll
       for (int x = 0; x < PER; ++x) {
-        Ps[tid + x * NT] = pre_p[x];
-        Qs[tid + x * NT] = pre_q[x];
-      }
-    } else {
-      for (int e = tid; e < KC * TB; e += NT) {
-        const int k = e / TB, c = e % TB;
+        const int e = tid + x * NT, k = e / TB, c = e % TB;
         Ps[e] = P[(size_t)(k0 + k) * n + ti * TB + c];
-        Qs[e] = Q[(size_t)(k0 + k) * n + tj * TB + c];
       }
     }
-    __syncthreads();
-    if constexpr (!CPLX) {
-      if (k0 + KC < n) {
 #pragma unroll
-        for (int x = 0; x < PER; ++x) {
-          const int e = tid + x * NT, k = e / TB, c = e % TB;
-          pre_p[x] = P[(size_t)(k0 + KC + k) * n + ti * TB + c];
-          pre_q[x] = Q[(size_t)(k0 + KC + k) * n + tj * TB + c];
-        }
+    for (int x = 0; x < PERW; ++x) {
+      if constexpr (!CPLX) Psw[tid + x * NT] = pre_p[x];
+      Qsw[tid + x * NT] = pre_q[x];
+    }
+    __syncthreads();
+    if (k0 + KC < n) {
+#pragma unroll
+      for (int x = 0; x < PERW; ++x) {
+        const int e = tid + x * NT, k = e / ROWW, c = e % ROWW;
+        if constexpr (!CPLX) pre_p[x] = Pw[(size_t)(k0 + KC + k) * ldw + ti * ROWW + c];
+        pre_q[x] = Qw[(size_t)(k0 + KC + k) * ldw + tj * ROWW + c];
       }
     }
 #pragma unroll
