@@ -23,6 +23,8 @@
 // sqrt(alpha beta), tol = max(n, 16) * machine epsilon of the compute type);
 // columns of negligible norm (rounding noise left by an exactly singular B) are
 // not rotated, see below.
+#include <type_traits>
+
 #include "jacobi_common.h"
 #include "jacobi_rr.h"
 #include "mfma_tile.h"
@@ -52,10 +54,13 @@ struct JacobiLds {
 };
 
 // One matrix (index mat of the policy) per workgroup, in the LDS area smem (JacobiLds bytes).
-template <typename S, int NMAX, int MODE, bool WARM, int NT, typename Policy, bool REG = false>
+template <typename S, int NMAX, int MODE, bool WARM, int NT, typename Policy, bool REG = false, bool VG = false>
 __device__ __attribute__((always_inline)) void jacobi_body(Policy pol, int n, int max_sweeps, void* vstore_raw,
                                                            int cold, const int mat, unsigned char* smem) {
   static_assert(!REG || (NMAX == 64 && (NT == 256 || NT == 512)), "register-resident sweeps: n = 64, 4 or 8 waves");
+  // VG: a warm projection solve whose kept V is read from its slot by the warm-start product instead of
+  // being staged in LDS (cold must not be 2), so the solve's LDS holds W alone
+  static_assert(!VG || (WARM && MODE == kProject && !REG), "V from its slot: warm projection solves only");
   using R = typename scalar_traits<S>::real;
   using D = typename wide<S>::type;  // FP64 storage type of V
   constexpr int LD = NMAX + 1;  // padded column stride (wider padding measured no faster)
@@ -70,7 +75,7 @@ __device__ __attribute__((always_inline)) void jacobi_body(Policy pol, int n, in
   // identity instead, which makes its next solve cold.  Half of every round's LDS traffic and
   // arithmetic (the V columns) goes away.
   constexpr bool VFW = WARM && MODE == kProject && !REG;
-  using L = JacobiLds<S, NMAX, WARM, NT>;
+  using L = JacobiLds<S, NMAX, WARM && !VG, NT>;
   S* const W = reinterpret_cast<S*>(smem);
   S* const V = reinterpret_cast<S*>(smem + L::oV);
   R* const red = reinterpret_cast<R*>(smem + L::oRed);
@@ -96,7 +101,7 @@ __device__ __attribute__((always_inline)) void jacobi_body(Policy pol, int n, in
   // 0. cold == 2: the kept V comes from a lower-precision solve; restore its
   // orthonormality first with one Newton-Schulz step V <- V (3I - V^H V)/2
   // (defect E -> O(E^2)), using W as the buffer for G = V^H V.
-  if constexpr (WARM) {
+  if constexpr (WARM && !VG) {
     if (cold == 2) {
       const D* vin = pol.template vslot<D>(vstore_raw, mat, (size_t)nn);
       for (int idx = tid; idx < nn; idx += NT) {
@@ -186,7 +191,55 @@ __device__ __attribute__((always_inline)) void jacobi_body(Policy pol, int n, in
   // solve of this matrix slot.  B V_prev is nearly column-orthogonal when the
   // matrix moved little, so few sweeps remain.  V accumulates the rotations (eigenvalue and
   // eigenvector solves; projection solves rebuild V from W at the end instead).
-  if constexpr (WARM) {
+  if constexpr (VG) {
+    // W <- B V_prev with V_prev read from its slot (column-major); a cold start keeps W = B (= B I)
+    const D* vin = pol.template vslot<D>(vstore_raw, mat, (size_t)nn);
+    if (cold != 1) {
+      if (use_mfma) {
+        if constexpr (TPW > 0) {
+          const int nt = n / 16, T = nt * nt;
+          TileAcc<S> acc[TPW];
+#pragma unroll
+          for (int q = 0; q < TPW; ++q) {
+            const int t = wv + q * NWAVE;
+            if (t < T)
+              acc[q] = tile_gemm<S>([&](int i, int k) { return W[k * LD + i]; },
+                                    [&](int k, int j) { return narrow<S>(vin[(size_t)j * n + k]); }, n,
+                                    (t / nt) * 16, (t % nt) * 16, ln);
+          }
+          __syncthreads();
+#pragma unroll
+          for (int q = 0; q < TPW; ++q) {
+            const int t = wv + q * NWAVE;
+            if (t < T)
+#pragma unroll
+              for (int r = 0; r < 4; ++r)
+                W[((t % nt) * 16 + (ln & 15)) * LD + (t / nt) * 16 + mfma_row<R>(ln, r)] = tile_value(acc[q], r);
+          }
+        }
+      } else {
+        S outv[NOUT];
+        #pragma unroll
+        for (int c = 0; c < NOUT; ++c) {  // compile-time c keeps outv in registers
+          const int idx = tid + c * NT;
+          if (idx >= nn) break;
+          const int j = idx / n, i = idx - (idx / n) * n;
+          S acc = s_zero<S>();
+          for (int k = 0; k < n; ++k) acc = acc + W[k * LD + i] * narrow<S>(vin[(size_t)j * n + k]);
+          outv[c] = acc;
+        }
+        __syncthreads();
+        #pragma unroll
+        for (int c = 0; c < NOUT; ++c) {  // compile-time c keeps outv in registers
+          const int idx = tid + c * NT;
+          if (idx >= nn) break;
+          const int j = idx / n, i = idx - (idx / n) * n;
+          W[j * LD + i] = outv[c];
+        }
+      }
+    }
+    __syncthreads();
+  } else if constexpr (WARM) {
     const D* vin = pol.template vslot<D>(vstore_raw, mat, (size_t)nn);  // column-major: V(i, j) at [j*n + i]
     if (cold == 1) {
       for (int idx = tid; idx < nn; idx += NT) {
@@ -481,11 +534,11 @@ __device__ __attribute__((always_inline)) void jacobi_body(Policy pol, int n, in
   }
 }
 
-template <typename S, int NMAX, int MODE, bool WARM, int NT, typename Policy, bool REG = false>
+template <typename S, int NMAX, int MODE, bool WARM, int NT, typename Policy, bool REG = false, bool VG = false>
 __global__ void __launch_bounds__(NT) jacobi_kernel(Policy pol, int n, int max_sweeps, void* vstore_raw, int cold) {
-  __shared__ __attribute__((aligned(16))) unsigned char smem[JacobiLds<S, NMAX, WARM, NT>::bytes];
+  __shared__ __attribute__((aligned(16))) unsigned char smem[JacobiLds<S, NMAX, WARM && !VG, NT>::bytes];
   if (!policy_active(pol, blockIdx.x)) return;  // a masked batch instance: the whole workgroup
-  jacobi_body<S, NMAX, MODE, WARM, NT, Policy, REG>(pol, n, max_sweeps, vstore_raw, cold, blockIdx.x, smem);
+  jacobi_body<S, NMAX, MODE, WARM, NT, Policy, REG, VG>(pol, n, max_sweeps, vstore_raw, cold, blockIdx.x, smem);
 }
 
 // The pair and momentum projections of one iteration in one launch: workgroups below P take the
@@ -509,8 +562,23 @@ __global__ void __launch_bounds__(NT) fused_projection_kernel(PairPolicy pp, int
 // tpb: threads per workgroup (256, 512 or 1024; others fall back to 256).  More
 // threads give each column pair more lanes (fewer rows per lane) and put up to
 // four wavefronts on each SIMD to hide the latency of a round.
+// Batched FP64 projections of 64-blocks read the kept V from its slot: without V in LDS two workgroups of
+// the complex solver fit on a CU, which the batches' thousands of blocks use.
+template <typename S, int MODE, int NM, bool REG, typename Policy>
+constexpr bool v_from_slot() {
+  return MODE == kProject && NM == 64 && !REG && std::is_same<typename scalar_traits<S>::real, double>::value &&
+         (std::is_same<Policy, BatchedPairPolicy>::value || std::is_same<Policy, BatchedMomentumPolicy>::value);
+}
+
 template <typename S, int MODE, int NM, int NT, typename Policy, bool REG = false>
 hipError_t launch_one(const Policy& pol, int n, int count, int max_sweeps, hipStream_t st, void* vstore, int cold) {
+  if constexpr (v_from_slot<S, MODE, NM, REG, Policy>()) {
+    if (vstore && cold != 2) {
+      hipLaunchKernelGGL((jacobi_kernel<S, NM, MODE, true, NT, Policy, REG, true>), dim3(count), dim3(NT), 0, st, pol,
+                         n, max_sweeps, vstore, cold);
+      return hipGetLastError();
+    }
+  }
   if (vstore)
     hipLaunchKernelGGL((jacobi_kernel<S, NM, MODE, true, NT, Policy, REG>), dim3(count), dim3(NT), 0, st, pol, n,
                        max_sweeps, vstore, cold);
