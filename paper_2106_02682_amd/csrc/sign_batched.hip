@@ -168,6 +168,7 @@ __global__ void __launch_bounds__(GemmShape<S>::NT) sign_gemm_kernel(S* work, in
   // prefetch the Q slice only
   constexpr int NC = CPLX ? 2 : 1;
   constexpr int ROWW = TB * NC, PERW = KC * ROWW / NT, PER = KC * TB / NT;
+  static_assert(PERW * NT == KC * ROWW && PER * NT == KC * TB, "the staging covers whole slices");
   const R* Pw = reinterpret_cast<const R*>(P);
   const R* Qw = reinterpret_cast<const R*>(Q);
   R* Psw = reinterpret_cast<R*>(Ps);
